@@ -1,0 +1,67 @@
+"""Error and cost measures of the paper.
+
+TEST INFRASTRUCTURE ONLY (part of the oracle).
+
+  rel_err_1(P, ref_hi, ref_lo)  the relative error in the 1-norm used
+      throughout the experiments (section 3.3):
+      ||P - p||_1 / ||p||_1, with the reference p = hi + lo given in dd and the
+      difference formed as (P - hi) - lo.
+  rel_err_cols(...)  the same measure restricted to a sample of columns.
+  cost_saving(D, s, r, d)  the cost ratio of eq. (Cr) read as a saving:
+      1 - ((s - 1) D + sum_i d_i) / ((s + r - 1) D), where D is the number of
+      decimal digits of the working precision and d_i those of u_i.  This is
+      the reading under which all four C_r entries of Table 1 reproduce.
+  alpha_m(X, m)  max(||X^d||^(1/d), ||X^(d+1)||^(1/(d+1))) with
+      d = floor((1 + sqrt(4m + 5)) / 2)  (section 3.2).
+  extra_scaling(normX, s)  l_0 = ceil(log2(e ||X||_1 / s)), the number of
+      extra squarings that would force ||X||_1 <= s/e (section 3.2).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def norm1(A) -> float:
+    return float(np.max(np.sum(np.abs(np.asarray(A, dtype=np.float64)), axis=0))) if np.size(A) else 0.0
+
+
+def rel_err_1(P, ref_hi, ref_lo=None) -> float:
+    P = np.asarray(P, dtype=np.float64)
+    D = P - np.asarray(ref_hi)
+    if ref_lo is not None:
+        D = D - np.asarray(ref_lo)
+    den = norm1(ref_hi)
+    num = norm1(D)
+    if den == 0.0:
+        return 0.0 if num == 0.0 else math.inf
+    return num / den
+
+
+def rel_err_dd(qh, ql, ph, pl) -> float:
+    """Relative 1-norm distance between two dd matrices (q - p) / p."""
+    D = (np.asarray(qh) - np.asarray(ph)) + (np.asarray(ql) - np.asarray(pl))
+    den = norm1(ph)
+    return norm1(D) / den if den else (0.0 if norm1(D) == 0 else math.inf)
+
+
+def rel_err_cols(Pcols, ref_hi, ref_lo=None) -> float:
+    """Column-sample version: max_j ||(P - p) e_j||_1 / max_j ||p e_j||_1."""
+    return rel_err_1(Pcols, ref_hi, ref_lo)
+
+
+def cost_saving(D: float, s: int, r: int, d) -> float:
+    return 1.0 - ((s - 1) * D + float(sum(d))) / ((s + r - 1) * D)
+
+
+def alpha_m(X, m: int) -> float:
+    X = np.asarray(X, dtype=np.float64)
+    d = int(math.floor((1 + math.sqrt(4 * m + 5)) / 2))
+    Pd = np.linalg.matrix_power(X, d)
+    Pd1 = Pd @ X
+    return max(norm1(Pd) ** (1.0 / d), norm1(Pd1) ** (1.0 / (d + 1)))
+
+
+def extra_scaling(normX: float, s: int) -> int:
+    return int(math.ceil(math.log2(math.e * normX / s)))

@@ -1,0 +1,383 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Each check is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign or index, a transposed operand, a wrong block boundary in the PS
+split, a missing squaring) fails at least one of them."""
+import math
+import os
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coeffs, metrics
+from oracle import plan as oplan
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53
+
+
+# ---------------------------------------------------------------- helpers
+def fmat(A):
+    return [[F(float(x)) for x in row] for row in np.asarray(A)]
+
+
+def fmul(A, B):
+    n, k, p = len(A), len(B), len(B[0])
+    return [[sum(A[i][l] * B[l][j] for l in range(k)) for j in range(p)] for i in range(n)]
+
+
+def fpoly(X, c):
+    """sum_k c_k X^k with exact rationals (brute force)."""
+    n = len(X)
+    T = [[F(int(i == j)) for j in range(n)] for i in range(n)]
+    S = [[F(c[0]) * T[i][j] for j in range(n)] for i in range(n)]
+    for k in range(1, len(c)):
+        T = fmul(T, X)
+        S = [[S[i][j] + F(c[k]) * T[i][j] for j in range(n)] for i in range(n)]
+    return S
+
+
+def as_float(Fm):
+    return np.array([[float(x) for x in row] for row in Fm])
+
+
+def dd_close(hi, lo, exact, rtol):
+    n = len(exact)
+    scale = max(max(abs(x) for x in row) for row in exact) or F(1)
+    for i in range(n):
+        for j in range(len(exact[0])):
+            err = abs(F(float(hi[i, j])) + F(float(lo[i, j])) - exact[i][j])
+            assert err <= F(rtol) * scale, (i, j, float(err), float(scale))
+
+
+def rand_normed(rng, n, t=1.0):
+    G = rng.standard_normal((n, n))
+    return G * (t / metrics.norm1(G))
+
+
+# ------------------------------------------------- P1: exactness on integers
+@pytest.mark.parametrize("seed", range(6))
+def test_integer_inputs_all_routes_bitwise(seed):
+    """Integer X in {-2..2}, integer c_k, n <= 4, m <= 8: every intermediate is an
+    integer below 2^53, so Algorithm 1 (any s), Horner, explicit powers and the
+    dd routes must all equal the exact integer polynomial bitwise."""
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(1, 5))
+    m = int(rng.integers(0, 9))
+    X = rng.integers(-2, 3, (n, n)).astype(np.float64)
+    c = rng.integers(-5, 6, m + 1).astype(np.float64)
+    exact = as_float(fpoly(fmat(X), c))
+    assert np.all(np.abs(exact) < 2 ** 53)
+    for s in range(1, max(m, 1) + 1):
+        assert np.array_equal(oracle.ps_f64(X, c, s), exact), ("ps_f64", s)
+        h, l = oracle.ps_dd(X, c, s)
+        assert np.array_equal(h, exact) and not np.any(l), ("ps_dd", s)
+    assert np.array_equal(oracle.horner_f64(X, c), exact)
+    assert np.array_equal(oracle.naive_f64(X, c), exact)
+    h, l = oracle.poly_dd(X, c)
+    assert np.array_equal(h, exact) and not np.any(l)
+
+
+# ---------------------------------------------- P2: diagonal closed form
+def test_diagonal_closed_form():
+    rng = np.random.default_rng(7)
+    d = rng.uniform(-3, 3, 5)
+    c = coeffs.taylor_exp(20)
+    h, l = oracle.poly_dd(np.diag(d), c)
+    exact = [[F(0)] * 5 for _ in range(5)]
+    for i in range(5):
+        exact[i][i] = sum(F(ck) * F(float(d[i])) ** k for k, ck in enumerate(c))
+    dd_close(h, l, exact, 1e-30)
+    # scaling and squaring on a diagonal: diag(p(d_i / 2^sigma)^(2^sigma))
+    sigma = 3
+    h, l = oracle.expm_dd(np.diag(d), c, sigma)
+    for i in range(5):
+        x = F(float(d[i])) / 2 ** sigma
+        exact[i][i] = sum(F(ck) * x ** k for k, ck in enumerate(c)) ** (2 ** sigma)
+    dd_close(h, l, exact, 1e-29)
+
+
+# ---------------------------------------------- P3: triangular invariant
+def test_upper_triangular_stays_triangular():
+    rng = np.random.default_rng(8)
+    n = 24
+    T = np.triu(rng.standard_normal((n, n))) / 4
+    c = coeffs.taylor_exp(16)
+    for P in (oracle.ps_f64(T, c, 4), oracle.poly_dd(T, c)[0], oracle.ps_dd(T, c, 4)[0],
+              oracle.expm_dd(T, c, 2)[0]):
+        assert not np.any(np.tril(P, -1))
+    h, l = oracle.poly_dd(T, c)
+    for i in range(n):
+        ex = sum(F(ck) * F(float(T[i, i])) ** k for k, ck in enumerate(c))
+        assert abs(F(float(h[i, i])) + F(float(l[i, i])) - ex) <= F(1e-30) * abs(ex)
+
+
+# ---------------------------------------------- P4: nilpotent / Jordan
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_jordan_block_taylor_is_exact_exponential(n):
+    """For J = J_n(0), J^n = 0, so the Taylor polynomial of degree m >= n-1 is
+    e^J with its coefficients: the Toeplitz matrix with c_j = fl(1/j!) on
+    superdiagonal j.  Every entry is a single product c_j * 1, so the result is
+    exact (lo part zero)."""
+    J = np.diag(np.ones(n - 1), 1) if n > 1 else np.zeros((1, 1))
+    c = coeffs.taylor_exp(max(n - 1, 0) + 3)
+    h, l = oracle.poly_dd(J, c)
+    exact = [[F(c[j - i]) if j >= i else F(0) for j in range(n)] for i in range(n)]
+    dd_close(h, l, exact, 0.0)
+    assert not np.any(l)
+    # and c_j is the double nearest to 1/j!
+    for j in range(n):
+        assert abs(F(c[j]) - F(1, math.factorial(j))) <= F(1, math.factorial(j)) * F(2.0 ** -53)
+    # PS with s = n: Y = J^n = 0 so p = B_0 (section 2, the nilpotent remark)
+    if n > 1:
+        h2, l2 = oracle.ps_dd(J, c, n)
+        dd_close(h2, l2, exact, 0.0)
+
+
+def test_strictly_upper_random_nilpotent():
+    rng = np.random.default_rng(9)
+    n = 5
+    N = np.triu(rng.integers(-3, 4, (n, n)), 1).astype(float)
+    c = coeffs.taylor_exp(8)
+    h, l = oracle.poly_dd(N, c)
+    exact = fpoly(fmat(N), c[:n])          # N^n = 0: terms beyond n-1 vanish
+    dd_close(h, l, exact, 1e-30)
+
+
+# ---------------------------------------------- P5: rotation generator
+@pytest.mark.parametrize("theta", [0.3, 1.0, 2.5])
+def test_rotation_generator_gives_truncated_cos_sin(theta):
+    m = 18
+    X = np.array([[0.0, -theta], [theta, 0.0]])
+    c = coeffs.taylor_exp(m)
+    h, l = oracle.poly_dd(X, c)
+    t = F(theta)
+    # truncated scalar cos / sin series with the same (double) coefficients
+    C = sum((-1) ** (k // 2) * F(c[k]) * t ** k for k in range(0, m + 1, 2))
+    S = sum((-1) ** ((k - 1) // 2) * F(c[k]) * t ** k for k in range(1, m + 1, 2))
+    dd_close(h, l, [[C, -S], [S, C]], 1e-31)
+    # with a long series the matrix tends to the rotation by theta
+    h, _ = oracle.poly_dd(X, coeffs.taylor_exp(40))
+    assert abs(h[0, 0] - math.cos(theta)) < 4e-16 and abs(h[1, 0] - math.sin(theta)) < 4e-16
+
+
+def test_cos_in_square_argument():
+    """X = theta [[0,1],[1,0]] has X^2 = theta^2 I, so c_m(X^2) = c_m(theta^2) I."""
+    theta = 1.3
+    X = theta * np.array([[0.0, 1.0], [1.0, 0.0]])
+    Z = oracle.gemm_f64(X, X)
+    c = coeffs.taylor_cos(12)
+    h, l = oracle.poly_dd(Z, c)
+    z = F(float(Z[0, 0]))
+    val = sum(F(ck) * z ** k for k, ck in enumerate(c))
+    dd_close(h, l, [[val, F(0)], [F(0), val]], 1e-31)
+    assert abs(float(val) - math.cos(theta)) < 1e-15
+
+
+# ---------------------------------------------- P6: group / commutation
+def test_exp_times_exp_minus_is_identity():
+    rng = np.random.default_rng(10)
+    n = 16
+    A = rand_normed(rng, n, 4.0)
+    # truncation is far below u at ||X|| = 1; what remains is the rounding of the
+    # coefficients c_k = fl(1/k!) themselves (relative u each), so the product
+    # is I to a few u, while a dropped or wrong term would leave O(1/k!).
+    c = coeffs.taylor_exp(40)
+    Eh, El = oracle.expm_dd(A, c, 2)
+    Fh, Fl = oracle.expm_dd(-A, c, 2)
+    Ph, Pl = oracle.gemm_dd(Eh, El, Fh, Fl)
+    R = (Ph - np.eye(n)) + Pl
+    assert metrics.norm1(R) < 16 * U
+
+
+def test_polynomial_commutes_with_argument():
+    rng = np.random.default_rng(11)
+    n = 20
+    A = rand_normed(rng, n, 2.0)
+    h, l = oracle.poly_dd(A, coeffs.taylor_exp(25))
+    Z = np.zeros((n, n))
+    AP = oracle.gemm_dd(A, Z, h, l)
+    PA = oracle.gemm_dd(h, l, A, Z)
+    D = (AP[0] - PA[0]) + (AP[1] - PA[1])
+    assert metrics.norm1(D) < 1e-29 * metrics.norm1(A) * metrics.norm1(h)
+
+
+# ---------------------------------------------- P14: route consistency
+@pytest.mark.parametrize("n,m,s", [(33, 30, 6), (64, 16, 4), (70, 13, 4), (40, 18, 5), (17, 7, 3)])
+def test_ps_dd_matches_plain_definition(n, m, s):
+    rng = np.random.default_rng(12 + n)
+    X = rand_normed(rng, n, 1.0)
+    c = coeffs.taylor_exp(m)
+    ph, pl = oracle.poly_dd(X, c)
+    qh, ql = oracle.ps_dd(X, c, s)
+    assert metrics.rel_err_dd(qh, ql, ph, pl) < 1e-28
+
+
+def test_column_apply_matches_full_matrix():
+    rng = np.random.default_rng(13)
+    n, sigma = 48, 3
+    A = rand_normed(rng, n, 8.0)
+    c = coeffs.taylor_exp(18)
+    Eh, El = oracle.expm_dd(A, c, sigma)
+    cols = [0, 7, 47]
+    V = np.eye(n)[:, cols]
+    Wh, Wl = oracle.expm_apply_dd(A, c, sigma, V)
+    assert metrics.rel_err_dd(Wh, Wl, Eh[:, cols], El[:, cols]) < 1e-27
+
+
+def test_fp64_ps_close_to_dd():
+    rng = np.random.default_rng(14)
+    n = 64
+    X = rand_normed(rng, n, 1.0)
+    c = coeffs.taylor_exp(16)
+    h, l = oracle.poly_dd(X, c)
+    e = metrics.rel_err_1(oracle.ps_f64(X, c, 4), h, l)
+    assert 0 < e < n * 4 * U
+
+
+# ---------------------------------------------- P7: Pade coefficients
+def test_pade13_blocks_match_paper():
+    p, q = coeffs.pade_exp_exact(13, 13)
+    rows = [ln.split() for ln in open(os.path.join(GOLD, "pade13_blocks.txt")) if ln.strip() and ln[0] != "#"]
+    assert len(rows) == 8
+    for idx, num, den in rows:
+        assert p[int(idx)] == F(int(num), int(den))
+    # q_mm(x) = p_mm(-x)
+    assert all(q[j] == (-1) ** j * p[j] for j in range(14))
+    # general formula sanity: [1/1] is (1 + x/2)/(1 - x/2)
+    p1, q1 = coeffs.pade_exp_exact(1, 1)
+    assert p1 == [1, F(1, 2)] and q1 == [1, F(-1, 2)]
+
+
+def test_taylor_cos_coefficients():
+    c = coeffs.taylor_cos_exact(4)
+    assert c == [1, F(-1, 2), F(1, 24), F(-1, 720), F(1, 40320)]
+    assert coeffs.taylor_exp(3) == [1.0, 1.0, 0.5, 1.0 / 6.0]
+
+
+# ---------------------------------------------- P8: alpha_m example
+def test_nonnormal_example_numbers():
+    g = {}
+    for ln in open(os.path.join(GOLD, "nonnormal_2x2.txt")):
+        if ln.strip() and ln[0] != "#":
+            k, v, tol = ln.split()
+            g[k] = (float(v), float(tol))
+    A = np.array([[-0.1, 1e6], [0.0, -0.1]])
+    X = A / 2
+    nx = metrics.norm1(X)
+    assert abs(nx - g["norm1_X"][0]) <= g["norm1_X"][1]
+    assert abs(metrics.alpha_m(X, 42) - g["alpha_m"][0]) <= g["alpha_m"][1]
+    s = math.ceil(math.sqrt(42))
+    assert s == 7
+    assert metrics.extra_scaling(nx, s) == int(g["l0"][0])
+
+
+# ---------------------------------------------- P9: cost model
+def test_table1_cost_ratio_and_block_counts():
+    for ln in open(os.path.join(GOLD, "table1_cauchy100.txt")):
+        if not ln.strip() or ln[0] == "#":
+            continue
+        head, tail = ln.split("|")
+        D, m, s, r, cr = head.split()
+        d = [int(x) for x in tail.split()]
+        D, m, s, r = int(D), int(m), int(s), int(r)
+        assert s == math.ceil(math.sqrt(m)) and r == m // s and len(d) == r
+        assert abs(100 * metrics.cost_saving(D, s, r, d) - float(cr)) < 0.05
+        # precisions decrease along the Horner chain (u_r >= ... >= u_1)
+        assert all(d[i] >= d[i + 1] for i in range(r - 1))
+
+
+def test_table2_saving():
+    g = dict((ln.split()[0], float(ln.split()[1])) for ln in open(os.path.join(GOLD, "table2_runtime.txt"))
+             if ln.strip() and ln[0] != "#")
+    assert abs(100 * (1 - g["T_tot"] / g["T_fix"]) - g["saving_percent"]) < 0.05
+
+
+# ---------------------------------------------- oracle planner
+def test_planner_hand_cases():
+    # strong decay: B norms 1, 1e-3, 1e-7; ||Y|| = 1e-2
+    u, nu, t = oplan.plan([1.0, 1e-3, 1e-7], 1e-2, working_tier=0)
+    # u_1 = 2^-53 / max(1e-5, 1e-11) = 1.1e-11 -> still FP64 (needs >= 2^-24)
+    # u_2 = 2^-53 / 1e-11 = 1.1e-5 -> FP32
+    assert nu == 1 and t == [0, 0, 1]
+    # Y = 0 (nilpotent of index <= s): every product is exactly zero
+    u, nu, t = oplan.plan([2.0, 1.0, 1.0], 0.0)
+    assert nu == 1 and t == [0, 3, 3]
+    # B_0 = 0: keep the working precision everywhere
+    u, nu, t = oplan.plan([0.0, 1.0, 1.0], 0.5)
+    assert nu == 3 and t == [0, 0, 0]
+    # no decay: fixed-precision PS is recovered
+    u, nu, t = oplan.plan([1.0, 1.0, 1.0], 2.0)
+    assert nu == 3 and t == [0, 0, 0]
+    # FP32 working precision with bf16/fp8 tiers; inclusive comparison at the threshold
+    u, nu, t = oplan.plan([1.0, 2.0 ** -20 / 2.0 ** -4, 1e-30], 2.0 ** -0, working_tier=1)
+    assert t[1] == 2 and t[2] == 3
+    # monotone: a large late block pulls earlier u_i down
+    u, nu, t = oplan.plan([1.0, 1e-12, 1e-3], 1e-1)
+    assert u[1] <= u[2]
+
+
+def test_apriori_norms_bound_block_norms():
+    rng = np.random.default_rng(15)
+    n, m, s = 30, 18, 5
+    X = rand_normed(rng, n, 0.7)
+    c = coeffs.taylor_exp(m)
+    r, ranges = oplan.block_bounds(s, m)
+    assert r == 3 and ranges[-1] == [15, 16, 17, 18]
+    nb, ny = oplan.apriori_norms(c, s, metrics.norm1(X))
+    powers = [np.eye(n)]
+    for _ in range(s):
+        powers.append(powers[-1] @ X)
+    for i in range(r + 1):
+        B = sum(c[k] * powers[k - s * i] for k in ranges[i])
+        assert metrics.norm1(B) <= nb[i] * (1 + 1e-12)
+    assert metrics.norm1(powers[s]) <= ny * (1 + 1e-12)
+
+
+# ---------------------------------------------- R4: gradient oracle
+def _fadd(A, B, a=1, b=1):
+    return [[a * A[i][j] + b * B[i][j] for j in range(len(A[0]))] for i in range(len(A))]
+
+
+def _fr(A, c, sigma):
+    X = [[x / 2 ** sigma for x in row] for row in A]
+    R = fpoly(X, c)
+    for _ in range(sigma):
+        R = fmul(R, R)
+    return R
+
+
+@pytest.mark.parametrize("sigma", [0, 1, 2])
+def test_gradient_oracle_matches_derivative_definition(sigma):
+    """<grad, E> must equal d/dh <G, r(A + hE)> at h = 0.  The derivative is
+    taken from its definition by an exact rational central difference with
+    h = 1e-30 (remainder O(h^2)), independent of the block-triangular identity
+    the oracle uses."""
+    rng = np.random.default_rng(20 + sigma)
+    n = 3
+    A = rng.standard_normal((n, n)) / 2
+    G = rng.standard_normal((n, n))
+    E = rng.standard_normal((n, n))
+    c = coeffs.taylor_exp(5)
+    gh, gl = oracle.expm_grad_dd(A, G, c, sigma)
+    got = sum(F(float(gh[i, j])) * F(float(E[i, j])) + F(float(gl[i, j])) * F(float(E[i, j]))
+              for i in range(n) for j in range(n))
+    h = F(1, 10 ** 30)
+    Af, Ef, Gf = fmat(A), fmat(E), fmat(G)
+    Rp = _fr(_fadd(Af, Ef, 1, h), c, sigma)
+    Rm = _fr(_fadd(Af, Ef, 1, -h), c, sigma)
+    want = sum(Gf[i][j] * (Rp[i][j] - Rm[i][j]) for i in range(n) for j in range(n)) / (2 * h)
+    assert abs(got - want) <= F(1e-28) * (abs(want) + 1)
+
+
+def test_gradient_oracle_polynomial_closed_form():
+    """p(X) = X^2: the gradient of <G, X^2> is G X^T + X^T G."""
+    rng = np.random.default_rng(23)
+    n = 5
+    X = rng.standard_normal((n, n))
+    G = rng.standard_normal((n, n))
+    gh, gl = oracle.expm_grad_dd(X, G, [0.0, 0.0, 1.0], 0, cols=[1, 4])
+    want = (G @ X.T + X.T @ G)[:, [1, 4]]
+    assert np.max(np.abs(gh + gl - want)) < 1e-14 * np.max(np.abs(want))
