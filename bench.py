@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of the PS hot path on one MI355X: exp(A) by scaling and squaring
+around Taylor PS (m = 30, s = 6) on dense n = 1024 FP64 matrices with
+||A||_1 in {0.1, 1, 8, 64} (sigma = 0, 0, 3, 6), mixed-precision tiers vs
+plain FP64 PS on the same GPU.
+
+One step = one evaluation of each of the four matrices (4 evals), inputs
+resident in HBM.  `value` = evals/s of the mixed-precision path.
+
+Also reported:
+  plain       the same workload with every product in FP64 (Algorithm 1)
+  accuracy    relative 1-norm distance mixed vs plain (full matrices, GPU)
+  roofline    the dominant kernel (FP64 MFMA GEMM of the power table and the
+              squarings): algorithmic 2 n^3 flops per launch over its average
+              launch duration, from hipEvent pairs around the power-table and
+              squaring phases (library profile mode, same stream), for the
+              same K steps run again after the timed region
+  cpu_baseline  the CPU oracle's plain FP64 Algorithm 1 + squarings
+              (OpenMP, all host cores) on one evaluation of each matrix, plus
+              the GPU result's error against the dd oracle on sampled columns
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 1024
+M = 30
+S = 6
+PEAK_FP64_MFMA = 78.6   # TFLOP/s, MI355X dense FP64 matrix
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "plain", "both"], default="both",
+                    help="restrict the timed modes (profiling runs)")
+    return ap.parse_args()
+
+
+def gemm_count(sigma):
+    r = M // S
+    horner = r - 1 if M % S == 0 else r
+    return (S - 1) + horner + sigma
+
+
+def load_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_gemm_f64_n1024.json")
+    src = os.path.join(ROOT, "paper_2312_17396_amd", "csrc", "ps_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if rec.get("kernel_source_sha256") != h:
+            return None
+        return rec.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU path is not built); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2312_17396_amd as ps
+    from paper_2312_17396_amd import inputs
+
+    ps.lib()
+    dev = torch.device("cuda:0")
+    norms = list(inputs.DENSE_NORMS)
+    sigmas = [inputs.squarings_for(t) for t in norms]
+    mats = [torch.tensor(inputs.dense_1024(t), dtype=torch.float64, device=dev) for t in norms]
+    outs = [torch.empty_like(a) for a in mats]
+    wss = [ps.expm_workspace(a, M, S, sg) for a, sg in zip(mats, sigmas)]
+    flops_per_step = sum(gemm_count(sg) * 2.0 * N ** 3 for sg in sigmas)
+
+    def step(mode, profile=False):
+        reps = []
+        for a, o, w, sg in zip(mats, outs, wss, sigmas):
+            r = ps.ps_expm(a, M, s=S, sigma=sg, mode=mode, out=o, workspace=w, profile=profile)
+            if profile:
+                reps.append(r[1])
+        return reps
+
+    def timed(mode):
+        for _ in range(args.warmup):
+            step(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(mode)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    res = {}
+    modes = ["plain", "mixed"] if args.only == "both" else [args.only]
+    for mode in modes:
+        res[mode] = timed("fixed" if mode == "plain" else "mixed")
+
+    # tiers and accuracy (outside the timed region)
+    _, rep = ps.ps_expm(mats[1], M, s=S, sigma=sigmas[1], mode="mixed", report=True)
+    plans = []
+    errs = []
+    for a, sg in zip(mats, sigmas):
+        em, rp = ps.ps_expm(a, M, s=S, sigma=sg, mode="mixed", report=True)
+        ef = ps.ps_expm(a, M, s=S, sigma=sg, mode="fixed")
+        plans.append([ps.TIER_NAMES[t] for t in rp["tier"][1:]])
+        d = torch.linalg.matrix_norm(em - ef, ord=1).item() / torch.linalg.matrix_norm(ef, ord=1).item()
+        errs.append(d)
+
+    # roofline of the dominant kernel: FP64 GEMM (power table + squarings)
+    prof_mode = "mixed" if "mixed" in res else "fixed"
+    gemm_ms, gemm_n = 0.0, 0
+    for _ in range(args.steps):
+        for r, sg in zip(step(prof_mode, profile=True), sigmas):
+            gemm_ms += r["ms"]["power"] + r["ms"]["square"]
+            gemm_n += (S - 1) + sg
+    avg_ms = gemm_ms / max(gemm_n, 1)
+    achieved = 2.0 * N ** 3 / (avg_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_gemm<double> (FP64 MFMA 16x16x4, 64x64 tile)", "bound": "mfma",
+                "achieved": round(achieved, 2), "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_MFMA, 4), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "traffic": load_traffic()}
+
+    main_mode = "mixed" if "mixed" in res else "plain"
+    t_step = res[main_mode]
+    value = len(mats) / t_step
+    out = {
+        "metric": "p(A) evals/s at fixed rel. error vs FP64 oracle, mixed vs FP64 PS",
+        "value": round(value, 2),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "expm_taylor_dense_1024", "n": N, "m": M, "s": S, "norms_1": norms,
+                   "sigma": sigmas, "mode": main_mode, "evals_per_step": len(mats)},
+        "tflops": round(flops_per_step / t_step / 1e12, 3),
+        "tiers": plans,
+        "rel_diff_mixed_vs_plain": [float("%.3e" % e) for e in errs],
+        "roofline": roofline,
+    }
+    if "plain" in res and "mixed" in res:
+        out["plain"] = {"evals_per_s": round(len(mats) / res["plain"], 2),
+                        "ms_per_step": round(res["plain"] * 1e3, 4),
+                        "tflops": round(flops_per_step / res["plain"] / 1e12, 3)}
+        out["speedup_mixed_vs_plain"] = round(res["plain"] / res["mixed"], 4)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mats, outs_mixed=[ps.ps_expm(a, M, s=S, sigma=sg, mode="mixed")
+                                                             for a, sg in zip(mats, sigmas)],
+                                           norms=norms, sigmas=sigmas)
+    print(json.dumps(out))
+
+
+def cpu_baseline(mats, outs_mixed, norms, sigmas):
+    """The oracle's plain FP64 Algorithm 1 + squarings on the host cores (one
+    evaluation of each matrix), and the GPU result against the dd oracle on
+    sampled columns."""
+    import numpy as np
+
+    import oracle
+    from oracle import coeffs
+
+    threads = min(os.cpu_count() or 1, 16)
+    oracle.set_threads(threads)
+    c = coeffs.taylor_exp(M)
+    A_np = [a.cpu().numpy() for a in mats]
+    t0 = time.perf_counter()
+    for A, sg in zip(A_np, sigmas):
+        oracle.expm_ps_f64(A, c, S, sg)
+    dt = time.perf_counter() - t0
+    errs = []
+    for A, sg, e in zip(A_np, sigmas, outs_mixed):
+        cols = [0, N // 2 + 1]
+        V = np.eye(N)[:, cols]
+        wh, wl = oracle.expm_apply_dd(A, c, sg, V)
+        got = e.cpu().numpy()[:, cols]
+        d = (got - wh) - wl
+        errs.append(float(np.max(np.sum(np.abs(d), 0)) / np.max(np.sum(np.abs(wh), 0))))
+    return {"value": round(len(A_np) / dt, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": "one evaluation of each of the 4 dense n=1024 matrices by the oracle's FP64 "
+                      "Algorithm 1 + squarings (%.1f s)" % dt,
+            "gpu_mixed_rel_err_vs_dd_oracle_sampled_cols": [float("%.3e" % e) for e in errs]}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * ps.h -- C ABI of libps: Paterson--Stockmeyer (PS) evaluation of matrix
+ * polynomials with scalar coefficients on AMD MI355X (gfx950), with
+ * per-Horner-step precision tiers (FP64 / FP32 / BF16 / FP8 matrix cores).
+ *
+ * Method: X. Liu, "Mixed-Precision Paterson--Stockmeyer Method for Evaluating
+ * Polynomials of Matrices", arXiv 2312.17396.
+ *   p(X) = sum_{k=0}^{m} c_k X^k is written as sum_{i=0}^{r} B_i (X^s)^i,
+ *   r = floor(m/s), B_i = sum_j c_{si+j} X^j (eq. (ps)), and evaluated by
+ *   Horner's rule in Y = X^s (eq. (ps-Horner), Algorithm 1).  In mixed mode
+ *   the product of Horner step i runs in the precision u_i chosen from
+ *   ||B_0||, ||B_i|| and ||Y|| (Theorem 2.1, eq. (choose-ui), Algorithms 2
+ *   and 3), rounded to the hardware tiers available (section 4.1.1).
+ *
+ * General conventions (every entry point):
+ *  - Return value: a ps_status; PS_OK (0) on success, negative on error.
+ *    Nothing throws or aborts across this boundary.
+ *  - Matrices are square, real, column-major with a leading dimension
+ *    (element (i,j) at ptr[i + j*ld]), ld >= n.  Since p(A^T) = p(A)^T for
+ *    real coefficients, row-major data may be passed unchanged and the
+ *    result comes back row-major too (the same holds for the gradient).
+ *  - Pointers named A, G, P, E, grad are DEVICE pointers; coefficient arrays
+ *    and size/index arrays are HOST pointers, copied before the call returns.
+ *  - All arguments are validated on the host before any device work; on
+ *    error no kernel is launched.  PS_ERR_ALIAS is returned when an output
+ *    overlaps an input.
+ *  - Work is queued asynchronously on `stream` (a hipStream_t; NULL = the
+ *    null stream).  The caller keeps every buffer alive until the stream
+ *    has completed.  When a ps_report is requested the call synchronises
+ *    the stream before returning.
+ *  - The library never allocates device memory: scratch space is the
+ *    caller's `ws` of at least the size returned by the matching
+ *    ps_workspace_size* query (256-byte aligned pointer required).
+ *  - On error, output contents are unspecified.  IEEE non-finite values in
+ *    the input propagate through the arithmetic.
+ */
+#ifndef PS_H
+#define PS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PS_OK = 0,
+  PS_ERR_ARG = -1,         /* invalid size, degree, block size, pointer, ld */
+  PS_ERR_ALIAS = -2,       /* output overlaps an input */
+  PS_ERR_WORKSPACE = -3,   /* workspace missing, too small or misaligned */
+  PS_ERR_UNSUPPORTED = -5, /* valid request this build does not implement */
+  PS_ERR_HIP = -6          /* a HIP runtime call failed; see ps_last_error() */
+} ps_status;
+
+/* Working (target) precision; also the element type of A and of the result. */
+typedef enum { PS_F64 = 0, PS_F32 = 1 } ps_dtype;
+
+/* Precision tiers of the Horner products (unit roundoffs 2^-53, 2^-24,
+ * 2^-8, 2^-4).  FP8 is OCP E4M3 with a power-of-two (E8M0) scale per 32
+ * consecutive elements along the reduction dimension. */
+typedef enum { PS_TIER_F64 = 0, PS_TIER_F32 = 1, PS_TIER_BF16 = 2, PS_TIER_FP8 = 3 } ps_tier;
+
+#define PS_MODE_FIXED 0   /* Algorithm 1: every product in the working precision */
+#define PS_MODE_MIXED 1   /* Algorithms 2/3 (fixed s): per-step tiers from the norms */
+
+#define PS_MAX_BLOCKS 64  /* r + 1 <= PS_MAX_BLOCKS */
+
+typedef struct ps_opts {
+  int mode;                  /* PS_MODE_FIXED or PS_MODE_MIXED */
+  unsigned tier_mask;        /* bit t allows tier t; 0 = all tiers.  The working
+                                tier is always allowed; tiers of higher precision
+                                than the working one are never used. */
+  double delta;              /* lower precision only where u_i >= delta*u
+                                (section 3.2, default 10; <= 0 = default) */
+  const int* tier_override;  /* optional host array of r+1 tiers (entry 0 ignored),
+                                replaces the plan (testing); NULL = plan */
+  int profile;               /* nonzero: time the phases with hipEvents */
+} ps_opts;
+
+typedef struct ps_report {
+  int s, r, nu;              /* block size, floor(m/s), first low-precision step */
+  int first_step;            /* index of the first Horner product formed as a GEMM */
+  int tier[PS_MAX_BLOCKS];   /* tier[i]: precision of the product P_i * Y (i = 1..r) */
+  double u[PS_MAX_BLOCKS];   /* u_i from eq. (choose-ui) (u_0 = working) */
+  double normB[PS_MAX_BLOCKS]; /* ||B_i||_1 of the assembled blocks */
+  double normY;              /* ||X^s||_1 */
+  int gemms[4];              /* GEMMs per tier: powers + Horner + squarings */
+  float ms_power, ms_assemble, ms_horner, ms_square;  /* profile != 0 only */
+} ps_report;
+
+/* Version of the ABI (major*10000 + minor*100 + patch). */
+int ps_version(void);
+
+/* Static text for a status code. */
+const char* ps_strerror(int status);
+
+/* Thread-local detail of the most recent failure in this thread ("" if none). */
+const char* ps_last_error(void);
+
+/* Built-in coefficients, correctly rounded to double from the exact rationals:
+ *   ps_coef_taylor_exp: c_k = 1/k!, k = 0..m            (section 3)
+ *   ps_coef_pade_exp:   numerator p_j and denominator q_j, j = 0..deg, of the
+ *                       [deg/deg] Pade approximant of exp (section 4.1);
+ *                       q_j = (-1)^j p_j
+ *   ps_coef_taylor_cos: c_k = (-1)^k / (2k)!, k = 0..m, a polynomial in X^2
+ *                       (section 4.2)
+ * Output arrays have m+1 (deg+1) entries; m <= 170. */
+ps_status ps_coef_taylor_exp(int m, double* coef);
+ps_status ps_coef_pade_exp(int deg, double* p, double* q);
+ps_status ps_coef_taylor_cos(int m, double* coef);
+
+/* Precision plan of the mixed scheme from block norms (host only, no GPU).
+ *   normB[0..r] = ||B_i||_1, normY = ||X^s||_1, dtype = working precision.
+ *   Rule: u_i = u ||B_0|| / max_{j>=i} ||B_j|| ||Y||^j  (eq. (choose-ui) with
+ *   nu = 1, made monotone as the framework of section 2 requires);
+ *   nu = min{i : u_i >= delta u} (Algorithms 2, 3); tier(i) for i >= nu is the
+ *   lowest-precision allowed tier whose unit roundoff does not exceed u_i
+ *   (section 4.1.1); steps 1..nu-1 stay in the working precision.  A zero
+ *   denominator gives u_i = +inf (the product is exactly zero).
+ * Outputs tier[0..r], u[0..r] (caller arrays of r+1) and *nu. */
+ps_status ps_plan(ps_dtype dtype, int r, const double* normB, double normY,
+                  const ps_opts* opts, int* tier, double* u, int* nu);
+
+/* ---------------------------------------------------------------------------
+ * Single matrix.
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for ps_eval / ps_expm with these sizes (sigma = 0 for
+ * ps_eval).  s = 0 selects ceil(sqrt(m)). */
+ps_status ps_workspace_size(ps_dtype dtype, int64_t n, int m, int s, int sigma, size_t* bytes);
+
+/* P = p(A) = sum_{k=0}^{m} coef[k] A^k  (Algorithm 1 in PS_MODE_FIXED,
+ * Algorithm 3 with fixed s in PS_MODE_MIXED).
+ *   n >= 1; A: n x n (lda >= n); coef: host array of m+1 doubles, used as
+ *   given (rounded to float where an FP32 step consumes it); 0 <= m;
+ *   1 <= s <= max(m,1) or s = 0 (= ceil(sqrt(m))); P: n x n output (ldp >= n),
+ *   must not overlap A.  opts may be NULL (fixed mode).  report may be NULL. */
+ps_status ps_eval(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
+                  const double* coef, int m, int s,
+                  void* P, int64_t ldp, const ps_opts* opts, ps_report* report,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* E = r(A) = p(2^-sigma A)^(2^sigma): scaling and squaring (eq. (scal-idea))
+ * around the PS evaluation of p at X = 2^-sigma A.  coef = NULL selects the
+ * Taylor coefficients 1/k! (Algorithm 2's polynomial).  0 <= sigma <= 1000.
+ * The squarings run in the working precision. */
+ps_status ps_expm(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
+                  const double* coef, int m, int s, int sigma,
+                  void* E, int64_t lde, const ps_opts* opts, ps_report* report,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Several polynomials of one matrix sharing one power table (section 4:
+ * the Pade numerator and denominator; the cosine, which is a polynomial in
+ * X^2).  square_arg = 0: P_t = p_t(A); square_arg = 1: P_t = p_t(A^2)
+ * (one extra product forms A^2 first).
+ *   k >= 1 polynomials; coefs[t]: host array of degrees[t]+1 doubles; one
+ *   block size s for all (s = 0: ceil(sqrt(max degree))); P: host array of k
+ *   device pointers, ldp: host array of k leading dimensions; reports: NULL
+ *   or a host array of k reports. */
+ps_status ps_workspace_size_multi(ps_dtype dtype, int64_t n, int k, const int* degrees, int s,
+                                  int square_arg, size_t* bytes);
+ps_status ps_eval_multi(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
+                        int k, const double* const* coefs, const int* degrees, int s,
+                        int square_arg, void* const* P, const int64_t* ldp,
+                        const ps_opts* opts, ps_report* reports,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Many matrices of one size n (contiguous, fixed stride): the same
+ * computation as ps_expm for each matrix b = 0..batch-1 at
+ * A + b*strideA, E + b*strideE (strides in elements).  Each matrix gets its
+ * own precision plan.  reports: NULL or host array of `batch` reports.
+ * ------------------------------------------------------------------------- */
+ps_status ps_workspace_size_strided(ps_dtype dtype, int batch, int64_t n, int m, int s, int sigma,
+                                    size_t* bytes);
+ps_status ps_expm_strided_batched(ps_dtype dtype, int batch, int64_t n,
+                                  const void* A, int64_t lda, int64_t strideA,
+                                  const double* coef, int m, int s, int sigma,
+                                  void* E, int64_t lde, int64_t strideE,
+                                  const ps_opts* opts, ps_report* reports,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Many matrices of uneven sizes in one persistent launch.  Matrix b has order
+ * n[b] (1 <= n[b] <= 256), lives at device pointer A[b] with leading dimension
+ * lda[b], and its result goes to E[b] (lde[b]).  Per-matrix block size s[b]
+ * (0 = chosen per matrix from {floor(sqrt m), ceil(sqrt m)} by the lower
+ * modelled cost) and scaling sigma[b].  Host arrays of `batch` entries.
+ * Every matrix is planned on the device (mixed mode) without a host round
+ * trip, so the whole call can be captured in a hipGraph.
+ * tiers_out: NULL or host array of batch*PS_MAX_BLOCKS ints receiving each
+ * matrix's tier vector (synchronises the stream).
+ * ------------------------------------------------------------------------- */
+ps_status ps_workspace_size_batched(ps_dtype dtype, int batch, const int32_t* n, int m,
+                                    const int32_t* s, size_t* bytes);
+ps_status ps_expm_batched(ps_dtype dtype, int batch, const int32_t* n,
+                          const void* const* A, const int64_t* lda,
+                          const double* coef, int m, const int32_t* s, const int32_t* sigma,
+                          void* const* E, const int64_t* lde,
+                          const ps_opts* opts, int32_t* tiers_out,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Graph form of ps_expm_batched for repeated evaluation of the same batch
+ * layout: ps_batched_prepare validates, uploads the work descriptors into the
+ * workspace (synchronously) and captures the launch sequence into a
+ * hipGraph; ps_batched_launch replays it on `stream`; ps_batched_destroy
+ * frees the host-side graph.  The pointers given to prepare must stay valid
+ * and keep their meaning for every launch. */
+typedef struct ps_batched_exec* ps_batched_handle;
+ps_status ps_batched_prepare(ps_dtype dtype, int batch, const int32_t* n,
+                             const void* const* A, const int64_t* lda,
+                             const double* coef, int m, const int32_t* s, const int32_t* sigma,
+                             void* const* E, const int64_t* lde, const ps_opts* opts,
+                             void* ws, size_t ws_bytes, void* stream, ps_batched_handle* out);
+ps_status ps_batched_launch(ps_batched_handle h, void* stream);
+ps_status ps_batched_destroy(ps_batched_handle h);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint.  gradA = d<G, r(A)>/dA for r(A) = p(2^-sigma A)^(2^sigma), i.e. the
+ * Frechet derivative L_r(A^T, G), by reverse-mode differentiation of the
+ * squarings, the Horner recurrence, the block assembly and the power table
+ * (each reverse Horner step reuses the forward step's tier).
+ * recompute = 1 keeps only A and recomputes the power table and Horner
+ * iterates (smaller workspace); 0 stores them from the forward pass.
+ * Strided-batched over `batch` matrices of order n like
+ * ps_expm_strided_batched.  G: upstream gradient, same layout as E.
+ * gradA must not overlap A or G.
+ * ------------------------------------------------------------------------- */
+ps_status ps_workspace_size_backward(ps_dtype dtype, int batch, int64_t n, int m, int s, int sigma,
+                                     int recompute, size_t* bytes);
+ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n,
+                           const void* A, int64_t lda, int64_t strideA,
+                           const void* G, int64_t ldg, int64_t strideG,
+                           const double* coef, int m, int s, int sigma,
+                           void* gradA, int64_t ldga, int64_t strideGA,
+                           int recompute, const ps_opts* opts,
+                           void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PS_H */

@@ -1,5 +1,313 @@
 """Mixed-precision Paterson--Stockmeyer evaluation of matrix polynomials on
-AMD MI355X (gfx950).  The compute path is the C-ABI library libps.so built
-from csrc/ (hand-written HIP kernels); this package only marshals arguments.
-Importing the package does not load the library; the first call does, and it
-raises if the library is missing."""
+AMD MI355X (gfx950).
+
+Every step of the computation runs in libps.so (hand-written HIP kernels,
+C ABI in include/ps.h).  This module only marshals arguments: it allocates
+outputs and the workspace as torch tensors on the tensor's device, passes raw
+device pointers and the current HIP stream, and raises if the library is
+missing or returns an error.  Importing the package loads nothing; the first
+call loads libps.so.
+
+Layout: torch tensors are row-major; they are handed to the column-major C ABI
+unchanged.  For real coefficients p(A^T) = p(A)^T (and likewise for the
+gradient), so results come back in the caller's row-major layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libps.so")
+
+PS_F64, PS_F32 = 0, 1
+TIER_F64, TIER_F32, TIER_BF16, TIER_FP8 = 0, 1, 2, 3
+TIER_NAMES = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp8"}
+MODE_FIXED, MODE_MIXED = 0, 1
+MAX_BLOCKS = 64
+
+
+class PSError(RuntimeError):
+    pass
+
+
+class ps_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("tier_mask", ctypes.c_uint), ("delta", ctypes.c_double),
+                ("tier_override", ctypes.POINTER(ctypes.c_int)), ("profile", ctypes.c_int)]
+
+
+class ps_report(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int), ("r", ctypes.c_int), ("nu", ctypes.c_int), ("first_step", ctypes.c_int),
+                ("tier", ctypes.c_int * MAX_BLOCKS), ("u", ctypes.c_double * MAX_BLOCKS),
+                ("normB", ctypes.c_double * MAX_BLOCKS), ("normY", ctypes.c_double),
+                ("gemms", ctypes.c_int * 4), ("ms_power", ctypes.c_float), ("ms_assemble", ctypes.c_float),
+                ("ms_horner", ctypes.c_float), ("ms_square", ctypes.c_float)]
+
+    def to_dict(self):
+        r = self.r
+        return {"s": self.s, "r": r, "nu": self.nu, "first_step": self.first_step,
+                "tier": [self.tier[i] for i in range(r + 1)], "u": [self.u[i] for i in range(r + 1)],
+                "normB": [self.normB[i] for i in range(r + 1)], "normY": self.normY,
+                "gemms": list(self.gemms), "ms": {"power": self.ms_power, "assemble": self.ms_assemble,
+                                                  "horner": self.ms_horner, "square": self.ms_square}}
+
+
+_lib = None
+
+_i, _u, _d = ctypes.c_int, ctypes.c_uint, ctypes.c_double
+_i64, _sz, _vp = ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_op = ctypes.POINTER(ps_opts)
+_rp = ctypes.POINTER(ps_report)
+
+_SIGS = {
+    "ps_version": ([], _i),
+    "ps_strerror": ([_i], ctypes.c_char_p),
+    "ps_last_error": ([], ctypes.c_char_p),
+    "ps_coef_taylor_exp": ([_i, _dp], _i),
+    "ps_coef_pade_exp": ([_i, _dp, _dp], _i),
+    "ps_coef_taylor_cos": ([_i, _dp], _i),
+    "ps_plan": ([_i, _i, _dp, _d, _op, _ip, _dp, _ip], _i),
+    "ps_workspace_size": ([_i, _i64, _i, _i, _i, _szp], _i),
+    "ps_eval": ([_i, _i64, _vp, _i64, _dp, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
+    "ps_expm": ([_i, _i64, _vp, _i64, _dp, _i, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
+    "ps_workspace_size_multi": ([_i, _i64, _i, _ip, _i, _i, _szp], _i),
+    "ps_eval_multi": ([_i, _i64, _vp, _i64, _i, ctypes.POINTER(_dp), _ip, _i, _i, ctypes.POINTER(_vp), _i64p,
+                       _op, _rp, _vp, _sz, _vp], _i),
+    "ps_workspace_size_strided": ([_i, _i, _i64, _i, _i, _i, _szp], _i),
+    "ps_expm_strided_batched": ([_i, _i, _i64, _vp, _i64, _i64, _dp, _i, _i, _i, _vp, _i64, _i64, _op, _rp,
+                                 _vp, _sz, _vp], _i),
+    "ps_workspace_size_batched": ([_i, _i, ctypes.POINTER(ctypes.c_int32), _i, ctypes.POINTER(ctypes.c_int32),
+                                   _szp], _i),
+    "ps_expm_batched": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _dp, _i,
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp),
+                         _i64p, _op, ctypes.POINTER(ctypes.c_int32), _vp, _sz, _vp], _i),
+    "ps_batched_prepare": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _dp, _i,
+                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp),
+                            _i64p, _op, _vp, _sz, _vp, ctypes.POINTER(_vp)], _i),
+    "ps_batched_launch": ([_vp, _vp], _i),
+    "ps_batched_destroy": ([_vp], _i),
+    "ps_workspace_size_backward": ([_i, _i, _i64, _i, _i, _i, _i, _szp], _i),
+    "ps_expm_backward": ([_i, _i, _i64, _vp, _i64, _i64, _vp, _i64, _i64, _dp, _i, _i, _i, _vp, _i64, _i64, _i,
+                          _op, _vp, _sz, _vp], _i),
+}
+
+
+def lib():
+    """Load libps.so (raises PSError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise PSError("libps.so not found at %s: build it with `python -m paper_2312_17396_amd.build` "
+                          "(there is no fallback path)" % LIBPATH)
+        L = ctypes.CDLL(LIBPATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status):
+    if status != 0:
+        L = lib()
+        raise PSError("%s: %s" % (L.ps_strerror(status).decode(), L.ps_last_error().decode()))
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return PS_F64
+    if t.dtype == torch.float32:
+        return PS_F32
+    raise PSError("dtype %s not supported (float64 or float32)" % t.dtype)
+
+
+def _darr(vals):
+    vals = [float(v) for v in vals]
+    return (ctypes.c_double * max(len(vals), 1))(*vals)
+
+
+def _opts(mode="fixed", tier_mask=0, delta=10.0, tier_override=None, profile=False):
+    o = ps_opts()
+    o.mode = MODE_MIXED if mode in ("mixed", MODE_MIXED) else MODE_FIXED
+    o.tier_mask = int(tier_mask)
+    o.delta = float(delta)
+    keep = None
+    if tier_override is not None:
+        keep = (ctypes.c_int * len(tier_override))(*[int(t) for t in tier_override])
+        o.tier_override = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int))
+    o.profile = 1 if profile else 0
+    return o, keep
+
+
+def _stream_ptr(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes, device):
+    """A 256-byte aligned device buffer of at least nbytes (torch allocation)."""
+    import torch
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off, int(nbytes)
+
+
+def _check_square(A):
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise PSError("expected a square matrix, got shape %s" % (tuple(A.shape),))
+    if not A.is_cuda:
+        raise PSError("expected a device (HIP) tensor")
+    return A.contiguous()
+
+
+# ---------------------------------------------------------------------------
+# coefficients and planning (host)
+# ---------------------------------------------------------------------------
+def coef_taylor_exp(m):
+    out = (ctypes.c_double * (m + 1))()
+    _check(lib().ps_coef_taylor_exp(int(m), out))
+    return list(out)
+
+
+def coef_taylor_cos(m):
+    out = (ctypes.c_double * (m + 1))()
+    _check(lib().ps_coef_taylor_cos(int(m), out))
+    return list(out)
+
+
+def coef_pade_exp(deg):
+    p = (ctypes.c_double * (deg + 1))()
+    q = (ctypes.c_double * (deg + 1))()
+    _check(lib().ps_coef_pade_exp(int(deg), p, q))
+    return list(p), list(q)
+
+
+def ps_plan(normB, normY, dtype=PS_F64, mode="mixed", tier_mask=0, delta=10.0):
+    r = len(normB) - 1
+    tier = (ctypes.c_int * (r + 1))()
+    u = (ctypes.c_double * (r + 1))()
+    nu = ctypes.c_int()
+    o, _k = _opts(mode, tier_mask, delta)
+    _check(lib().ps_plan(int(dtype), r, _darr(normB), float(normY), ctypes.byref(o), tier, u, ctypes.byref(nu)))
+    return list(tier), list(u), nu.value
+
+
+def default_s(m):
+    if m <= 1:
+        return 1
+    return int(math.ceil(math.sqrt(m) - 1e-12))
+
+
+# ---------------------------------------------------------------------------
+# single matrix
+# ---------------------------------------------------------------------------
+def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=None, report=False, profile=False):
+    """P = sum_k coef[k] A^k by Paterson--Stockmeyer (mixed mode: per-step tiers)."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    m = len(coef) - 1
+    dt = _dtype_code(A)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size(dt, n, m, int(s), 0, ctypes.byref(nbytes)))
+    ws, wsp, wsb = _workspace(nbytes.value, A.device)
+    P = torch.empty_like(A)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile)
+    rep = ps_report() if (report or profile) else None
+    _check(lib().ps_eval(dt, n, A.data_ptr(), n, _darr(coef), m, int(s), P.data_ptr(), n, ctypes.byref(o),
+                         ctypes.byref(rep) if rep is not None else None, wsp, wsb, _stream_ptr(A.device)))
+    return (P, rep.to_dict()) if rep is not None else P
+
+
+def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, tier_override=None,
+            report=False, profile=False, out=None, workspace=None):
+    """E = p(2^-sigma A)^(2^sigma); coef=None uses the Taylor coefficients 1/k!."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size(dt, n, int(m), int(s), int(sigma), ctypes.byref(nbytes)))
+    if workspace is None:
+        ws, wsp, wsb = _workspace(nbytes.value, A.device)
+    else:
+        ws, wsp, wsb = workspace
+    E = torch.empty_like(A) if out is None else out
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile)
+    rep = ps_report() if (report or profile) else None
+    c = _darr(coef) if coef is not None else None
+    _check(lib().ps_expm(dt, n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n, ctypes.byref(o),
+                         ctypes.byref(rep) if rep is not None else None, wsp, wsb, _stream_ptr(A.device)))
+    return (E, rep.to_dict()) if rep is not None else E
+
+
+def expm_workspace(A, m, s=0, sigma=0):
+    """Pre-allocate a workspace for repeated ps_expm calls of this shape."""
+    n = A.shape[0]
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size(_dtype_code(A), n, int(m), int(s), int(sigma), ctypes.byref(nbytes)))
+    return _workspace(nbytes.value, A.device)
+
+
+def ps_eval_multi(A, coefs, s=0, square_arg=False, mode="fixed", tier_mask=0, delta=10.0, report=False,
+                  profile=False):
+    """[p_t(A) for t] (or p_t(A^2) with square_arg) sharing one power table."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    k = len(coefs)
+    dt = _dtype_code(A)
+    degrees = (ctypes.c_int * k)(*[len(c) - 1 for c in coefs])
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_multi(dt, n, k, degrees, int(s), int(bool(square_arg)), ctypes.byref(nbytes)))
+    ws, wsp, wsb = _workspace(nbytes.value, A.device)
+    outs = [torch.empty_like(A) for _ in range(k)]
+    carr = [_darr(c) for c in coefs]
+    cptrs = (_dp * k)(*[ctypes.cast(c, _dp) for c in carr])
+    pptrs = (_vp * k)(*[o.data_ptr() for o in outs])
+    lds = (ctypes.c_int64 * k)(*([n] * k))
+    o, _k = _opts(mode, tier_mask, delta, None, profile)
+    reps = (ps_report * k)() if (report or profile) else None
+    _check(lib().ps_eval_multi(dt, n, A.data_ptr(), n, k, cptrs, degrees, int(s), int(bool(square_arg)), pptrs, lds,
+                               ctypes.byref(o), reps, wsp, wsb, _stream_ptr(A.device)))
+    if reps is not None:
+        return outs, [r.to_dict() for r in reps]
+    return outs
+
+
+# ---------------------------------------------------------------------------
+# batches
+# ---------------------------------------------------------------------------
+def ps_expm_strided_batched(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
+                            tier_override=None, profile=False):
+    """E[b] = p(2^-sigma A[b])^(2^sigma) for A of shape (batch, n, n)."""
+    import torch
+    if A.dim() != 3 or A.shape[1] != A.shape[2]:
+        raise PSError("expected (batch, n, n)")
+    A = A.contiguous()
+    bsz, n = A.shape[0], A.shape[1]
+    dt = _dtype_code(A)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_strided(dt, bsz, n, int(m), int(s), int(sigma), ctypes.byref(nbytes)))
+    ws, wsp, wsb = _workspace(nbytes.value, A.device)
+    E = torch.empty_like(A)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile)
+    reps = (ps_report * bsz)() if (report or profile) else None
+    c = _darr(coef) if coef is not None else None
+    _check(lib().ps_expm_strided_batched(dt, bsz, n, A.data_ptr(), n, n * n, c, int(m), int(s), int(sigma),
+                                         E.data_ptr(), n, n * n, ctypes.byref(o), reps, wsp, wsb,
+                                         _stream_ptr(A.device)))
+    if reps is not None:
+        return E, [r.to_dict() for r in reps]
+    return E

@@ -1,0 +1,660 @@
+// Host side of libps: argument validation, workspace layout and the launch
+// sequence of the PS hot path.  See include/ps.h for the contract.
+//
+// Launch sequence for one evaluation (Algorithm 1 / Algorithm 3 with fixed s,
+// X = beta * A, beta = 2^-sigma for the scaling-and-squaring driver):
+//   1. power table  X_2 = beta^2 (A A), X_{j+1} = beta (X_j A)    s-1 GEMMs
+//   2. k_assemble   B_0..B_r, ||B_i||_1, ||Y||_1, low-precision copies of Y
+//   3. k_plan       tiers of the Horner products (on the device)
+//   4. Horner       cast of the first block into its step's format, then
+//                   P_{i-1} = B_{i-1} + P_i Y for i = first..1
+//   5. squarings    R <- R R, sigma times (eq. (scal-idea))
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "ps_internal.h"
+#include "ps_planner.h"
+
+using namespace psk;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ps_status fail(ps_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ps_status fail(ps_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define PS_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail(PS_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxSigma = 500;
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int default_s(int m) {
+  if (m <= 1) return 1;
+  int s = (int)ceil(sqrt((double)m));
+  while ((s - 1) * (s - 1) >= m) --s;
+  while (s * s < m) ++s;
+  return s;
+}
+
+// exact-rational coefficients rounded once: the dd value of the rational
+// (relative error ~1e-32) rounded to double is the correctly rounded double
+// unless the rational lies within 1e-32 of a rounding boundary.
+struct DD { double hi, lo; };
+DD dd_two_sum(double a, double b) {
+  double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+DD dd_div_int(DD x, double k) {  // x / k for a small positive integer k
+  double q1 = x.hi / k;
+  double p = q1 * k;
+  double e = fma(q1, k, -p);
+  double r = ((x.hi - p) - e) + x.lo;
+  double q2 = r / k;
+  DD s = dd_two_sum(q1, q2);
+  return s;
+}
+
+bool overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t mat_span_bytes(int64_t n, int64_t ld, int esize) {
+  return (size_t)((n - 1) * ld + n) * esize;
+}
+
+struct Opts {
+  int mode = PS_MODE_FIXED;
+  unsigned mask = 0xF;
+  double delta = 10.0;
+  const int* override_tiers = nullptr;
+  int profile = 0;
+};
+
+Opts read_opts(const ps_opts* o, int working) {
+  Opts r;
+  if (o) {
+    r.mode = o->mode;
+    r.mask = o->tier_mask ? o->tier_mask : 0xF;
+    r.delta = o->delta > 0 ? o->delta : 10.0;
+    r.override_tiers = o->tier_override;
+    r.profile = o->profile;
+  }
+  r.mask |= 1u << working;
+  for (int t = 0; t < working; ++t) r.mask &= ~(1u << t);
+  return r;
+}
+
+}  // namespace
+
+namespace psk {
+
+Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg) {
+  Layout L;
+  memset(&L, 0, sizeof L);
+  L.n = n;
+  L.m = m;
+  L.s = s;
+  L.r = m / s;
+  L.sigma = sigma;
+  L.working = dt == PS_F64 ? 0 : 1;
+  L.esize = dt == PS_F64 ? 8 : 4;
+  L.square_arg = square_arg;
+  L.trivial_last = (L.r >= 1 && m == s * L.r) ? 1 : 0;
+  L.nB = L.trivial_last ? L.r : L.r + 1;
+  L.first_step = L.trivial_last ? L.r - 1 : L.r;
+  L.Mp = round_up(n, kTile);
+  L.Kp = round_up(n, kKPad);
+  L.slot = al256((size_t)n * n * L.esize);
+  size_t packed8 = (size_t)L.Mp * L.Kp + (size_t)L.Mp * (L.Kp / 32);
+  size_t packed16 = (size_t)L.Mp * L.Kp * 2;
+  L.pslot = al256(std::max({L.slot, packed8, packed16}));
+  size_t off = 0;
+  L.npow = (s >= 2 ? s - 1 : 0) + (square_arg ? 1 : 0);
+  L.off_pow = off;   off += L.npow * L.slot;
+  L.off_B = off;     off += (size_t)L.nB * L.slot;
+  L.off_P0 = off;    off += L.pslot;
+  L.off_P1 = off;    off += L.pslot;
+  L.off_R = off;     off += (sigma > 0 ? L.slot : 0);
+  L.off_yf32 = off;  off += (L.working == 0 ? al256((size_t)n * n * 4) : 0);
+  L.off_ybf16 = off; off += al256((size_t)L.Mp * L.Kp * 2);
+  L.off_yfp8 = off;  off += al256((size_t)L.Mp * L.Kp);
+  L.off_yfp8s = off; off += al256((size_t)L.Mp * (L.Kp / 32));
+  L.off_colsum = off; off += al256((size_t)(L.nB + 1) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
+  L.off_plan = off;  off += al256(sizeof(Plan));
+  L.bytes = al256(off);
+  return L;
+}
+
+}  // namespace psk
+
+namespace {
+
+// Validation shared by the single / strided entry points.
+ps_status check_common(ps_dtype dt, int64_t n, int m, int* s, int sigma) {
+  if (dt != PS_F64 && dt != PS_F32) return fail(PS_ERR_ARG, "dtype must be PS_F64 or PS_F32");
+  if (n < 1 || n > (1LL << 20)) return fail(PS_ERR_ARG, "n = %lld out of range [1, 2^20]", (long long)n);
+  if (m < 0 || m > kMaxDegree) return fail(PS_ERR_ARG, "degree m = %d out of range [0, %d]", m, kMaxDegree);
+  if (*s == 0) *s = default_s(m);
+  if (*s < 1 || *s > std::max(m, 1)) return fail(PS_ERR_ARG, "block size s = %d out of range [1, max(m,1)]", *s);
+  if (m / *s + 1 > PS_MAX_BLOCKS) return fail(PS_ERR_ARG, "r + 1 = %d exceeds %d blocks", m / *s + 1, PS_MAX_BLOCKS);
+  if (sigma < 0 || sigma > kMaxSigma) return fail(PS_ERR_ARG, "sigma = %d out of range [0, %d]", sigma, kMaxSigma);
+  return PS_OK;
+}
+
+ps_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
+  if (ws_bytes < need) return fail(PS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (need && !ws) return fail(PS_ERR_WORKSPACE, "workspace pointer is NULL");
+  if (((uintptr_t)ws & 255) != 0) return fail(PS_ERR_WORKSPACE, "workspace pointer not 256-byte aligned");
+  return PS_OK;
+}
+
+ps_status check_opts(const Opts& o) {
+  if (o.mode != PS_MODE_FIXED && o.mode != PS_MODE_MIXED) return fail(PS_ERR_ARG, "opts.mode must be 0 or 1");
+  return PS_OK;
+}
+
+// One PS evaluation (+ squarings) for a uniform batch, all matrices sharing L.
+struct Job {
+  const Layout* L;
+  int batch;
+  MatArg X1;             // base matrix of the power table (A, or Z = A^2 in the workspace)
+  double beta;           // X_1 = beta * X1
+  const double* coef;
+  MatArg out;            // final result
+  char* ws;
+  size_t ws_stride;
+  Opts opts;
+  bool write_y;          // produce the low-precision copies of Y (first polynomial only)
+  bool build_powers;     // run the power table (first polynomial only)
+  bool skip_square;      // squarings handled by the caller
+};
+
+MatArg ws_mat(char* ws, size_t off, int64_t n, size_t stride_bytes, int esize) {
+  MatArg a;
+  a.p = ws + off;
+  a.ld = n;
+  a.stride = (int64_t)(stride_bytes / esize);
+  return a;
+}
+
+struct Timer {
+  bool on = false;
+  hipEvent_t ev[8];
+  int k = 0;
+  hipStream_t st;
+  ps_status init(bool enable, hipStream_t s) {
+    on = enable;
+    st = s;
+    if (!on) return PS_OK;
+    for (auto& e : ev) PS_HIP(hipEventCreate(&e));
+    return PS_OK;
+  }
+  ps_status mark() {
+    if (on) PS_HIP(hipEventRecord(ev[k++], st));
+    return PS_OK;
+  }
+  float between(int a, int b) {
+    float ms = 0.f;
+    if (on && b < k) (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+    return ms;
+  }
+  ~Timer() {
+    if (on) for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
+  const Layout& L = *J.L;
+  const int W = L.working;
+  const int64_t n = L.n;
+  const size_t wss = J.ws_stride;
+  Timer tm;
+  if (ps_status e = tm.init(phase_ms != nullptr, st)) return e;
+  if (ps_status e = tm.mark()) return e;
+  // 1. power table
+  if (J.build_powers && L.s >= 2) {
+    MatArg prev = J.X1;
+    for (int j = 2; j <= L.s; ++j) {
+      MatArg dst = ws_mat(J.ws, L.off_pow + (size_t)(j - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
+      const double alpha = (j == 2) ? J.beta * J.beta : J.beta;
+      PS_HIP(launch_gemm(W, n, J.batch, prev, 0, J.X1, 0, dst, alpha, 0, st));
+      prev = dst;
+    }
+  }
+  if (ps_status e = tm.mark()) return e;
+  // 2. assemble blocks, norms, Y copies
+  Coefs cf;
+  memset(&cf, 0, sizeof cf);
+  for (int k = 0; k <= L.m; ++k) cf.c[k] = J.coef[k];
+  if (W == 1)  // FP32 working precision: the coefficients enter FP32 arithmetic
+    for (int k = 0; k <= L.m; ++k) cf.c[k] = (double)(float)cf.c[k];
+  AssembleArgs aa;
+  aa.n = n;
+  aa.m = L.m;
+  aa.s = L.s;
+  aa.r = L.r;
+  aa.nB = L.nB;
+  aa.trivial_last = L.trivial_last;
+  aa.X1 = J.X1;
+  aa.x1_scale = J.beta;
+  aa.ws = J.ws;
+  aa.ws_stride = wss;
+  aa.L = L;
+  aa.tier_mask = (J.opts.mode == PS_MODE_MIXED || J.opts.override_tiers) && J.write_y ? J.opts.mask : 0u;
+  PS_HIP(launch_assemble(W, aa, cf, J.batch, st));
+  if (ps_status e = tm.mark()) return e;
+  // 3. plan
+  PlanArgs pa;
+  memset(&pa, 0, sizeof pa);
+  pa.r = L.r;
+  pa.mode = J.opts.mode;
+  pa.working = W;
+  pa.nB = L.nB;
+  pa.trivial_last = L.trivial_last;
+  pa.mask = J.opts.mask;
+  pa.delta = J.opts.delta;
+  pa.abs_cm = fabs(cf.c[L.m]);
+  pa.use_override = J.opts.override_tiers != nullptr;
+  if (pa.use_override)
+    for (int i = 0; i <= L.r; ++i) pa.override_tier[i] = J.opts.override_tiers[i];
+  pa.ws = J.ws;
+  pa.ws_stride = wss;
+  pa.L = L;
+  PS_HIP(launch_plan(pa, J.batch, st));
+  // 4. Horner
+  const bool square = L.sigma > 0 && !J.skip_square;
+  MatArg hout = square ? ws_mat(J.ws, L.off_R, n, wss, L.esize) : J.out;
+  HornerArgs ha;
+  memset(&ha, 0, sizeof ha);
+  ha.n = n;
+  ha.ws = J.ws;
+  ha.ws_stride = wss;
+  ha.L = L;
+  ha.out = hout;
+  if (L.s == 1) {
+    ha.ysrc = J.X1;
+    ha.yscale = J.beta;
+  } else {
+    ha.ysrc = ws_mat(J.ws, L.off_pow + (size_t)(L.s - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
+    ha.yscale = 1.0;
+  }
+  const int i0 = L.first_step;
+  // cast of the first block into the operand format of step i0 (or the result)
+  ha.cast_only = 1;
+  ha.step = i0;
+  ha.final_out = (i0 == 0);
+  ha.off_bsrc = L.off_B + (size_t)i0 * L.slot;
+  ha.off_pout = L.off_P0;
+  PS_HIP(launch_horner(W, ha, J.batch, st));
+  ha.cast_only = 0;
+  for (int i = i0; i >= 1; --i) {
+    const int k = i0 - i;
+    ha.step = i;
+    ha.final_out = (i == 1);
+    ha.off_pin = (k & 1) ? L.off_P1 : L.off_P0;
+    ha.off_pout = (k & 1) ? L.off_P0 : L.off_P1;
+    ha.off_bsrc = L.off_B + (size_t)(i - 1) * L.slot;
+    PS_HIP(launch_horner(W, ha, J.batch, st));
+  }
+  if (ps_status e = tm.mark()) return e;
+  // 5. squarings: R <- R R (working precision), last product into the output
+  if (square) {
+    MatArg bufs[2] = {ws_mat(J.ws, L.off_R, n, wss, L.esize), ws_mat(J.ws, L.off_P0, n, wss, L.esize)};
+    for (int t = 1; t <= L.sigma; ++t) {
+      MatArg src = bufs[(t - 1) & 1];
+      MatArg dst = (t == L.sigma) ? J.out : bufs[t & 1];
+      PS_HIP(launch_gemm(W, n, J.batch, src, 0, src, 0, dst, 1.0, 0, st));
+    }
+  }
+  if (ps_status e = tm.mark()) return e;
+  if (phase_ms) {
+    PS_HIP(hipStreamSynchronize(st));
+    phase_ms[0] = tm.between(0, 1);
+    phase_ms[1] = tm.between(1, 2);
+    phase_ms[2] = tm.between(2, 3);
+    phase_ms[3] = tm.between(3, 4);
+  }
+  return PS_OK;
+}
+
+ps_status fill_report(const Layout& L, const Job& J, int b, ps_report* rep, hipStream_t st, const float* ms) {
+  Plan P;
+  PS_HIP(hipMemcpyAsync(&P, J.ws + (size_t)b * J.ws_stride + L.off_plan, sizeof P, hipMemcpyDeviceToHost, st));
+  PS_HIP(hipStreamSynchronize(st));
+  memset(rep, 0, sizeof *rep);
+  rep->s = L.s;
+  rep->r = L.r;
+  rep->nu = P.nu;
+  rep->first_step = L.first_step;
+  for (int i = 0; i <= L.r; ++i) {
+    rep->tier[i] = P.tier[i];
+    rep->u[i] = P.u[i];
+    rep->normB[i] = P.normB[i];
+  }
+  rep->normY = P.normY;
+  rep->gemms[L.working] += L.npow + L.sigma;
+  for (int i = L.first_step; i >= 1; --i) rep->gemms[P.tier[i]] += 1;
+  if (ms) {
+    rep->ms_power = ms[0];
+    rep->ms_assemble = ms[1];
+    rep->ms_horner = ms[2];
+    rep->ms_square = ms[3];
+  }
+  return PS_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported entry points
+// ===========================================================================
+extern "C" {
+
+int ps_version(void) { return 10000; }
+
+const char* ps_strerror(int status) {
+  switch (status) {
+    case PS_OK: return "success";
+    case PS_ERR_ARG: return "invalid argument";
+    case PS_ERR_ALIAS: return "output overlaps an input";
+    case PS_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case PS_ERR_UNSUPPORTED: return "unsupported request";
+    case PS_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+ps_status ps_coef_taylor_exp(int m, double* coef) {
+  if (m < 0 || m > 170 || !coef) return fail(PS_ERR_ARG, "ps_coef_taylor_exp: m in [0,170], coef != NULL");
+  DD x = {1.0, 0.0};
+  coef[0] = 1.0;
+  for (int k = 1; k <= m; ++k) {
+    x = dd_div_int(x, (double)k);
+    coef[k] = x.hi + x.lo;
+  }
+  return PS_OK;
+}
+
+ps_status ps_coef_taylor_cos(int m, double* coef) {
+  if (m < 0 || m > 85 || !coef) return fail(PS_ERR_ARG, "ps_coef_taylor_cos: m in [0,85], coef != NULL");
+  DD x = {1.0, 0.0};
+  coef[0] = 1.0;
+  for (int k = 1; k <= m; ++k) {
+    x = dd_div_int(x, (double)(2 * k - 1));
+    x = dd_div_int(x, (double)(2 * k));
+    double v = x.hi + x.lo;
+    coef[k] = (k & 1) ? -v : v;
+  }
+  return PS_OK;
+}
+
+ps_status ps_coef_pade_exp(int deg, double* p, double* q) {
+  if (deg < 0 || deg > 60 || !p || !q) return fail(PS_ERR_ARG, "ps_coef_pade_exp: deg in [0,60], p,q != NULL");
+  // p_j = (2d-j)! d! / ((2d)! j! (d-j)!), via p_j = p_{j-1} (d-j+1) / (j (2d-j+1))
+  DD x = {1.0, 0.0};
+  p[0] = q[0] = 1.0;
+  for (int j = 1; j <= deg; ++j) {
+    // multiply by the integer (d-j+1) exactly in dd, then divide by j and (2d-j+1)
+    double f = (double)(deg - j + 1);
+    double hi = x.hi * f;
+    double e = fma(x.hi, f, -hi);
+    DD y = dd_two_sum(hi, e + x.lo * f);
+    y = dd_div_int(y, (double)j);
+    y = dd_div_int(y, (double)(2 * deg - j + 1));
+    x = y;
+    p[j] = x.hi + x.lo;
+    q[j] = (j & 1) ? -p[j] : p[j];
+  }
+  return PS_OK;
+}
+
+ps_status ps_plan(ps_dtype dtype, int r, const double* normB, double normY, const ps_opts* opts, int* tier,
+                  double* u, int* nu) {
+  if (dtype != PS_F64 && dtype != PS_F32) return fail(PS_ERR_ARG, "dtype must be PS_F64 or PS_F32");
+  if (r < 0 || r + 1 > PS_MAX_BLOCKS) return fail(PS_ERR_ARG, "r = %d out of range", r);
+  if (!normB || !tier || !u || !nu) return fail(PS_ERR_ARG, "NULL output or norm array");
+  const int W = dtype == PS_F64 ? 0 : 1;
+  Opts o = read_opts(opts, W);
+  if (o.mode == PS_MODE_FIXED) {
+    for (int i = 0; i <= r; ++i) { tier[i] = W; u[i] = tier_unit_roundoff(W); }
+    *nu = r + 1;
+    return PS_OK;
+  }
+  plan_tiers(r, normB, normY, W, o.mask, o.delta, tier, u, nu);
+  return PS_OK;
+}
+
+ps_status ps_workspace_size(ps_dtype dtype, int64_t n, int m, int s, int sigma, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  if (ps_status e = check_common(dtype, n, m, &s, sigma)) return e;
+  *bytes = make_layout(dtype, n, m, s, sigma, 0).bytes;
+  return PS_OK;
+}
+
+ps_status ps_workspace_size_strided(ps_dtype dtype, int batch, int64_t n, int m, int s, int sigma, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  if (batch < 1 || batch > 65535) return fail(PS_ERR_ARG, "batch = %d out of range [1, 65535]", batch);
+  if (ps_status e = check_common(dtype, n, m, &s, sigma)) return e;
+  *bytes = make_layout(dtype, n, m, s, sigma, 0).bytes * (size_t)batch;
+  return PS_OK;
+}
+
+static ps_status expm_impl(ps_dtype dtype, int batch, int64_t n, const void* A, int64_t lda, int64_t strideA,
+                           const double* coef, int m, int s, int sigma, double beta, void* E, int64_t lde,
+                           int64_t strideE, const ps_opts* opts, ps_report* reports, void* ws, size_t ws_bytes,
+                           void* stream) {
+  if (ps_status e = check_common(dtype, n, m, &s, sigma)) return e;
+  if (batch < 1 || batch > 65535) return fail(PS_ERR_ARG, "batch = %d out of range [1, 65535]", batch);
+  if (!A || !E) return fail(PS_ERR_ARG, "NULL matrix pointer");
+  if (lda < n || lde < n) return fail(PS_ERR_ARG, "leading dimension smaller than n");
+  const int esize = dtype == PS_F64 ? 8 : 4;
+  if (batch > 1) {
+    if (strideA < (int64_t)((n - 1) * lda + n) || strideE < (int64_t)((n - 1) * lde + n))
+      return fail(PS_ERR_ARG, "batch stride smaller than one matrix");
+  }
+  Opts o = read_opts(opts, dtype == PS_F64 ? 0 : 1);
+  if (ps_status e = check_opts(o)) return e;
+  if (o.override_tiers) {
+    const int r = m / s;
+    for (int i = 1; i <= r; ++i)
+      if (o.override_tiers[i] < (dtype == PS_F64 ? 0 : 1) || o.override_tiers[i] > 3)
+        return fail(PS_ERR_ARG, "tier_override[%d] = %d not a usable tier", i, o.override_tiers[i]);
+  }
+  const size_t spanA = (size_t)(batch - 1) * strideA * esize + mat_span_bytes(n, lda, esize);
+  const size_t spanE = (size_t)(batch - 1) * strideE * esize + mat_span_bytes(n, lde, esize);
+  if (overlap(A, spanA, E, spanE)) return fail(PS_ERR_ALIAS, "output overlaps the input matrix");
+  Layout L = make_layout(dtype, n, m, s, sigma, 0);
+  if (ps_status e = check_ws(ws, ws_bytes, L.bytes * (size_t)batch)) return e;
+  if (overlap(ws, L.bytes * (size_t)batch, E, spanE) || overlap(ws, L.bytes * (size_t)batch, A, spanA))
+    return fail(PS_ERR_ALIAS, "workspace overlaps a matrix argument");
+  std::vector<double> c(m + 1);
+  if (coef) {
+    for (int k = 0; k <= m; ++k) c[k] = coef[k];
+  } else {
+    if (m > 170) return fail(PS_ERR_ARG, "built-in Taylor coefficients need m <= 170");
+    ps_coef_taylor_exp(m, c.data());
+  }
+  Job J;
+  J.L = &L;
+  J.batch = batch;
+  J.X1 = MatArg{A, lda, strideA};
+  J.beta = beta;
+  J.coef = c.data();
+  J.out = MatArg{E, lde, strideE};
+  J.ws = (char*)ws;
+  J.ws_stride = L.bytes;
+  J.opts = o;
+  J.write_y = true;
+  J.build_powers = true;
+  J.skip_square = false;
+  hipStream_t st = (hipStream_t)stream;
+  float ms[4] = {0, 0, 0, 0};
+  if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
+  if (reports)
+    for (int b = 0; b < batch; ++b)
+      if (ps_status e = fill_report(L, J, b, &reports[b], st, o.profile ? ms : nullptr)) return e;
+  return PS_OK;
+}
+
+ps_status ps_eval(ps_dtype dtype, int64_t n, const void* A, int64_t lda, const double* coef, int m, int s, void* P,
+                  int64_t ldp, const ps_opts* opts, ps_report* report, void* ws, size_t ws_bytes, void* stream) {
+  if (!coef) return fail(PS_ERR_ARG, "coef == NULL");
+  return expm_impl(dtype, 1, n, A, lda, 0, coef, m, s, 0, 1.0, P, ldp, 0, opts, report, ws, ws_bytes, stream);
+}
+
+ps_status ps_expm(ps_dtype dtype, int64_t n, const void* A, int64_t lda, const double* coef, int m, int s, int sigma,
+                  void* E, int64_t lde, const ps_opts* opts, ps_report* report, void* ws, size_t ws_bytes,
+                  void* stream) {
+  if (sigma < 0 || sigma > kMaxSigma) return fail(PS_ERR_ARG, "sigma = %d out of range [0, %d]", sigma, kMaxSigma);
+  return expm_impl(dtype, 1, n, A, lda, 0, coef, m, s, sigma, ldexp(1.0, -sigma), E, lde, 0, opts, report, ws,
+                   ws_bytes, stream);
+}
+
+ps_status ps_expm_strided_batched(ps_dtype dtype, int batch, int64_t n, const void* A, int64_t lda, int64_t strideA,
+                                  const double* coef, int m, int s, int sigma, void* E, int64_t lde, int64_t strideE,
+                                  const ps_opts* opts, ps_report* reports, void* ws, size_t ws_bytes, void* stream) {
+  if (sigma < 0 || sigma > kMaxSigma) return fail(PS_ERR_ARG, "sigma = %d out of range [0, %d]", sigma, kMaxSigma);
+  return expm_impl(dtype, batch, n, A, lda, strideA, coef, m, s, sigma, ldexp(1.0, -sigma), E, lde, strideE, opts,
+                   reports, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// several polynomials sharing one power table
+// ---------------------------------------------------------------------------
+static ps_status multi_layouts(ps_dtype dtype, int64_t n, int k, const int* degrees, int* s, int square_arg,
+                               std::vector<Layout>& Ls, size_t* total) {
+  if (k < 1 || k > 16) return fail(PS_ERR_ARG, "k = %d polynomials out of range [1, 16]", k);
+  if (!degrees) return fail(PS_ERR_ARG, "degrees == NULL");
+  int mmax = 0;
+  for (int t = 0; t < k; ++t) {
+    if (degrees[t] < 0 || degrees[t] > kMaxDegree) return fail(PS_ERR_ARG, "degree %d out of range", degrees[t]);
+    mmax = std::max(mmax, degrees[t]);
+  }
+  int sv = *s;
+  if (ps_status e = check_common(dtype, n, mmax, &sv, 0)) return e;
+  for (int t = 0; t < k; ++t)
+    if (degrees[t] / sv + 1 > PS_MAX_BLOCKS) return fail(PS_ERR_ARG, "too many blocks for degree %d", degrees[t]);
+  *s = sv;
+  // shared part: the power table (and Z = A^2) and the Y copies live in the
+  // layout of polynomial 0; every other polynomial gets a private section
+  // holding its blocks, iterates, column sums and plan.
+  Ls.clear();
+  Layout base = make_layout(dtype, n, degrees[0], sv, 0, square_arg);
+  // make sure polynomial 0's section fits the largest block count
+  size_t off = base.bytes;
+  Ls.push_back(base);
+  for (int t = 1; t < k; ++t) {
+    Layout Lt = make_layout(dtype, n, degrees[t], sv, 0, square_arg);
+    Layout priv = Lt;
+    // private offsets: B, P0, P1, colsum, plan relocated after `off`
+    size_t o = off;
+    priv.off_B = o;      o += (size_t)Lt.nB * Lt.slot;
+    priv.off_P0 = o;     o += Lt.pslot;
+    priv.off_P1 = o;     o += Lt.pslot;
+    priv.off_colsum = o; o += al256((size_t)(Lt.nB + 1) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
+    priv.off_plan = o;   o += al256(sizeof(Plan));
+    // shared offsets from polynomial 0
+    priv.off_pow = base.off_pow;
+    priv.npow = base.npow;
+    priv.off_yf32 = base.off_yf32;
+    priv.off_ybf16 = base.off_ybf16;
+    priv.off_yfp8 = base.off_yfp8;
+    priv.off_yfp8s = base.off_yfp8s;
+    priv.off_R = base.off_R;
+    off = al256(o);
+    Ls.push_back(priv);
+  }
+  *total = off;
+  for (auto& L : Ls) L.bytes = off;
+  return PS_OK;
+}
+
+ps_status ps_workspace_size_multi(ps_dtype dtype, int64_t n, int k, const int* degrees, int s, int square_arg,
+                                  size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  std::vector<Layout> Ls;
+  return multi_layouts(dtype, n, k, degrees, &s, square_arg ? 1 : 0, Ls, bytes);
+}
+
+ps_status ps_eval_multi(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int k, const double* const* coefs,
+                        const int* degrees, int s, int square_arg, void* const* P, const int64_t* ldp,
+                        const ps_opts* opts, ps_report* reports, void* ws, size_t ws_bytes, void* stream) {
+  std::vector<Layout> Ls;
+  size_t total = 0;
+  square_arg = square_arg ? 1 : 0;
+  if (ps_status e = multi_layouts(dtype, n, k, degrees, &s, square_arg, Ls, &total)) return e;
+  if (!A || !coefs || !P || !ldp) return fail(PS_ERR_ARG, "NULL argument");
+  if (lda < n) return fail(PS_ERR_ARG, "lda < n");
+  const int esize = dtype == PS_F64 ? 8 : 4;
+  const size_t spanA = mat_span_bytes(n, lda, esize);
+  for (int t = 0; t < k; ++t) {
+    if (!coefs[t] || !P[t]) return fail(PS_ERR_ARG, "NULL coefficient or output pointer for polynomial %d", t);
+    if (ldp[t] < n) return fail(PS_ERR_ARG, "ldp[%d] < n", t);
+    const size_t spanP = mat_span_bytes(n, ldp[t], esize);
+    if (overlap(A, spanA, P[t], spanP)) return fail(PS_ERR_ALIAS, "output %d overlaps the input", t);
+    if (overlap(ws, total, P[t], spanP)) return fail(PS_ERR_ALIAS, "output %d overlaps the workspace", t);
+    for (int u2 = 0; u2 < t; ++u2)
+      if (overlap(P[u2], mat_span_bytes(n, ldp[u2], esize), P[t], spanP))
+        return fail(PS_ERR_ALIAS, "outputs %d and %d overlap", u2, t);
+  }
+  if (ps_status e = check_ws(ws, ws_bytes, total)) return e;
+  Opts o = read_opts(opts, dtype == PS_F64 ? 0 : 1);
+  if (ps_status e = check_opts(o)) return e;
+  if (o.override_tiers) return fail(PS_ERR_UNSUPPORTED, "tier_override is not supported by ps_eval_multi");
+  hipStream_t st = (hipStream_t)stream;
+  const int W = dtype == PS_F64 ? 0 : 1;
+  MatArg X1{A, lda, 0};
+  if (square_arg) {
+    MatArg Z = ws_mat((char*)ws, Ls[0].off_pow, n, total, esize);
+    PS_HIP(launch_gemm(W, n, 1, X1, 0, X1, 0, Z, 1.0, 0, st));
+    X1 = Z;
+  }
+  for (int t = 0; t < k; ++t) {
+    Job J;
+    J.L = &Ls[t];
+    J.batch = 1;
+    J.X1 = X1;
+    J.beta = 1.0;
+    J.coef = coefs[t];
+    J.out = MatArg{P[t], ldp[t], 0};
+    J.ws = (char*)ws;
+    J.ws_stride = total;
+    J.opts = o;
+    J.write_y = (t == 0);
+    J.build_powers = (t == 0);
+    J.skip_square = true;
+    float ms[4] = {0, 0, 0, 0};
+    if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
+    if (reports)
+      if (ps_status e = fill_report(Ls[t], J, 0, &reports[t], st, o.profile ? ms : nullptr)) return e;
+  }
+  return PS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations shared by the host driver (ps_api.cpp) and the HIP
+// kernel files.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ps.h"
+
+namespace psk {
+
+constexpr int kMaxDegree = 255;  // coefficients travel by value in kernel arguments
+constexpr int kTile = 64;        // output tile edge of every GEMM kernel
+constexpr int kKPad = 128;       // K padding of the packed low-precision layouts
+constexpr int kRowChunk = 256;   // rows per wave in the column passes
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Per-matrix plan as written by the planning kernel (device) or the host.
+struct Plan {
+  int tier[PS_MAX_BLOCKS];
+  double u[PS_MAX_BLOCKS];
+  double normB[PS_MAX_BLOCKS];
+  double normY;
+  int nu;
+  int pad_[3];
+};
+
+struct Coefs {
+  double c[kMaxDegree + 1];
+};
+
+// Byte layout of the per-matrix workspace region for one PS evaluation
+// (optionally followed by squarings).  All offsets are relative to the start
+// of the matrix's region and 256-byte aligned.
+struct Layout {
+  int64_t n;
+  int m, s, r, sigma;
+  int working;         // 0 = FP64, 1 = FP32
+  int esize;           // bytes of the working type
+  int trivial_last;    // s divides m: B_r = c_m I, step r folded into B_{r-1}
+  int first_step;      // index of the first Horner product formed by a GEMM (0 = none)
+  int square_arg;      // power table of A^2 instead of A
+  int64_t Mp, Kp;      // padded sizes of the packed BF16/FP8 layouts
+  size_t slot;         // bytes of one n x n working-precision matrix
+  size_t pslot;        // bytes of one Horner iterate buffer (any format)
+  size_t off_pow;      // X_2..X_s (s-1 slots); with square_arg slot 0 holds Z = A^2
+  int npow;            // number of power slots
+  size_t off_B;        // B_0..B_{nB-1}
+  int nB;
+  size_t off_P0, off_P1, off_R;
+  size_t off_yf32, off_ybf16, off_yfp8, off_yfp8s;
+  size_t off_colsum;   // (nB + 1) * nchunks * n doubles: partial column abs sums of B_i and Y
+  size_t off_plan;
+  size_t bytes;        // total per matrix
+};
+
+Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in ps_kernels.hip).  All take a batch of matrices
+// addressed as base + b * stride (strides in bytes for workspace pointers, in
+// elements for user pointers).
+// ---------------------------------------------------------------------------
+struct MatArg {
+  const void* p;
+  int64_t ld;
+  int64_t stride;   // elements between consecutive matrices of the batch
+};
+
+// C = alpha * op(A) op(B)  (accumulate != 0: C += alpha * op(A) op(B)).
+hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, MatArg B, int transB,
+                       MatArg C, double alpha, int accumulate, hipStream_t st);
+
+// Column pass: B_0..B_r, folded last step, column abs sums, low-precision Y copies.
+struct AssembleArgs {
+  int64_t n;
+  int m, s, r, nB, trivial_last;
+  MatArg X1;            // X_1 = x1_scale * X1
+  double x1_scale;
+  char* ws;             // base of matrix 0's region
+  size_t ws_stride;     // bytes per matrix
+  Layout L;
+  unsigned tier_mask;   // which low-precision copies of Y to produce
+};
+hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, int batch, hipStream_t st);
+
+// Per-matrix planning kernel.
+struct PlanArgs {
+  int r, mode, working, nB, trivial_last;
+  unsigned mask;
+  double delta;
+  double abs_cm;        // |c_m| (norm of B_r = c_m I when s divides m)
+  int use_override;
+  int override_tier[PS_MAX_BLOCKS];
+  char* ws;
+  size_t ws_stride;
+  Layout L;
+};
+hipError_t launch_plan(const PlanArgs& a, int batch, hipStream_t st);
+
+// One Horner step: P_{i-1} = B_{i-1} + P_i Y (or, with cast_only, P = B_src
+// converted to the format of the consumer step).
+struct HornerArgs {
+  int64_t n;
+  int step;              // i (product P_i Y); for cast_only: the consumer step index
+  int cast_only;
+  int final_out;         // output is the working-precision result (to `out`)
+  MatArg out;            // final output (working precision)
+  size_t off_pin, off_pout;   // Horner iterate buffers in the workspace
+  size_t off_bsrc;       // B_{i-1} (or the cast source) in the workspace
+  MatArg ysrc;           // Y in working precision (X_s slot, or X1 when s == 1)
+  double yscale;         // applied to the working-precision product (s == 1)
+  char* ws;
+  size_t ws_stride;
+  Layout L;
+};
+hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_t st);
+
+// Elementwise scale/copy used by the drivers: dst = alpha * src (n x n).
+hipError_t launch_scale_copy(int working, int64_t n, int batch, MatArg src, MatArg dst, double alpha,
+                             hipStream_t st);
+
+// Fill an n x n matrix with alpha * I (graph-safe replacement for memset).
+hipError_t launch_fill_identity(int working, int64_t n, int batch, MatArg dst, double alpha, hipStream_t st);
+
+// Adjoint helper: Xbar_j += sum_i c_{si+j} Bbar_i  (column pass).
+struct ScatterArgs {
+  int64_t n;
+  int s, r, nB;
+  double coef_scale;
+  char* ws;
+  size_t ws_stride;
+  size_t off_Bbar;      // Bbar_0..Bbar_{nB-1}
+  size_t off_Xbar;      // Xbar_1..Xbar_{s} (s slots)
+  size_t slot;
+};
+hipError_t launch_scatter(int working, const ScatterArgs& a, const Coefs& c, int batch, hipStream_t st);
+
+}  // namespace psk

@@ -1,0 +1,113 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that
+include/ps.h declares, its host-only helpers agree with the oracle, and
+argument validation rejects bad calls before any device work (no kernel is
+launched in this file)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coeffs
+from oracle import plan as oplan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import paper_2312_17396_amd as ps
+    if not os.path.exists(ps.LIBPATH):
+        from paper_2312_17396_amd import build
+        build.build()
+    ps.lib()
+    return ps
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ps.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ps_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported(ps):
+    names = declared_functions()
+    assert len(names) >= 20
+    L = ctypes.CDLL(ps.LIBPATH)
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(names) == set(ps.exported_symbols())
+
+
+def test_builtin_coefficients_match_exact_rationals(ps):
+    assert ps.coef_taylor_exp(170) == coeffs.taylor_exp(170)
+    assert ps.coef_taylor_cos(40) == coeffs.taylor_cos(40)
+    for d in range(0, 31):
+        p, q = ps.coef_pade_exp(d)
+        P, Q = coeffs.pade_exp(d, d)
+        assert p == P and q == Q, d
+
+
+def test_host_planner_matches_oracle_planner(ps):
+    rng = np.random.default_rng(5)
+    for trial in range(400):
+        r = int(rng.integers(0, 8))
+        nb = list(np.exp(rng.uniform(-40, 3, r + 1)))
+        if trial % 17 == 0:
+            nb[0] = 0.0
+        ny = float(np.exp(rng.uniform(-30, 2))) if trial % 13 else 0.0
+        for wt in (0, 1):
+            mask = int(rng.integers(0, 16))
+            allowed = [t for t in range(4) if (mask >> t) & 1] if mask else [0, 1, 2, 3]
+            t_lib, u_lib, nu_lib = ps.ps_plan(nb, ny, dtype=wt, mode="mixed", tier_mask=mask)
+            u_o, nu_o, t_o = oplan.plan(nb, ny, working_tier=wt, allowed=allowed)
+            assert t_lib == t_o and nu_lib == nu_o, (nb, ny, wt, mask)
+            assert np.allclose(u_lib, u_o, rtol=1e-15, atol=0) or all(
+                (a == b) for a, b in zip(u_lib, u_o))
+
+
+def test_fixed_mode_plan_is_working_precision(ps):
+    t, u, nu = ps.ps_plan([1.0, 1e-9, 1e-20], 1e-3, mode="fixed")
+    assert t == [0, 0, 0] and nu == 3
+
+
+def test_workspace_sizes(ps):
+    sz = ctypes.c_size_t()
+    L = ps.lib()
+    assert L.ps_workspace_size(0, 1024, 30, 6, 6, ctypes.byref(sz)) == 0
+    n = 1024
+    assert sz.value >= (5 + 5 + 2) * n * n * 8
+    assert sz.value % 256 == 0
+    small = ctypes.c_size_t()
+    assert L.ps_workspace_size(1, 64, 16, 4, 0, ctypes.byref(small)) == 0
+    assert 0 < small.value < sz.value
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(n=0), -1), (dict(m=-1), -1), (dict(s=7, m=5), -1), (dict(sigma=-1), -1), (dict(sigma=501), -1),
+    (dict(lda=3, n=4), -1), (dict(dtype=7), -1), (dict(A=0), -1), (dict(alias=True), -2),
+    (dict(ws_small=True), -3), (dict(ws_misaligned=True), -3), (dict(m=300), -1),
+])
+def test_argument_validation_before_device_work(ps, args, code):
+    L = ps.lib()
+    n = args.get("n", 4)
+    m = args.get("m", 6)
+    s = args.get("s", 0)
+    sigma = args.get("sigma", 0)
+    lda = args.get("lda", n)
+    dtype = args.get("dtype", 0)
+    A = args.get("A", 0x10000000)
+    E = A if args.get("alias") else 0x20000000
+    need = ctypes.c_size_t(1 << 30)
+    ws = 0x40000010 if args.get("ws_misaligned") else 0x40000000
+    wsb = 16 if args.get("ws_small") else (1 << 30)
+    st = L.ps_expm(dtype, n, A, lda, None, m, s, sigma, E, n, None, None, ws, wsb, None)
+    assert st == code, (st, L.ps_last_error())
+    assert L.ps_last_error()
+
+
+def test_unimplemented_entry_points_report_unsupported(ps):
+    L = ps.lib()
+    assert L.ps_batched_launch(None, None) in (-1, -5)

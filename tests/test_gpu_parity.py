@@ -1,0 +1,253 @@
+"""GPU parity of the PS hot path (single matrix, strided batches) against the
+CPU oracle, through the C ABI.
+
+Tolerances: the relative 1-norm error of the paper's experiments
+(section 3.3), bounded by 1e-13 in the FP64 target mode and 1e-6 in the FP32
+target mode (the targets of this implementation); integer and structural
+cases are bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coeffs, metrics
+from oracle import plan as oplan
+from paper_2312_17396_amd import inputs
+
+from helpers import DEV, U32, U64, quantize_operand, relerr_cols, sample_cols, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-13
+TOL32 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import torch
+    import paper_2312_17396_amd as ps
+    ps.lib()
+    assert torch.cuda.is_available()
+    return ps
+
+
+def _rand(n, t, seed):
+    g = np.random.default_rng(seed)
+    G = g.standard_normal((n, n))
+    return G * (t / metrics.norm1(G))
+
+
+# ------------------------------------------------------------ exactness pins
+@pytest.mark.parametrize("seed", range(4))
+def test_integer_data_bit_exact(ps, seed):
+    g = np.random.default_rng(300 + seed)
+    n = int(g.integers(1, 40))
+    m = int(g.integers(1, 9))
+    X = g.integers(-1, 2, (n, n)).astype(np.float64)
+    c = g.integers(-3, 4, m + 1).astype(np.float64)
+    exact = oracle.naive_f64(X, c)           # exact: integers below 2^53 (checked)
+    assert np.max(np.abs(exact)) < 2 ** 52
+    for s in sorted(set([1, max(1, m // 2), ps.default_s(m), m])):
+        P = ps.ps_eval(to_dev(X), c, s=s)
+        assert np.array_equal(to_np(P), exact), (n, m, s)
+
+
+@pytest.mark.parametrize("n", [1, 5, 40, 70])
+def test_jordan_block_exact(ps, n):
+    J = np.diag(np.ones(n - 1), 1) if n > 1 else np.zeros((1, 1))
+    m = 30
+    c = coeffs.taylor_exp(m)
+    P = to_np(ps.ps_expm(to_dev(J), m, s=6, sigma=0))
+    want = np.zeros((n, n))
+    for j in range(min(n, m + 1)):
+        want += np.diag(np.full(n - j, c[j]), j)
+    assert np.array_equal(P, want)
+
+
+def test_upper_triangular_lower_part_exactly_zero(ps):
+    g = np.random.default_rng(7)
+    n = 150
+    T = np.triu(g.standard_normal((n, n))) / 8
+    for mode in ("fixed", "mixed"):
+        E = to_np(ps.ps_expm(to_dev(T), 18, s=5, sigma=1, mode=mode))
+        assert not np.any(np.tril(E, -1)), mode
+        c = coeffs.taylor_exp(18)
+        d = np.diag(T) / 2
+        want = np.polyval(c[::-1], d) ** 2
+        assert np.max(np.abs(np.diag(E) - want) / np.abs(want)) < 1e-13, mode
+
+
+def test_rotation_generator(ps):
+    th = 1.1
+    X = np.array([[0.0, -th], [th, 0.0]])
+    P = to_np(ps.ps_expm(to_dev(X), 30, s=6, sigma=0))
+    assert abs(P[0, 0] - math.cos(th)) < 4e-16 and abs(P[1, 0] - math.sin(th)) < 4e-16
+    assert abs(P[0, 1] + math.sin(th)) < 4e-16
+
+
+# ------------------------------------------------------------ oracle parity
+@pytest.mark.parametrize("n,m,s,sigma,t", [
+    (1, 16, 4, 0, 1.0), (2, 7, 3, 0, 0.5), (17, 16, 4, 0, 1.0), (64, 16, 4, 0, 1.0), (100, 30, 6, 2, 4.0),
+    (130, 13, 4, 0, 1.0), (200, 18, 5, 1, 2.0), (257, 30, 6, 0, 0.1), (96, 12, 1, 0, 0.3), (65, 9, 9, 0, 0.8),
+])
+@pytest.mark.parametrize("mode", ["fixed", "mixed"])
+def test_fp64_vs_oracle_small(ps, n, m, s, sigma, t, mode):
+    A = _rand(n, t, 1000 + n + m)
+    c = coeffs.taylor_exp(m)
+    Eh, El = oracle.expm_dd(A, c, sigma)
+    E, rep = ps.ps_expm(to_dev(A), m, s=s, sigma=sigma, mode=mode, report=True)
+    err = metrics.rel_err_1(to_np(E), Eh, El)
+    assert err <= TOL64, (err, rep["tier"])
+    # plan parity: the oracle's planner on the library's norms gives the same tiers
+    if mode == "mixed" and rep["r"] >= 1:
+        u, nu, tiers = oplan.plan(rep["normB"], rep["normY"], working_tier=0)
+        assert tiers[1:] == rep["tier"][1:]
+
+
+def test_single_64_config(ps):
+    """Taylor m = 16, s = 4, no scaling, one 64x64 matrix with ||A||_1 = 1."""
+    A = inputs.single_64()
+    c = coeffs.taylor_exp(16)
+    Ph, Pl = oracle.poly_dd(A, c)
+    for mode in ("fixed", "mixed"):
+        P = ps.ps_eval(to_dev(A), c, s=4, mode=mode)
+        assert metrics.rel_err_1(to_np(P), Ph, Pl) <= TOL64, mode
+    # Algorithm 1 in double on the CPU lands at the same accuracy level
+    assert metrics.rel_err_1(oracle.ps_f64(A, c, 4), Ph, Pl) <= TOL64
+
+
+def test_norms_match_oracle(ps):
+    """||B_i||_1 and ||X^s||_1 reported by the device assembly agree with the
+    oracle's dd values.  The library works on the column-major view of the
+    row-major tensor, i.e. on A^T, so its 1-norms are those of B_i^T."""
+    n, m, s = 160, 18, 5
+    A = _rand(n, 1.0, 77)
+    c = coeffs.taylor_exp(m)
+    _, rep = ps.ps_expm(to_dev(A), m, s=s, sigma=0, mode="mixed", report=True)
+    r, ranges = oplan.block_bounds(s, m)
+    # direct check on B_i via explicit powers in dd
+    Xp = [oracle.poly_dd(A, [0.0] * j + [1.0]) for j in range(s + 1)]
+    for i in range(r + 1):
+        B = sum(c[k] * (Xp[k - s * i][0] + Xp[k - s * i][1]) for k in ranges[i]).T
+        assert abs(metrics.norm1(B) - rep["normB"][i]) <= 1e-14 * metrics.norm1(B) + 1e-300
+    Y = Xp[s][0].T
+    assert abs(metrics.norm1(Y) - rep["normY"]) <= 1e-14 * metrics.norm1(Y)
+
+
+# ------------------------------------------------------------ per-tier GEMM paths
+@pytest.mark.parametrize("tier", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [33, 128, 300])
+def test_tier_product_matches_format_emulation(ps, tier, n):
+    """p(X) = X^2 with s = 1 is one Horner product P_1 Y with P_1 = Y = X.  Forcing
+    its tier exercises the cast epilogue, the Y copy and that tier's MFMA path;
+    the result must equal the product of the quantised operands up to the
+    accumulation rounding."""
+    g = np.random.default_rng(900 + n + tier)
+    X = g.standard_normal((n, n)) * np.exp2(g.integers(-6, 6, (n, n)))
+    P = to_np(ps.ps_eval(to_dev(X), [0.0, 0.0, 1.0], s=1, mode="mixed", tier_override=[0, tier, tier]))
+    M = X.T                                    # the library's column-major view
+    qa = quantize_operand(M, tier, "A")
+    qb = quantize_operand(M, tier, "B")
+    want = (qa @ qb).T
+    scale = (np.abs(qa) @ np.abs(qb)).T
+    uacc = U64 if tier == 0 else U32
+    # The scaled FP8 MFMA sums each 128-element slab internally before the FP32
+    # accumulate; its observed deviation from an FP32 running sum is ~2^-12 of
+    # sum |a||b| (integer data below shows the formats themselves are exact).
+    tol = 2 * n * uacc * scale if tier < 3 else 2.0 ** -10 * scale
+    assert np.all(np.abs(P - want) <= tol + 1e-300), np.max(np.abs(P - want) / scale)
+
+
+@pytest.mark.parametrize("tier", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [40, 200])
+def test_tier_product_integer_data_bit_exact(ps, tier, n):
+    """Integers in [-8, 8] are exact in every operand format (E4M3 keeps 3
+    fraction bits, so every block scale maps them onto its grid exactly) and
+    the products and sums stay below 2^24: each tier's GEMM path must return
+    X @ X bit for bit."""
+    g = np.random.default_rng(700 + n + tier)
+    X = g.integers(-8, 9, (n, n)).astype(np.float64)
+    P = to_np(ps.ps_eval(to_dev(X), [0.0, 0.0, 1.0], s=1, mode="mixed", tier_override=[0, tier, tier]))
+    assert np.array_equal(P, X @ X)
+
+
+@pytest.mark.parametrize("pattern", [[0, 1, 1, 2, 3], [0, 0, 2, 3, 3], [0, 3, 3, 3, 3], [0, 1, 2, 2, 1]])
+def test_forced_tier_chains_within_bound(ps, pattern):
+    """Horner chains mixing all formats (every producer/consumer format pair)."""
+    n, m, s = 190, 8, 2     # r = 4, s | m: step 4 folded, steps 3..1 are GEMMs
+    A = _rand(n, 1.5, 5)
+    c = coeffs.taylor_exp(m)
+    Ph, Pl = oracle.poly_dd(A, c)
+    P, rep = ps.ps_eval(to_dev(A), c, s=s, mode="mixed", tier_override=pattern, report=True)
+    err = metrics.rel_err_1(to_np(P), Ph, Pl)
+    nb, ny = rep["normB"], rep["normY"]
+    uin = {0: U64, 1: U32, 2: 2.0 ** -8, 3: 2.0 ** -4}
+    bound = 0.0
+    for i in range(1, rep["first_step"] + 1):
+        t = pattern[i]
+        tail = max(nb[j] * ny ** j for j in range(i, len(nb)))
+        bound += (2 * uin[t] + n * (U64 if t == 0 else U32)) * tail
+    bound = 4 * bound / metrics.norm1(Ph) + 1e-13
+    assert err <= bound, (err, bound)
+
+
+# ------------------------------------------------------------ dense n = 1024
+@pytest.mark.parametrize("t", inputs.DENSE_NORMS)
+def test_dense_1024_sampled_columns(ps, t):
+    """||A||_1 in {0.1, 1, 8, 64}, Taylor m = 30, s = 6, sigma = ceil(log2 t):
+    plain and mixed PS agree with the oracle on sampled columns within 1e-13."""
+    A = inputs.dense_1024(t)
+    sigma = inputs.squarings_for(t)
+    c = coeffs.taylor_exp(30)
+    cols = sample_cols(1024, 4 if sigma >= 6 else 6, seed=int(t * 10))
+    V = np.eye(1024)[:, cols]
+    Wh, Wl = oracle.expm_apply_dd(A, c, sigma, V)
+    for mode in ("fixed", "mixed"):
+        E, rep = ps.ps_expm(to_dev(A), 30, s=6, sigma=sigma, mode=mode, report=True)
+        err = relerr_cols(to_np(E)[:, cols], Wh, Wl)
+        print("t=%g mode=%s sigma=%d err=%.3e tiers=%s" % (t, mode, sigma, err, rep["tier"]))
+        assert err <= TOL64, (t, mode, err, rep["tier"])
+        if mode == "mixed":
+            u, nu, tiers = oplan.plan(rep["normB"], rep["normY"], working_tier=0)
+            assert tiers[1:] == rep["tier"][1:]
+
+
+# ------------------------------------------------------------ batches / determinism
+def test_strided_batch_equals_single_calls_bitwise(ps):
+    import torch
+    g = np.random.default_rng(11)
+    n, bsz = 96, 5
+    A = np.stack([_rand(n, float(t), 40 + i) for i, t in enumerate(g.uniform(0.1, 3, bsz))])
+    for mode in ("fixed", "mixed"):
+        E = to_np(ps.ps_expm_strided_batched(to_dev(A), 18, s=5, sigma=2, mode=mode))
+        for b in range(bsz):
+            Eb = to_np(ps.ps_expm(to_dev(A[b]), 18, s=5, sigma=2, mode=mode))
+            assert np.array_equal(E[b], Eb), (mode, b)
+
+
+def test_repeat_runs_bitwise(ps):
+    A = to_dev(_rand(300, 2.0, 3))
+    r1 = to_np(ps.ps_expm(A, 30, s=6, sigma=1, mode="mixed"))
+    r2 = to_np(ps.ps_expm(A, 30, s=6, sigma=1, mode="mixed"))
+    assert np.array_equal(r1, r2)
+
+
+@pytest.mark.parametrize("n,t,sigma", [(64, 1.0, 0), (200, 3.0, 2), (512, 4.0, 2)])
+def test_fp32_target_vs_oracle(ps, n, t, sigma):
+    """FP32 working precision.  Equal accuracy is judged as
+    err_mixed <= max(1e-6, 2 err_plain); plain FP32 PS itself must stay within
+    the normwise bound of the paper's analysis (section 2: about r n u)."""
+    import torch
+    A = _rand(n, t, 500 + n).astype(np.float32).astype(np.float64)
+    c32 = [float(np.float32(x)) for x in coeffs.taylor_exp(18)]
+    cols = sample_cols(n, 6)
+    Wh, Wl = oracle.expm_apply_dd(A, c32, sigma, np.eye(n)[:, cols])
+    errs = {}
+    for mode in ("fixed", "mixed"):
+        E = ps.ps_expm(to_dev(A, torch.float32), 18, s=5, sigma=sigma, mode=mode)
+        errs[mode] = relerr_cols(to_np(E)[:, cols], Wh, Wl)
+    print("n=%d sigma=%d plain %.2e mixed %.2e" % (n, sigma, errs["fixed"], errs["mixed"]))
+    r = 18 // 5
+    assert errs["fixed"] <= 2 ** sigma * r * n * U32
+    assert errs["mixed"] <= max(TOL32, 2 * errs["fixed"]), errs
