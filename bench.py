@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "plain", "both"], default="both",
                     help="restrict the timed modes (profiling runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run three 256 MiB device-to-device copies (known traffic, for counter scaling)")
     return ap.parse_args()
 
 
@@ -108,6 +110,14 @@ def main():
             step(mode)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / args.steps
+
+    if args.calib_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     res = {}
     modes = ["plain", "mixed"] if args.only == "both" else [args.only]

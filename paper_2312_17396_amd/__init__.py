@@ -311,3 +311,96 @@ def ps_expm_strided_batched(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_ma
     if reps is not None:
         return E, [r.to_dict() for r in reps]
     return E
+
+
+def _batch_arrays(mats, s, sigma):
+    k = len(mats)
+    n = (ctypes.c_int32 * k)(*[int(a.shape[0]) for a in mats])
+    sv = None
+    if s is not None:
+        s = [int(s)] * k if not hasattr(s, "__len__") else [int(x) for x in s]
+        sv = (ctypes.c_int32 * k)(*s)
+    sg = [int(sigma)] * k if not hasattr(sigma, "__len__") else [int(x) for x in sigma]
+    sgv = (ctypes.c_int32 * k)(*sg)
+    return n, sv, sgv
+
+
+def batched_workspace_bytes(mats, m, s=None, dtype=None):
+    n, sv, _ = _batch_arrays(mats, s, 0)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_batched(_dtype_code(mats[0]) if dtype is None else dtype, len(mats), n, int(m),
+                                           sv, ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def ps_expm_batched(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
+                    outs=None, workspace=None):
+    """E_b = p(2^-sigma_b A_b)^(2^sigma_b) for a list of square matrices of
+    uneven order (1..256), one persistent launch.  s: None/0 (choose per
+    matrix), an int, or a list; sigma: int or list."""
+    import torch
+    mats = [_check_square(a) for a in mats]
+    k = len(mats)
+    dt = _dtype_code(mats[0])
+    if any(_dtype_code(a) != dt for a in mats):
+        raise PSError("all matrices of a batch must share one dtype")
+    n, sv, sgv = _batch_arrays(mats, s, sigma)
+    if workspace is None:
+        ws, wsp, wsb = _workspace(batched_workspace_bytes(mats, m, s), mats[0].device)
+    else:
+        ws, wsp, wsb = workspace
+    outs = [torch.empty_like(a) for a in mats] if outs is None else outs
+    aptr = (_vp * k)(*[a.data_ptr() for a in mats])
+    eptr = (_vp * k)(*[o.data_ptr() for o in outs])
+    lda = (ctypes.c_int64 * k)(*[a.shape[0] for a in mats])
+    o, _k = _opts(mode, tier_mask, delta)
+    tiers = (ctypes.c_int32 * (k * MAX_BLOCKS))() if report else None
+    c = _darr(coef) if coef is not None else None
+    _check(lib().ps_expm_batched(dt, k, n, aptr, lda, c, int(m), sv, sgv, eptr, lda, ctypes.byref(o), tiers,
+                                 wsp, wsb, _stream_ptr(mats[0].device)))
+    if report:
+        reps = []
+        for b in range(k):
+            row = list(tiers[b * MAX_BLOCKS:(b + 1) * MAX_BLOCKS])
+            reps.append({"s": row[-1], "tier": [t for t in row[:-1] if t >= 0]})
+        return outs, reps
+    return outs
+
+
+class BatchedGraph:
+    """A captured hipGraph of one batched evaluation (ps_batched_prepare);
+    launch() replays it on the current stream.  The input and output tensors
+    are held so their memory stays valid for every replay."""
+
+    def __init__(self, mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0):
+        import torch
+        self.mats = [_check_square(a) for a in mats]
+        k = len(self.mats)
+        dt = _dtype_code(self.mats[0])
+        n, sv, sgv = _batch_arrays(self.mats, s, sigma)
+        self.ws = _workspace(batched_workspace_bytes(self.mats, m, s), self.mats[0].device)
+        self.outs = [torch.empty_like(a) for a in self.mats]
+        aptr = (_vp * k)(*[a.data_ptr() for a in self.mats])
+        eptr = (_vp * k)(*[o.data_ptr() for o in self.outs])
+        lda = (ctypes.c_int64 * k)(*[a.shape[0] for a in self.mats])
+        o, _k = _opts(mode, tier_mask, delta)
+        c = _darr(coef) if coef is not None else None
+        h = ctypes.c_void_p()
+        _check(lib().ps_batched_prepare(dt, k, n, aptr, lda, c, int(m), sv, sgv, eptr, lda, ctypes.byref(o),
+                                        self.ws[1], self.ws[2], _stream_ptr(self.mats[0].device), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self):
+        _check(lib().ps_batched_launch(self.handle, _stream_ptr(self.mats[0].device)))
+        return self.outs
+
+    def close(self):
+        if self.handle:
+            lib().ps_batched_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

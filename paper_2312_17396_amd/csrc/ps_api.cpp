@@ -369,6 +369,11 @@ ps_status fill_report(const Layout& L, const Job& J, int b, ps_report* rep, hipS
 
 }  // namespace
 
+ps_status ps_set_error(ps_status st, const char* msg) {
+  g_last_error = msg ? msg : "";
+  return st;
+}
+
 // ===========================================================================
 // exported entry points
 // ===========================================================================

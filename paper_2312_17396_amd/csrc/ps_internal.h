@@ -58,6 +58,13 @@ struct Layout {
 
 Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg);
 
+}  // namespace psk
+
+// Records `msg` as the thread's last error (ps_last_error) and returns st.
+ps_status ps_set_error(ps_status st, const char* msg);
+
+namespace psk {
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in ps_kernels.hip).  All take a batch of matrices
 // addressed as base + b * stride (strides in bytes for workspace pointers, in

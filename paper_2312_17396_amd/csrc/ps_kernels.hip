@@ -27,234 +27,12 @@
 //   operands (f64, f32, bf16): lane l holds A[l%16][kb + e] and
 //   B[kb + e][l%16] with kb = (l/16) * (K/4), e over K/4 consecutive elements;
 //   f8f6f4 16x16x128 interleaves K and its scales, see mainloop_fp8.
-#include <hip/hip_runtime.h>
-#include <type_traits>
-
-#include "ps_internal.h"
-#include "ps_planner.h"
+#include "ps_device.h"
 
 namespace psk {
 
-typedef double d4v __attribute__((ext_vector_type(4)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
-typedef int i8v __attribute__((ext_vector_type(8)));
-
-constexpr int NT = 256;
-constexpr int BKL = 32;               // K slab of the LDS main loop
-constexpr int LROW = kTile + 16;      // padded LDS row (elements): 2 half-wave passes hit disjoint banks
-constexpr int CSTR = kTile + 1;       // epilogue tile column stride (elements)
-constexpr int SLAB = BKL * LROW;      // elements of one operand slab in LDS
-constexpr int SMEM_BYTES = 4 * SLAB * 8;   // 80 KiB: two stages of A and B slabs (FP64)
-
 // ---------------------------------------------------------------------------
-// tile scheduling: workgroups are dispatched round-robin over the 8 XCDs; each
-// XCD is given a contiguous range of tiles, walked in groups of 4 tile-rows,
-// so the workgroups sharing an L2 also share A row panels and B column panels.
-// ---------------------------------------------------------------------------
-__device__ inline void tile_of_block(int nt, int& tm, int& tn) {
-  const int total = nt * nt;
-  int bid = blockIdx.x;
-  int t = bid;
-  if ((total & 7) == 0) t = (bid & 7) * (total >> 3) + (bid >> 3);
-  const int GM = 4;
-  const int per_group = GM * nt;
-  const int group = t / per_group;
-  const int first = group * GM;
-  const int gsize = min(nt - first, GM);
-  const int local = t - group * per_group;
-  tm = first + local % gsize;
-  tn = local / gsize;
-}
-
-template <typename T> struct MF;
-template <> struct MF<double> {
-  typedef d4v V;
-  static __device__ inline V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int v, int g) { return 4 * v + g; }
-};
-template <> struct MF<float> {
-  typedef f4v V;
-  static __device__ inline V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int v, int g) { return 4 * g + v; }
-};
-
-// ---- global -> register slab loads.  Each thread moves 8 consecutive
-// elements (a contiguous run in memory) of the 64 x BKL A slab and of the
-// BKL x 64 B slab; runs that are fully in bounds and 16-byte aligned use
-// vector loads, the rest are guarded element loads (zero fill).
-template <typename T>
-__device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim, T r[8]) {
-  if (full && (((uintptr_t)p) & 15) == 0) {
-    typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int W = 16 / sizeof(T);
-#pragma unroll
-    for (int i = 0; i < 8; i += W) {
-      v2 x = *(const v2*)(p + i);
-#pragma unroll
-      for (int j = 0; j < W; ++j) r[i + j] = x[j];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = (i < lim) ? p[i] : T(0);
-  }
-}
-// A(m,k): TA = false -> A[m + k lda] (run along m), true -> A[k + m lda] (run along k)
-template <typename T, bool TA>
-__device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, int64_t m0, int64_t k0, int t, T r[8]) {
-  if (!TA) {
-    const int kk = t >> 3, mm = (t & 7) * 8;
-    const int64_t k = k0 + kk, m = m0 + mm;
-    const int64_t lim = (k < n) ? min<int64_t>(8, n - m) : 0;
-    load_run<T>(A + m + k * lda, lim >= 8, lim, r);
-  } else {
-    const int mm = t >> 2, kk = (t & 3) * 8;
-    const int64_t m = m0 + mm, k = k0 + kk;
-    const int64_t lim = (m < n) ? min<int64_t>(8, n - k) : 0;
-    load_run<T>(A + k + m * lda, lim >= 8, lim, r);
-  }
-}
-template <typename T, bool TA>
-__device__ inline void store_a(T* As, int t, const T r[8]) {
-  if (!TA) {
-    const int kk = t >> 3, mm = (t & 7) * 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) As[kk * LROW + mm + i] = r[i];
-  } else {
-    const int mm = t >> 2, kk = (t & 3) * 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) As[(kk + i) * LROW + mm] = r[i];
-  }
-}
-// B(k,j): TB = false -> B[k + j ldb] (run along k), true -> B[j + k ldb] (run along j)
-template <typename T, bool TB>
-__device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, int64_t n0, int64_t k0, int t, T r[8]) {
-  if (!TB) {
-    const int jj = t >> 2, kk = (t & 3) * 8;
-    const int64_t j = n0 + jj, k = k0 + kk;
-    const int64_t lim = (j < n) ? min<int64_t>(8, n - k) : 0;
-    load_run<T>(B + k + j * ldb, lim >= 8, lim, r);
-  } else {
-    const int kk = t >> 3, jj = (t & 7) * 8;
-    const int64_t k = k0 + kk, j = n0 + jj;
-    const int64_t lim = (k < n) ? min<int64_t>(8, n - j) : 0;
-    load_run<T>(B + j + k * ldb, lim >= 8, lim, r);
-  }
-}
-template <typename T, bool TB>
-__device__ inline void store_b(T* Bs, int t, const T r[8]) {
-  if (!TB) {
-    const int jj = t >> 2, kk = (t & 3) * 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) Bs[(kk + i) * LROW + jj] = r[i];
-  } else {
-    const int kk = t >> 3, jj = (t & 7) * 8;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) Bs[kk * LROW + jj + i] = r[i];
-  }
-}
-
-template <typename T>
-__device__ inline void mma_slab(const T* as, const T* bs, int wr, int wc, int g, int c, typename MF<T>::V acc[4]) {
-#pragma unroll
-  for (int ks = 0; ks < BKL / 4; ++ks) {
-    const int k = ks * 4 + g;
-    const T a0 = as[k * LROW + wr + c], a1 = as[k * LROW + wr + 16 + c];
-    const T b0 = bs[k * LROW + wc + c], b1 = bs[k * LROW + wc + 16 + c];
-    acc[0] = MF<T>::mma(a0, b0, acc[0]);
-    acc[1] = MF<T>::mma(a0, b1, acc[1]);
-    acc[2] = MF<T>::mma(a1, b0, acc[2]);
-    acc[3] = MF<T>::mma(a1, b1, acc[3]);
-  }
-}
-
-// ---- FP64 / FP32 main loop: acc[2*bi+bj] += A-tile x B-tile over all of K.
-// Two LDS stages; global loads run two slabs ahead of the MFMAs (register
-// sets R0/R1 alternate, loop unrolled by two), so each load has two slabs of
-// MFMA work to complete before its data is stored to LDS.
-template <typename T, bool TA, bool TB>
-__device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
-                                    int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[4]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-  T* As[2] = {(T*)smem, (T*)smem + 2 * SLAB};
-  T* Bs[2] = {(T*)smem + SLAB, (T*)smem + 3 * SLAB};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = typename MF<T>::V{0, 0, 0, 0};
-  const int64_t nk = (n + BKL - 1) / BKL;
-  T ra0[8], rb0[8], ra1[8], rb1[8];
-  // prologue: slab 0 -> LDS stage 0, slab 1 -> registers set 1
-  load_a<T, TA>(A, lda, n, m0, 0, t, ra0);
-  load_b<T, TB>(B, ldb, n, n0, 0, t, rb0);
-  if (nk > 1) {
-    load_a<T, TA>(A, lda, n, m0, BKL, t, ra1);
-    load_b<T, TB>(B, ldb, n, n0, BKL, t, rb1);
-  }
-  store_a<T, TA>(As[0], t, ra0);
-  store_b<T, TB>(Bs[0], t, rb0);
-  __syncthreads();
-  for (int64_t kt = 0; kt < nk; kt += 2) {
-    // even slab kt in stage 0; registers set 1 holds slab kt+1
-    if (kt + 2 < nk) {
-      load_a<T, TA>(A, lda, n, m0, (kt + 2) * BKL, t, ra0);
-      load_b<T, TB>(B, ldb, n, n0, (kt + 2) * BKL, t, rb0);
-    }
-    mma_slab<T>(As[0], Bs[0], wr, wc, g, c, acc);
-    if (kt + 1 < nk) {
-      store_a<T, TA>(As[1], t, ra1);
-      store_b<T, TB>(Bs[1], t, rb1);
-    }
-    __syncthreads();
-    if (kt + 1 >= nk) break;
-    // odd slab kt+1 in stage 1; registers set 0 holds slab kt+2
-    if (kt + 3 < nk) {
-      load_a<T, TA>(A, lda, n, m0, (kt + 3) * BKL, t, ra1);
-      load_b<T, TB>(B, ldb, n, n0, (kt + 3) * BKL, t, rb1);
-    }
-    mma_slab<T>(As[1], Bs[1], wr, wc, g, c, acc);
-    if (kt + 2 < nk) {
-      store_a<T, TA>(As[0], t, ra0);
-      store_b<T, TB>(Bs[0], t, rb0);
-    }
-    __syncthreads();
-  }
-}
-
-// accumulator fragments -> LDS tile Cs[col * CSTR + row] (type W)
-template <typename T, typename W>
-__device__ inline void frag_to_cs(const typename MF<T>::V acc[4], W* Cs, double scale) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr + 16 * bi + MF<T>::row(v, g);
-        const int col = wc + 16 * bj + c;
-        Cs[col * CSTR + row] = (W)((double)acc[bi * 2 + bj][v] * scale);
-      }
-}
-
-__device__ inline void frag_f32_to_cs_any(const f4v acc[4], double* Csd, float* Csf, bool isd) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr + 16 * bi + 4 * g + v;
-        const int col = wc + 16 * bj + c;
-        if (isd) Csd[col * CSTR + row] = (double)acc[bi * 2 + bj][v];
-        else Csf[col * CSTR + row] = acc[bi * 2 + bj][v];
-      }
-}
-
-// ---------------------------------------------------------------------------
-// k_gemm
+// k_gemm: one 64x64 tile per workgroup
 // ---------------------------------------------------------------------------
 template <typename T, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void k_gemm(int64_t n, MatArg A, MatArg B, MatArg C, double alpha, int accumulate) {
@@ -262,30 +40,10 @@ __global__ __launch_bounds__(NT) void k_gemm(int64_t n, MatArg A, MatArg B, MatA
   const int nt = (int)((n + kTile - 1) / kTile);
   int tm, tn;
   tile_of_block(nt, tm, tn);
-  const int64_t m0 = (int64_t)tm * kTile, n0 = (int64_t)tn * kTile;
   const int64_t b = blockIdx.z;
-  const T* Ap = (const T*)A.p + b * A.stride;
-  const T* Bp = (const T*)B.p + b * B.stride;
-  T* Cp = (T*)C.p + b * C.stride;
-  typename MF<T>::V acc[4];
-  mainloop_lds<T, TA, TB>(Ap, A.ld, Bp, B.ld, n, m0, n0, smem, acc);
-  T* Cs = (T*)smem;
-  frag_to_cs<T, T>(acc, Cs, 1.0);
-  __syncthreads();
-  const int t = threadIdx.x;
-  const int row = t & 63;
-  const int64_t gr = m0 + row;
-#pragma unroll 4
-  for (int q = 0; q < 16; ++q) {
-    const int col = (t >> 6) + 4 * q;
-    const int64_t gc = n0 + col;
-    if (gr < n && gc < n) {
-      const T v = (T)(alpha * (double)Cs[col * CSTR + row]);
-      T* dst = Cp + gr + gc * C.ld;
-      if (accumulate) *dst = *dst + v;
-      else *dst = v;
-    }
-  }
+  gemm_tile<T, TA, TB>((const T*)A.p + b * A.stride, A.ld, (const T*)B.p + b * B.stride, B.ld,
+                       (T*)C.p + b * C.stride, C.ld, n, (int64_t)tm * kTile, (int64_t)tn * kTile, alpha, accumulate,
+                       smem);
 }
 
 hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, MatArg B, int transB,
@@ -310,212 +68,38 @@ hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, 
 }
 
 // ---------------------------------------------------------------------------
-// low-precision main loops (operands packed K-contiguous, zero-masked past n)
-// ---------------------------------------------------------------------------
-__device__ inline uint16_t bf16_bits_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-// P: row-major [Mp][Kp] bf16 bits; Yb: [Np][Kp] (column j of Y contiguous in k)
-__device__ inline void mainloop_bf16(const uint16_t* __restrict__ P, const uint16_t* __restrict__ Yb, int64_t Kp,
-                                     int64_t n, int64_t m0, int64_t n0, f4v acc[4]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = f4v{0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < n; k0 += 32) {
-    const int64_t kb = k0 + 8 * g;
-    union U { uint4 q; uint16_t h[8]; bf8v v; } a[2], bb[2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi) a[bi].q = *(const uint4*)(P + (m0 + wr + 16 * bi + c) * Kp + kb);
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) bb[bj].q = *(const uint4*)(Yb + (n0 + wc + 16 * bj + c) * Kp + kb);
-    if (kb + 8 > n) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (kb + e >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb[0].h[e] = 0; bb[1].h[e] = 0; }
-    }
-    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0].v, bb[0].v, acc[0], 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0].v, bb[1].v, acc[1], 0, 0, 0);
-    acc[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1].v, bb[0].v, acc[2], 0, 0, 0);
-    acc[3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1].v, bb[1].v, acc[3], 0, 0, 0);
-  }
-}
-
-// P8: [Mp][Kp] E4M3 bytes, Ps: [Mp][Kp/32] E8M0 scales; Y8, Ys likewise per column.
-// The scaled f8f6f4 16x16x128 MFMA orders K inside a 128-slab as: lane group
-// g = l/16 holds slab elements [16g, 16g+16) in bytes 0..15 and
-// [64+16g, 64+16g+16) in bytes 16..31, and the E8M0 scale of the 32-element
-// slab block b of row (column) l%16 is the one passed by lane l%16 + 16b.
-// Loading each lane's halves from those two offsets makes every hardware
-// scale block coincide with one 32-element block of the packed layout.
-__device__ inline void mainloop_fp8(const uint8_t* __restrict__ P8, const uint8_t* __restrict__ Ps,
-                                    const uint8_t* __restrict__ Y8, const uint8_t* __restrict__ Ys, int64_t Kp,
-                                    int64_t n, int64_t m0, int64_t n0, f4v acc[4]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-  const int64_t Ks = Kp / 32;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = f4v{0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < n; k0 += 128) {
-    const int64_t klo = k0 + 16 * g;        // bytes 0..15
-    const int64_t khi = k0 + 64 + 16 * g;   // bytes 16..31
-    const int64_t kblk = k0 / 32 + g;       // scale block this lane supplies
-    union U { uint4 q[2]; uint8_t h[32]; i8v v; } a[2], bb[2];
-    int sa[2], sb[2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      const int64_t r = m0 + wr + 16 * bi + c;
-      a[bi].q[0] = *(const uint4*)(P8 + r * Kp + klo);
-      a[bi].q[1] = *(const uint4*)(P8 + r * Kp + khi);
-      sa[bi] = Ps[r * Ks + kblk];
-    }
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int64_t col = n0 + wc + 16 * bj + c;
-      bb[bj].q[0] = *(const uint4*)(Y8 + col * Kp + klo);
-      bb[bj].q[1] = *(const uint4*)(Y8 + col * Kp + khi);
-      sb[bj] = Ys[col * Ks + kblk];
-    }
-    if (k0 + 128 > n) {
-      if (kblk * 32 >= n) { sa[0] = sa[1] = sb[0] = sb[1] = 127; }
-#pragma unroll
-      for (int e = 0; e < 32; ++e) {
-        const int64_t k = (e < 16) ? klo + e : khi + (e - 16);
-        if (k >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb[0].h[e] = 0; bb[1].h[e] = 0; }
-      }
-    }
-    acc[0] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0].v, bb[0].v, acc[0], 0, 0, 0, sa[0], 0, sb[0]);
-    acc[1] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0].v, bb[1].v, acc[1], 0, 0, 0, sa[0], 0, sb[1]);
-    acc[2] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1].v, bb[0].v, acc[2], 0, 0, 0, sa[1], 0, sb[0]);
-    acc[3] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1].v, bb[1].v, acc[3], 0, 0, 0, sa[1], 0, sb[1]);
-  }
-}
-
-// E4M3 quantisation of 32 floats with a shared power-of-two scale (E8M0).
-// amax = f 2^e with f in [0.5,1): scaled values lie in (-256, 256), inside the
-// E4M3 range (max 448); conversion is round-to-nearest-even.
-__device__ inline int e8m0_for(float amax) {
-  if (!(amax > 0.0f) || !(amax < INFINITY)) return 127;
-  int e;
-  frexpf(amax, &e);
-  int se = e - 8;
-  se = max(-127, min(127, se));
-  return se + 127;
-}
-__device__ inline uint32_t pack4_e4m3(float a, float b, float c, float d) {
-  const float L = 448.0f;
-  a = fminf(fmaxf(a, -L), L); b = fminf(fmaxf(b, -L), L);
-  c = fminf(fmaxf(c, -L), L); d = fminf(fmaxf(d, -L), L);
-  int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
-  w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
-  return (uint32_t)w;
-}
-
-// ---------------------------------------------------------------------------
-// k_horner
+// k_horner: one tile of one Horner step per workgroup
 // ---------------------------------------------------------------------------
 template <typename W>
 __global__ __launch_bounds__(NT) void k_horner(HornerArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
-  constexpr int WT = std::is_same<W, double>::value ? 0 : 1;   // working tier
+  constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   const Layout& L = a.L;
-  const int64_t n = a.n;
-  const int nt = (int)((n + kTile - 1) / kTile);
+  const int nt = (int)((a.n + kTile - 1) / kTile);
   int tm, tn;
   tile_of_block(nt, tm, tn);
-  const int64_t m0 = (int64_t)tm * kTile, n0 = (int64_t)tn * kTile;
   const int64_t b = blockIdx.z;
   char* ws = a.ws + b * a.ws_stride;
   const Plan* plan = (const Plan*)(ws + L.off_plan);
-  const int t_in = a.cast_only ? -1 : plan->tier[a.step];
-  const int t_out = a.final_out ? WT : plan->tier[a.cast_only ? a.step : a.step - 1];
-  const int64_t Kp = L.Kp;
-  const char* pin = ws + a.off_pin;
-  W* Cs = (W*)smem;
-
-  if (t_in == WT) {
-    const W* Y = (const W*)a.ysrc.p + b * a.ysrc.stride;
-    typename MF<W>::V acc[4];
-    mainloop_lds<W, false, false>((const W*)pin, n, Y, a.ysrc.ld, n, m0, n0, smem, acc);
-    frag_to_cs<W, W>(acc, Cs, a.yscale);
-  } else if (t_in == 1) {   // FP32 product below an FP64 working precision
-    const float* Y = (const float*)(ws + L.off_yf32);
-    typename MF<float>::V acc[4];
-    mainloop_lds<float, false, false>((const float*)pin, n, Y, n, n, m0, n0, smem, acc);
-    frag_to_cs<float, W>(acc, Cs, 1.0);
-  } else if (t_in == 2) {
-    f4v acc[4];
-    mainloop_bf16((const uint16_t*)pin, (const uint16_t*)(ws + L.off_ybf16), Kp, n, m0, n0, acc);
-    frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
-  } else if (t_in == 3) {
-    f4v acc[4];
-    const int64_t Mp = L.Mp;
-    mainloop_fp8((const uint8_t*)pin, (const uint8_t*)pin + Mp * Kp, (const uint8_t*)(ws + L.off_yfp8),
-                 (const uint8_t*)(ws + L.off_yfp8s), Kp, n, m0, n0, acc);
-    frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
-  }
-  __syncthreads();
-
-  // pass 1 (column-major, coalesced): add B_{i-1} in the precision of tier(i-1)
-  const int t = threadIdx.x;
-  const int row = t & 63;
-  const int64_t gr = m0 + row;
-  const W* Bsrc = (const W*)(ws + a.off_bsrc);
-  char* pout = ws + a.off_pout;
-  W* outw = a.final_out ? ((W*)a.out.p + b * a.out.stride) : (W*)pout;
-  const int64_t ldo = a.final_out ? a.out.ld : n;
-  for (int q = 0; q < 16; ++q) {
-    const int col = (t >> 6) + 4 * q;
-    const int64_t gc = n0 + col;
-    const bool in = gr < n && gc < n;
-    const W v = (t_in < 0) ? W(0) : Cs[col * CSTR + row];
-    const W bb = in ? Bsrc[gr + gc * n] : W(0);
-    if (t_out == WT) {
-      if (in) outw[gr + gc * ldo] = bb + v;
-    } else if (t_out == 1) {
-      if (in) ((float*)pout)[gr + gc * n] = (float)bb + (float)v;
-    } else {
-      Cs[col * CSTR + row] = in ? (W)((float)bb + (float)v) : W(0);
-    }
-  }
-  if (t_out < 2) return;
-  __syncthreads();
-  // pass 2 (row-major): pack into the K-contiguous low-precision layout
-  if (t_out == 2) {
-    const int r = t >> 2, seg = (t & 3) * 16;
-    union { uint4 q[2]; uint16_t h[16]; } o;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) o.h[e] = bf16_bits_rne((float)Cs[(seg + e) * CSTR + r]);
-    uint4* dst = (uint4*)((uint16_t*)pout + (m0 + r) * Kp + n0 + seg);
-    dst[0] = o.q[0];
-    dst[1] = o.q[1];
-  } else if (t < 128) {
-    const int r = t >> 1, blk = t & 1;
-    float vals[32];
-    float amax = 0.0f;
-#pragma unroll
-    for (int e = 0; e < 32; ++e) {
-      vals[e] = (float)Cs[(32 * blk + e) * CSTR + r];
-      amax = fmaxf(amax, fabsf(vals[e]));
-    }
-    const int sbyte = e8m0_for(amax);
-    const int sexp = sbyte - 127;
-    union { uint4 q[2]; uint32_t wv[8]; } o;
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      o.wv[e] = pack4_e4m3(ldexpf(vals[4 * e], -sexp), ldexpf(vals[4 * e + 1], -sexp),
-                           ldexpf(vals[4 * e + 2], -sexp), ldexpf(vals[4 * e + 3], -sexp));
-    const int64_t Mp = L.Mp;
-    uint8_t* p8 = (uint8_t*)pout;
-    uint4* dst = (uint4*)(p8 + (m0 + r) * Kp + n0 + 32 * blk);
-    dst[0] = o.q[0];
-    dst[1] = o.q[1];
-    p8[Mp * Kp + (m0 + r) * (Kp / 32) + n0 / 32 + blk] = (uint8_t)sbyte;
-  }
+  HornerTile<W> h;
+  h.n = a.n;
+  h.Mp = L.Mp;
+  h.Kp = L.Kp;
+  h.t_in = a.cast_only ? -1 : plan->tier[a.step];
+  h.t_out = a.final_out ? WT : plan->tier[a.cast_only ? a.step : a.step - 1];
+  h.pin = ws + a.off_pin;
+  h.ysrc = (const W*)a.ysrc.p + b * a.ysrc.stride;
+  h.ldy = a.ysrc.ld;
+  h.yscale = a.yscale;
+  h.yf32 = (const float*)(ws + L.off_yf32);
+  h.ybf16 = (const uint16_t*)(ws + L.off_ybf16);
+  h.yfp8 = (const uint8_t*)(ws + L.off_yfp8);
+  h.yfp8s = (const uint8_t*)(ws + L.off_yfp8s);
+  h.bsrc = (const W*)(ws + a.off_bsrc);
+  h.pout = ws + a.off_pout;
+  h.outw = a.final_out ? ((W*)a.out.p + b * a.out.stride) : (W*)(ws + a.off_pout);
+  h.ldo = a.final_out ? a.out.ld : a.n;
+  horner_tile<W>(h, (int64_t)tm * kTile, (int64_t)tn * kTile, smem);
 }
 
 hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_t st) {
@@ -527,109 +111,17 @@ hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// k_assemble: one wave per column
+// k_assemble: one wave per (column, row chunk)
 // ---------------------------------------------------------------------------
 template <typename W>
 __global__ __launch_bounds__(NT) void k_assemble(AssembleArgs a, Coefs cf) {
-  const Layout& L = a.L;
-  const int64_t n = a.n;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
   const int64_t col = (int64_t)blockIdx.x * 4 + w;
-  if (col >= n) return;  // no block-wide synchronisation below
+  if (col >= a.n) return;  // no block-wide synchronisation below
   const int64_t b = blockIdx.z;
   char* ws = a.ws + b * a.ws_stride;
   const W* X1 = (const W*)a.X1.p + b * a.X1.stride;
-  const int64_t se = (int64_t)(L.slot / sizeof(W));
-  const W* pw = (const W*)(ws + L.off_pow) + (L.square_arg ? se : 0);  // X_2 .. X_s
-  W* Bm = (W*)(ws + L.off_B);
-  double* colsum = (double*)(ws + L.off_colsum);
-  const int s = a.s, r = a.r, m = a.m, nB = a.nB;
-  const double x1s = a.x1_scale;
-  const bool want32 = std::is_same<W, double>::value && ((a.tier_mask >> 1) & 1u);
-  const bool want16 = (a.tier_mask >> 2) & 1u;
-  const bool want8 = (a.tier_mask >> 3) & 1u;
-  const int64_t Kp = L.Kp, Ks = Kp / 32;
-  float* yf32 = (float*)(ws + L.off_yf32);
-  uint16_t* ybf = (uint16_t*)(ws + L.off_ybf16);
-  uint8_t* y8 = (uint8_t*)(ws + L.off_yfp8);
-  uint8_t* y8s = (uint8_t*)(ws + L.off_yfp8s);
-
-  // this wave's rows: one chunk of kRowChunk rows of column `col`
-  const int64_t r_begin = (int64_t)blockIdx.y * kRowChunk;
-  const int64_t r_end = min<int64_t>(n, r_begin + kRowChunk);
-  const int64_t r_stop = r_begin + round_up(r_end - r_begin, 64);   // all lanes step together
-  const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
-  double ysum = 0.0;
-  // blocks in chunks of 8 so their running column sums stay in registers
-  for (int i0 = 0; i0 < nB; i0 += 8) {
-    double bsum[8];
-#pragma unroll
-    for (int ii = 0; ii < 8; ++ii) bsum[ii] = 0.0;
-    for (int64_t rw = r_begin + lane; rw < r_stop; rw += 64) {
-      const bool valid = rw < r_end;
-      W y = W(0);
-      if (valid) {
-        if (s == 1) y = (W)(x1s * (double)X1[rw + col * a.X1.ld]);
-        else y = pw[(int64_t)(s - 2) * se + rw + col * n];
-      }
-      if (i0 == 0) {
-        // Y statistics and copies (first chunk of blocks only)
-        ysum += fabs((double)y);
-        if (valid && want32) yf32[rw + col * n] = (float)y;
-        if (valid && want16) ybf[col * Kp + rw] = bf16_bits_rne((float)y);
-        if (want8) {
-          float av = fabsf((float)y);
-#pragma unroll
-          for (int off = 16; off >= 1; off >>= 1) av = fmaxf(av, __shfl_xor(av, off, 64));
-          const int sbyte = e8m0_for(av);
-          if (valid) {
-            float q = ldexpf((float)y, -(sbyte - 127));
-            q = fminf(fmaxf(q, -448.0f), 448.0f);
-            const int wv = __builtin_amdgcn_cvt_pk_fp8_f32(q, 0.0f, 0, false);
-            y8[col * Kp + rw] = (uint8_t)(wv & 0xff);
-          }
-          if ((rw & 31) == 0) y8s[col * Ks + rw / 32] = (uint8_t)sbyte;
-        }
-      }
-      if (!valid) continue;
-      W bv[8];
-#pragma unroll
-      for (int ii = 0; ii < 8; ++ii) {
-        const int i = i0 + ii;
-        bv[ii] = W(0);
-        if (i < nB && s * i <= m) bv[ii] = (rw == col) ? (W)cf.c[s * i] : W(0);
-      }
-      for (int j = 1; j < s; ++j) {
-        W xj;
-        if (j == 1) xj = (W)(x1s * (double)X1[rw + col * a.X1.ld]);
-        else xj = pw[(int64_t)(j - 2) * se + rw + col * n];
-#pragma unroll
-        for (int ii = 0; ii < 8; ++ii) {
-          const int k = s * (i0 + ii) + j;
-          if (i0 + ii < nB && k <= m) bv[ii] += (W)cf.c[k] * xj;
-        }
-      }
-#pragma unroll
-      for (int ii = 0; ii < 8; ++ii) {
-        const int i = i0 + ii;
-        if (i < nB) {
-          bsum[ii] += fabs((double)bv[ii]);
-          W outv = bv[ii];
-          if (a.trivial_last && i == r - 1) outv += (W)cf.c[m] * y;   // step r: c_m I * Y
-          Bm[(int64_t)i * se + rw + col * n] = outv;
-        }
-      }
-    }
-#pragma unroll
-    for (int ii = 0; ii < 8; ++ii) {
-      double v = bsum[ii];
-      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0 && i0 + ii < nB) colsum[((int64_t)(i0 + ii) * nch + blockIdx.y) * n + col] = v;
-    }
-  }
-  double v = ysum;
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (lane == 0) colsum[((int64_t)nB * nch + blockIdx.y) * n + col] = v;
+  assemble_column<W>(a, cf, ws, X1, col, blockIdx.y);
 }
 
 hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, int batch, hipStream_t st) {
@@ -645,54 +137,8 @@ hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, i
 __global__ __launch_bounds__(NT) void k_plan(PlanArgs a) {
   __shared__ double red[NT];
   __shared__ double norms[PS_MAX_BLOCKS + 1];
-  const Layout& L = a.L;
-  const int64_t n = L.n;
   char* ws = a.ws + (int64_t)blockIdx.x * a.ws_stride;
-  const double* colsum = (const double*)(ws + L.off_colsum);
-  const int t = threadIdx.x;
-  const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
-  for (int i = 0; i <= a.nB; ++i) {
-    double mx = 0.0;
-    for (int64_t c = t; c < n; c += NT) {
-      double v = 0.0;
-      for (int64_t ch = 0; ch < nch; ++ch) v += colsum[((int64_t)i * nch + ch) * n + c];
-      if (v > mx || v != v) mx = v;
-    }
-    red[t] = mx;
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-      if (t < h) {
-        const double o = red[t + h];
-        if (o > red[t] || o != o) red[t] = o;
-      }
-      __syncthreads();
-    }
-    if (t == 0) norms[i] = red[0];
-    __syncthreads();
-  }
-  if (t != 0) return;
-  Plan* P = (Plan*)(ws + L.off_plan);
-  double nb[PS_MAX_BLOCKS];
-  for (int i = 0; i < a.nB; ++i) nb[i] = norms[i];
-  if (a.trivial_last) nb[a.r] = a.abs_cm;
-  const double ny = norms[a.nB];
-  for (int i = 0; i <= a.r; ++i) P->normB[i] = nb[i];
-  P->normY = ny;
-  if (a.use_override) {
-    for (int i = 0; i <= a.r; ++i) {
-      P->tier[i] = (i == 0) ? a.working : a.override_tier[i];
-      P->u[i] = tier_unit_roundoff(P->tier[i]);
-    }
-    P->nu = a.r + 1;
-    for (int i = 1; i <= a.r; ++i) if (P->tier[i] != a.working) { P->nu = i; break; }
-  } else if (a.mode == PS_MODE_FIXED) {
-    for (int i = 0; i <= a.r; ++i) { P->tier[i] = a.working; P->u[i] = tier_unit_roundoff(a.working); }
-    P->nu = a.r + 1;
-  } else {
-    int nu;
-    plan_tiers(a.r, nb, ny, a.working, a.mask, a.delta, P->tier, P->u, &nu);
-    P->nu = nu;
-  }
+  plan_matrix(a, a.L, ws, red, norms);
 }
 
 hipError_t launch_plan(const PlanArgs& a, int batch, hipStream_t st) {
