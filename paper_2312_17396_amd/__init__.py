@@ -404,3 +404,65 @@ class BatchedGraph:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+def ps_expm_backward(A, G, m, s=0, sigma=0, coef=None, recompute=False):
+    """gradA = d<G, r(A)>/dA for r(A) = p(2^-sigma A)^(2^sigma) (the Frechet
+    derivative L_r(A^T, G)); A and G of shape (n, n) or (batch, n, n)."""
+    import torch
+    squeeze = A.dim() == 2
+    A3 = (A.unsqueeze(0) if squeeze else A).contiguous()
+    G3 = (G.unsqueeze(0) if squeeze else G).contiguous().to(A3.dtype)
+    if A3.dim() != 3 or A3.shape[1] != A3.shape[2] or G3.shape != A3.shape:
+        raise PSError("A and G must be (n, n) or (batch, n, n) of the same shape")
+    bsz, n = A3.shape[0], A3.shape[1]
+    dt = _dtype_code(A3)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_backward(dt, bsz, n, int(m), int(s), int(sigma), int(bool(recompute)),
+                                            ctypes.byref(nbytes)))
+    ws, wsp, wsb = _workspace(nbytes.value, A3.device)
+    gA = torch.empty_like(A3)
+    c = _darr(coef) if coef is not None else None
+    _check(lib().ps_expm_backward(dt, bsz, n, A3.data_ptr(), n, n * n, G3.data_ptr(), n, n * n, c, int(m), int(s),
+                                  int(sigma), gA.data_ptr(), n, n * n, int(bool(recompute)), None, wsp, wsb,
+                                  _stream_ptr(A3.device)))
+    return gA[0] if squeeze else gA
+
+
+def _autograd_cls():
+    import torch
+
+    class ExpmPS(torch.autograd.Function):
+        """r(A) = p(2^-sigma A)^(2^sigma) by (mixed-precision) PS; the backward is
+        the library's hand-written adjoint (ps_expm_backward)."""
+
+        @staticmethod
+        def forward(ctx, A, m, s, sigma, coef, mode, recompute):
+            ctx.save_for_backward(A)
+            ctx.cfg = (m, s, sigma, coef, recompute)
+            if A.dim() == 3:
+                return ps_expm_strided_batched(A, m, s=s, sigma=sigma, coef=coef, mode=mode)
+            return ps_expm(A, m, s=s, sigma=sigma, coef=coef, mode=mode)
+
+        @staticmethod
+        def backward(ctx, gE):
+            (A,) = ctx.saved_tensors
+            m, s, sigma, coef, recompute = ctx.cfg
+            gA = ps_expm_backward(A, gE, m, s=s, sigma=sigma, coef=coef, recompute=recompute)
+            return gA, None, None, None, None, None, None
+
+    return ExpmPS
+
+
+_EXPM_FN = None
+
+
+def expm(A, m, s=0, sigma=0, coef=None, mode="mixed", recompute=False):
+    """Differentiable r(A) = p(2^-sigma A)^(2^sigma) (Taylor exp when coef is None)."""
+    global _EXPM_FN
+    if _EXPM_FN is None:
+        _EXPM_FN = _autograd_cls()
+    return _EXPM_FN.apply(A, m, s, sigma, coef, mode, recompute)

@@ -132,17 +132,22 @@ hipError_t launch_scale_copy(int working, int64_t n, int batch, MatArg src, MatA
 // Fill an n x n matrix with alpha * I (graph-safe replacement for memset).
 hipError_t launch_fill_identity(int working, int64_t n, int batch, MatArg dst, double alpha, hipStream_t st);
 
-// Adjoint helper: Xbar_j += sum_i c_{si+j} Bbar_i  (column pass).
+// Adjoint helper: for j = 0..nd-1 with coef[j] != 0: dst_j += coef[j] * src
+// (dst_j = dst base + j * dst_step bytes), all n x n column-major, per matrix
+// of the batch (workspace stride ws_stride, user stride in MatArg).
 struct ScatterArgs {
   int64_t n;
-  int s, r, nB;
-  double coef_scale;
-  char* ws;
-  size_t ws_stride;
-  size_t off_Bbar;      // Bbar_0..Bbar_{nB-1}
-  size_t off_Xbar;      // Xbar_1..Xbar_{s} (s slots)
-  size_t slot;
+  int nd;
+  MatArg src;
+  char* dst;            // first destination (ld n)
+  size_t dst_step;      // bytes between destinations
+  size_t ws_stride;     // bytes between matrices for dst
+  double coef[PS_MAX_BLOCKS];
 };
-hipError_t launch_scatter(int working, const ScatterArgs& a, const Coefs& c, int batch, hipStream_t st);
+hipError_t launch_scatter(int working, const ScatterArgs& a, int batch, hipStream_t st);
+
+// dst = alpha * (x + y) elementwise (n x n, batch).
+hipError_t launch_axpby(int working, int64_t n, int batch, MatArg x, MatArg y, MatArg dst, double alpha,
+                        hipStream_t st);
 
 }  // namespace psk

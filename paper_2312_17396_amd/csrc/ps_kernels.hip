@@ -180,4 +180,41 @@ hipError_t launch_fill_identity(int working, int64_t n, int batch, MatArg dst, d
   return hipGetLastError();
 }
 
+template <typename W>
+__global__ void k_scatter(ScatterArgs a) {
+  const int64_t b = blockIdx.z, col = blockIdx.y;
+  const W* s = (const W*)a.src.p + b * a.src.stride;
+  for (int64_t rw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; rw < a.n; rw += (int64_t)gridDim.x * blockDim.x) {
+    const W v = s[rw + col * a.src.ld];
+    for (int j = 0; j < a.nd; ++j) {
+      if (a.coef[j] == 0.0) continue;
+      W* d = (W*)(a.dst + b * a.ws_stride + (size_t)j * a.dst_step);
+      d[rw + col * a.n] += (W)a.coef[j] * v;
+    }
+  }
+}
+hipError_t launch_scatter(int working, const ScatterArgs& a, int batch, hipStream_t st) {
+  dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)a.n, batch);
+  if (working == 0) hipLaunchKernelGGL(k_scatter<double>, grid, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_scatter<float>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename W>
+__global__ void k_axpby(int64_t n, MatArg x, MatArg y, MatArg dst, double alpha) {
+  const int64_t b = blockIdx.z, col = blockIdx.y;
+  const W* xs = (const W*)x.p + b * x.stride;
+  const W* ys = (const W*)y.p + b * y.stride;
+  W* d = (W*)dst.p + b * dst.stride;
+  for (int64_t rw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; rw < n; rw += (int64_t)gridDim.x * blockDim.x)
+    d[rw + col * dst.ld] = (W)(alpha * ((double)xs[rw + col * x.ld] + (double)ys[rw + col * y.ld]));
+}
+hipError_t launch_axpby(int working, int64_t n, int batch, MatArg x, MatArg y, MatArg dst, double alpha,
+                        hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)n, batch);
+  if (working == 0) hipLaunchKernelGGL(k_axpby<double>, grid, dim3(256), 0, st, n, x, y, dst, alpha);
+  else hipLaunchKernelGGL(k_axpby<float>, grid, dim3(256), 0, st, n, x, y, dst, alpha);
+  return hipGetLastError();
+}
+
 }  // namespace psk
