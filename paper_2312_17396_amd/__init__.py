@@ -19,7 +19,7 @@ import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIBPATH = os.path.join(HERE, "libps.so")
+LIBPATH = os.environ.get("PS_LIBPATH") or os.path.join(HERE, "libps.so")
 
 PS_F64, PS_F32 = 0, 1
 TIER_F64, TIER_F32, TIER_BF16, TIER_FP8 = 0, 1, 2, 3

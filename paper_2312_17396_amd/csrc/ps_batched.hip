@@ -99,7 +99,7 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
   if (!it.s_fixed && it.L[0].s != it.L[1].s) {
     // ||X||_1 = beta * max column abs sum of A
     double mx = 0.0;
-    for (int64_t c = w; c < n; c += 4) {
+    for (int64_t c = w; c < n; c += NW) {
       double v = 0.0;
       for (int64_t rw = lane; rw < n; rw += 64) v += fabs((double)A[rw + c * lda]);
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -109,14 +109,14 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
     __syncthreads();
     if (t == 0) {
       double x = red[0];
-      for (int k = 1; k < 4; ++k) if (red[k] > x || red[k] != red[k]) x = red[k];
+      for (int k = 1; k < NW; ++k) if (red[k] > x || red[k] != red[k]) x = red[k];
       x *= beta;
       const double c0 = apriori_cost(it.L[0], a.cf, x, WT, a.mask, a.delta);
       const double c1 = apriori_cost(it.L[1], a.cf, x, WT, a.mask, a.delta);
-      red[4] = (c0 < c1) ? 0.0 : 1.0;
+      red[NW] = (c0 < c1) ? 0.0 : 1.0;
     }
     __syncthreads();
-    pick = red[4] != 0.0 ? 1 : 0;
+    pick = red[NW] != 0.0 ? 1 : 0;
     __syncthreads();
   }
   const Layout& L = it.L[pick];
@@ -149,7 +149,7 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
   aa.L = L;
   aa.tier_mask = a.mode == PS_MODE_MIXED ? a.mask : 0u;
   const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
-  for (int64_t c = w; c < n; c += 4)
+  for (int64_t c = w; c < n; c += NW)
     for (int64_t ch = 0; ch < nch; ++ch) assemble_column<W>(aa, a.cf, ws, A, c, ch);
   __syncthreads();
   // ---- 3. plan

@@ -17,12 +17,31 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 
-constexpr int NT = 256;
-constexpr int BKL = 32;               // K slab of the LDS main loop
-constexpr int LROW = kTile + 16;      // padded LDS row (elements): 2 half-wave passes hit disjoint banks
+constexpr int NT = 512;               // threads per workgroup: 8 waves, two per SIMD
+constexpr int NW = NT / 64;           // waves per workgroup
+#ifndef PS_BKL
+#define PS_BKL 32
+#endif
+#ifndef PS_LPAD
+#define PS_LPAD 16
+#endif
+#ifndef PS_KCHAINS
+#define PS_KCHAINS 2
+#endif
+constexpr int BKL = PS_BKL;           // K slab of the LDS main loop
+constexpr int LROW = kTile + PS_LPAD; // padded LDS row (elements): with 16 the two half-wave passes of
+                                      // a fragment read (rows k and k+1, 640 B apart) hit disjoint banks
+constexpr int KCH = PS_KCHAINS;       // independent accumulator chains per MFMA block (k-step parity)
 constexpr int CSTR = kTile + 1;       // epilogue tile column stride (elements)
 constexpr int SLAB = BKL * LROW;      // elements of one operand slab in LDS
 constexpr int SMEM_BYTES = 4 * SLAB * 8;   // 80 KiB: two stages of A and B slabs (FP64)
+constexpr int RUN = BKL * kTile / NT; // consecutive elements each thread moves per operand and slab (4)
+constexpr int TILE_Q = kTile * kTile / NT;  // tile elements per thread in the epilogue passes (8)
+
+// Wave layout of a 64x64 output tile: wave w owns rows [32 (w & 1), +32) and
+// columns [16 (w >> 1), +16) as two 16x16 MFMA blocks stacked in M.
+__device__ inline int wave_row0() { return ((threadIdx.x >> 6) & 1) * 32; }
+__device__ inline int wave_col0() { return (threadIdx.x >> 7) * 16; }
 
 // ---------------------------------------------------------------------------
 // tile scheduling: workgroups are dispatched round-robin over the 8 XCDs; each
@@ -56,178 +75,167 @@ template <> struct MF<float> {
   static __device__ inline int row(int v, int g) { return 4 * g + v; }
 };
 
-// ---- global -> register slab loads.  Each thread moves 8 consecutive
+// ---- global -> register slab loads.  Each thread moves RUN consecutive
 // elements (a contiguous run in memory) of the 64 x BKL A slab and of the
-// BKL x 64 B slab; runs that are fully in bounds and 16-byte aligned use
-// vector loads, the rest are guarded element loads (zero fill).
+// BKL x 64 B slab; runs fully in bounds and 16-byte aligned use vector loads,
+// the rest guarded element loads (zero fill).  Runs along k (A transposed,
+// B normal) are laid out lane -> column so that each LDS store instruction of
+// a wave writes 64 consecutive elements of one k-row (no bank conflicts).
 template <typename T>
-__device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim, T r[8]) {
+__device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim, T r[RUN]) {
   if (full && (((uintptr_t)p) & 15) == 0) {
     typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
     constexpr int W = 16 / sizeof(T);
 #pragma unroll
-    for (int i = 0; i < 8; i += W) {
+    for (int i = 0; i < RUN; i += W) {
       v2 x = *(const v2*)(p + i);
 #pragma unroll
       for (int j = 0; j < W; ++j) r[i + j] = x[j];
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = (i < lim) ? p[i] : T(0);
+    for (int i = 0; i < RUN; ++i) r[i] = (i < lim) ? p[i] : T(0);
   }
 }
 // A(m,k): TA = false -> A[m + k lda] (run along m), true -> A[k + m lda] (run along k)
 template <typename T, bool TA>
-__device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, int64_t m0, int64_t k0, int t, T r[8]) {
+__device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, int64_t m0, int64_t k0, int t, T r[RUN]) {
   if (!TA) {
-    const int kk = t >> 3, mm = (t & 7) * 8;
+    const int kk = t >> 4, mm = (t & 15) * RUN;
     const int64_t k = k0 + kk, m = m0 + mm;
-    const int64_t lim = (k < n) ? min<int64_t>(8, n - m) : 0;
-    load_run<T>(A + m + k * lda, lim >= 8, lim, r);
+    const int64_t lim = (k < n) ? min<int64_t>(RUN, n - m) : 0;
+    load_run<T>(A + m + k * lda, lim >= RUN, lim, r);
   } else {
-    const int mm = t >> 2, kk = (t & 3) * 8;
+    const int mm = t & 63, kk = (t >> 6) * RUN;
     const int64_t m = m0 + mm, k = k0 + kk;
-    const int64_t lim = (m < n) ? min<int64_t>(8, n - k) : 0;
-    load_run<T>(A + k + m * lda, lim >= 8, lim, r);
+    const int64_t lim = (m < n) ? min<int64_t>(RUN, n - k) : 0;
+    load_run<T>(A + k + m * lda, lim >= RUN, lim, r);
   }
 }
 template <typename T, bool TA>
-__device__ inline void store_a(T* As, int t, const T r[8]) {
+__device__ inline void store_a(T* As, int t, const T r[RUN]) {
   if (!TA) {
-    const int kk = t >> 3, mm = (t & 7) * 8;
+    const int kk = t >> 4, mm = (t & 15) * RUN;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) As[kk * LROW + mm + i] = r[i];
+    for (int i = 0; i < RUN; ++i) As[kk * LROW + mm + i] = r[i];
   } else {
-    const int mm = t >> 2, kk = (t & 3) * 8;
+    const int mm = t & 63, kk = (t >> 6) * RUN;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) As[(kk + i) * LROW + mm] = r[i];
+    for (int i = 0; i < RUN; ++i) As[(kk + i) * LROW + mm] = r[i];
   }
 }
 // B(k,j): TB = false -> B[k + j ldb] (run along k), true -> B[j + k ldb] (run along j)
 template <typename T, bool TB>
-__device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, int64_t n0, int64_t k0, int t, T r[8]) {
+__device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, int64_t n0, int64_t k0, int t, T r[RUN]) {
   if (!TB) {
-    const int jj = t >> 2, kk = (t & 3) * 8;
+    const int jj = t & 63, kk = (t >> 6) * RUN;
     const int64_t j = n0 + jj, k = k0 + kk;
-    const int64_t lim = (j < n) ? min<int64_t>(8, n - k) : 0;
-    load_run<T>(B + k + j * ldb, lim >= 8, lim, r);
+    const int64_t lim = (j < n) ? min<int64_t>(RUN, n - k) : 0;
+    load_run<T>(B + k + j * ldb, lim >= RUN, lim, r);
   } else {
-    const int kk = t >> 3, jj = (t & 7) * 8;
+    const int kk = t >> 4, jj = (t & 15) * RUN;
     const int64_t k = k0 + kk, j = n0 + jj;
-    const int64_t lim = (k < n) ? min<int64_t>(8, n - j) : 0;
-    load_run<T>(B + j + k * ldb, lim >= 8, lim, r);
+    const int64_t lim = (k < n) ? min<int64_t>(RUN, n - j) : 0;
+    load_run<T>(B + j + k * ldb, lim >= RUN, lim, r);
   }
 }
 template <typename T, bool TB>
-__device__ inline void store_b(T* Bs, int t, const T r[8]) {
+__device__ inline void store_b(T* Bs, int t, const T r[RUN]) {
   if (!TB) {
-    const int jj = t >> 2, kk = (t & 3) * 8;
+    const int jj = t & 63, kk = (t >> 6) * RUN;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Bs[(kk + i) * LROW + jj] = r[i];
+    for (int i = 0; i < RUN; ++i) Bs[(kk + i) * LROW + jj] = r[i];
   } else {
-    const int kk = t >> 3, jj = (t & 7) * 8;
+    const int kk = t >> 4, jj = (t & 15) * RUN;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Bs[kk * LROW + jj + i] = r[i];
+    for (int i = 0; i < RUN; ++i) Bs[kk * LROW + jj + i] = r[i];
   }
 }
 
 template <typename T>
-__device__ inline void mma_slab(const T* as, const T* bs, int wr, int wc, int g, int c, typename MF<T>::V acc[4]) {
+__device__ inline void mma_slab(const T* as, const T* bs, int wr, int wc, int g, int c,
+                                typename MF<T>::V acc[2 * KCH]) {
 #pragma unroll
   for (int ks = 0; ks < BKL / 4; ++ks) {
     const int k = ks * 4 + g;
+    const int ch = (ks % KCH) * 2;
     const T a0 = as[k * LROW + wr + c], a1 = as[k * LROW + wr + 16 + c];
-    const T b0 = bs[k * LROW + wc + c], b1 = bs[k * LROW + wc + 16 + c];
-    acc[0] = MF<T>::mma(a0, b0, acc[0]);
-    acc[1] = MF<T>::mma(a0, b1, acc[1]);
-    acc[2] = MF<T>::mma(a1, b0, acc[2]);
-    acc[3] = MF<T>::mma(a1, b1, acc[3]);
+    const T b0 = bs[k * LROW + wc + c];
+    acc[ch] = MF<T>::mma(a0, b0, acc[ch]);
+    acc[ch + 1] = MF<T>::mma(a1, b0, acc[ch + 1]);
   }
 }
 
-// ---- FP64 / FP32 main loop: acc[2*bi+bj] += A-tile x B-tile over all of K.
-// Two LDS stages; global loads run two slabs ahead of the MFMAs (register
-// sets R0/R1 alternate, loop unrolled by two), so each load has two slabs of
-// MFMA work to complete before its data is stored to LDS.
+// ---- FP64 / FP32 main loop: acc[bi] += A-tile x B-tile over all of K for the
+// wave's two 16x16 blocks.  Two LDS stages; the global loads of slab kt+1 are
+// issued before the MFMAs of slab kt and stored to the other stage after them.
 template <typename T, bool TA, bool TB>
 __device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
-                                    int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[4]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-  T* As[2] = {(T*)smem, (T*)smem + 2 * SLAB};
-  T* Bs[2] = {(T*)smem + SLAB, (T*)smem + 3 * SLAB};
+                                    int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
+  const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
+  const int wr = wave_row0(), wc = wave_col0();
+  T* const As0 = (T*)smem;
+  T* const Bs0 = (T*)smem + SLAB;
+  typename MF<T>::V chains[2 * KCH];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = typename MF<T>::V{0, 0, 0, 0};
+  for (int i = 0; i < 2 * KCH; ++i) chains[i] = typename MF<T>::V{0, 0, 0, 0};
   const int64_t nk = (n + BKL - 1) / BKL;
-  T ra0[8], rb0[8], ra1[8], rb1[8];
-  // prologue: slab 0 -> LDS stage 0, slab 1 -> registers set 1
-  load_a<T, TA>(A, lda, n, m0, 0, t, ra0);
-  load_b<T, TB>(B, ldb, n, n0, 0, t, rb0);
-  if (nk > 1) {
-    load_a<T, TA>(A, lda, n, m0, BKL, t, ra1);
-    load_b<T, TB>(B, ldb, n, n0, BKL, t, rb1);
-  }
-  store_a<T, TA>(As[0], t, ra0);
-  store_b<T, TB>(Bs[0], t, rb0);
+  T ra[RUN], rb[RUN];
+  load_a<T, TA>(A, lda, n, m0, 0, t, ra);
+  load_b<T, TB>(B, ldb, n, n0, 0, t, rb);
+  store_a<T, TA>(As0, t, ra);
+  store_b<T, TB>(Bs0, t, rb);
   __syncthreads();
-  for (int64_t kt = 0; kt < nk; kt += 2) {
-    // even slab kt in stage 0; registers set 1 holds slab kt+1
-    if (kt + 2 < nk) {
-      load_a<T, TA>(A, lda, n, m0, (kt + 2) * BKL, t, ra0);
-      load_b<T, TB>(B, ldb, n, n0, (kt + 2) * BKL, t, rb0);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      load_a<T, TA>(A, lda, n, m0, (kt + 1) * BKL, t, ra);
+      load_b<T, TB>(B, ldb, n, n0, (kt + 1) * BKL, t, rb);
     }
-    mma_slab<T>(As[0], Bs[0], wr, wc, g, c, acc);
-    if (kt + 1 < nk) {
-      store_a<T, TA>(As[1], t, ra1);
-      store_b<T, TB>(Bs[1], t, rb1);
-    }
-    __syncthreads();
-    if (kt + 1 >= nk) break;
-    // odd slab kt+1 in stage 1; registers set 0 holds slab kt+2
-    if (kt + 3 < nk) {
-      load_a<T, TA>(A, lda, n, m0, (kt + 3) * BKL, t, ra1);
-      load_b<T, TB>(B, ldb, n, n0, (kt + 3) * BKL, t, rb1);
-    }
-    mma_slab<T>(As[1], Bs[1], wr, wc, g, c, acc);
-    if (kt + 2 < nk) {
-      store_a<T, TA>(As[0], t, ra0);
-      store_b<T, TB>(Bs[0], t, rb0);
+    mma_slab<T>(As0 + cur * 2 * SLAB, Bs0 + cur * 2 * SLAB, wr, wc, g, c, chains);
+    if (more) {
+      store_a<T, TA>(As0 + (cur ^ 1) * 2 * SLAB, t, ra);
+      store_b<T, TB>(Bs0 + (cur ^ 1) * 2 * SLAB, t, rb);
     }
     __syncthreads();
+  }
+  acc[0] = chains[0];
+  acc[1] = chains[1];
+#pragma unroll
+  for (int ch = 1; ch < KCH; ++ch) {
+    acc[0] += chains[2 * ch];
+    acc[1] += chains[2 * ch + 1];
   }
 }
 
 // accumulator fragments -> LDS tile Cs[col * CSTR + row] (type W)
 template <typename T, typename W>
-__device__ inline void frag_to_cs(const typename MF<T>::V acc[4], W* Cs, double scale) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+__device__ inline void frag_to_cs(const typename MF<T>::V acc[2], W* Cs, double scale) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int wr = wave_row0(), wc = wave_col0();
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr + 16 * bi + MF<T>::row(v, g);
-        const int col = wc + 16 * bj + c;
-        Cs[col * CSTR + row] = (W)((double)acc[bi * 2 + bj][v] * scale);
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int row = wr + 16 * bi + MF<T>::row(v, g);
+      const int col = wc + c;
+      Cs[col * CSTR + row] = (W)((double)acc[bi][v] * scale);
+    }
 }
 
-__device__ inline void frag_f32_to_cs_any(const f4v acc[4], double* Csd, float* Csf, bool isd) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+__device__ inline void frag_f32_to_cs_any(const f4v acc[2], double* Csd, float* Csf, bool isd) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int wr = wave_row0(), wc = wave_col0();
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = wr + 16 * bi + 4 * g + v;
-        const int col = wc + 16 * bj + c;
-        if (isd) Csd[col * CSTR + row] = (double)acc[bi * 2 + bj][v];
-        else Csf[col * CSTR + row] = acc[bi * 2 + bj][v];
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int row = wr + 16 * bi + 4 * g + v;
+      const int col = wc + c;
+      if (isd) Csd[col * CSTR + row] = (double)acc[bi][v];
+      else Csf[col * CSTR + row] = acc[bi][v];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -242,27 +250,24 @@ __device__ inline uint16_t bf16_bits_rne(float x) {
 
 // P: row-major [Mp][Kp] bf16 bits; Yb: [Np][Kp] (column j of Y contiguous in k)
 __device__ inline void mainloop_bf16(const uint16_t* __restrict__ P, const uint16_t* __restrict__ Yb, int64_t Kp,
-                                     int64_t n, int64_t m0, int64_t n0, f4v acc[4]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = f4v{0, 0, 0, 0};
+                                     int64_t n, int64_t m0, int64_t n0, f4v acc[2]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int wr = wave_row0(), wc = wave_col0();
+  acc[0] = f4v{0, 0, 0, 0};
+  acc[1] = f4v{0, 0, 0, 0};
   for (int64_t k0 = 0; k0 < n; k0 += 32) {
     const int64_t kb = k0 + 8 * g;
-    union U { uint4 q; uint16_t h[8]; bf8v v; } a[2], bb[2];
+    union U { uint4 q; uint16_t h[8]; bf8v v; } a[2], bb;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) a[bi].q = *(const uint4*)(P + (m0 + wr + 16 * bi + c) * Kp + kb);
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) bb[bj].q = *(const uint4*)(Yb + (n0 + wc + 16 * bj + c) * Kp + kb);
+    bb.q = *(const uint4*)(Yb + (n0 + wc + c) * Kp + kb);
     if (kb + 8 > n) {
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        if (kb + e >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb[0].h[e] = 0; bb[1].h[e] = 0; }
+        if (kb + e >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb.h[e] = 0; }
     }
-    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0].v, bb[0].v, acc[0], 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0].v, bb[1].v, acc[1], 0, 0, 0);
-    acc[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1].v, bb[0].v, acc[2], 0, 0, 0);
-    acc[3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1].v, bb[1].v, acc[3], 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0].v, bb.v, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1].v, bb.v, acc[1], 0, 0, 0);
   }
 }
 
@@ -275,18 +280,18 @@ __device__ inline void mainloop_bf16(const uint16_t* __restrict__ P, const uint1
 // scale block coincide with one 32-element block of the packed layout.
 __device__ inline void mainloop_fp8(const uint8_t* __restrict__ P8, const uint8_t* __restrict__ Ps,
                                     const uint8_t* __restrict__ Y8, const uint8_t* __restrict__ Ys, int64_t Kp,
-                                    int64_t n, int64_t m0, int64_t n0, f4v acc[4]) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+                                    int64_t n, int64_t m0, int64_t n0, f4v acc[2]) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int wr = wave_row0(), wc = wave_col0();
   const int64_t Ks = Kp / 32;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = f4v{0, 0, 0, 0};
+  acc[0] = f4v{0, 0, 0, 0};
+  acc[1] = f4v{0, 0, 0, 0};
   for (int64_t k0 = 0; k0 < n; k0 += 128) {
     const int64_t klo = k0 + 16 * g;        // bytes 0..15
     const int64_t khi = k0 + 64 + 16 * g;   // bytes 16..31
     const int64_t kblk = k0 / 32 + g;       // scale block this lane supplies
-    union U { uint4 q[2]; uint8_t h[32]; i8v v; } a[2], bb[2];
-    int sa[2], sb[2];
+    union U { uint4 q[2]; uint8_t h[32]; i8v v; } a[2], bb;
+    int sa[2], sb;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
       const int64_t r = m0 + wr + 16 * bi + c;
@@ -294,25 +299,22 @@ __device__ inline void mainloop_fp8(const uint8_t* __restrict__ P8, const uint8_
       a[bi].q[1] = *(const uint4*)(P8 + r * Kp + khi);
       sa[bi] = Ps[r * Ks + kblk];
     }
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      const int64_t col = n0 + wc + 16 * bj + c;
-      bb[bj].q[0] = *(const uint4*)(Y8 + col * Kp + klo);
-      bb[bj].q[1] = *(const uint4*)(Y8 + col * Kp + khi);
-      sb[bj] = Ys[col * Ks + kblk];
+    {
+      const int64_t col = n0 + wc + c;
+      bb.q[0] = *(const uint4*)(Y8 + col * Kp + klo);
+      bb.q[1] = *(const uint4*)(Y8 + col * Kp + khi);
+      sb = Ys[col * Ks + kblk];
     }
     if (k0 + 128 > n) {
-      if (kblk * 32 >= n) { sa[0] = sa[1] = sb[0] = sb[1] = 127; }
+      if (kblk * 32 >= n) { sa[0] = sa[1] = sb = 127; }
 #pragma unroll
       for (int e = 0; e < 32; ++e) {
         const int64_t k = (e < 16) ? klo + e : khi + (e - 16);
-        if (k >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb[0].h[e] = 0; bb[1].h[e] = 0; }
+        if (k >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb.h[e] = 0; }
       }
     }
-    acc[0] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0].v, bb[0].v, acc[0], 0, 0, 0, sa[0], 0, sb[0]);
-    acc[1] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0].v, bb[1].v, acc[1], 0, 0, 0, sa[0], 0, sb[1]);
-    acc[2] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1].v, bb[0].v, acc[2], 0, 0, 0, sa[1], 0, sb[0]);
-    acc[3] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1].v, bb[1].v, acc[3], 0, 0, 0, sa[1], 0, sb[1]);
+    acc[0] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0].v, bb.v, acc[0], 0, 0, 0, sa[0], 0, sb);
+    acc[1] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1].v, bb.v, acc[1], 0, 0, 0, sa[1], 0, sb);
   }
 }
 
@@ -344,7 +346,7 @@ template <typename T, bool TA, bool TB>
 __device__ inline void gemm_tile(const T* __restrict__ Ap, int64_t lda, const T* __restrict__ Bp, int64_t ldb,
                                  T* Cp, int64_t ldc, int64_t n, int64_t m0, int64_t n0, double alpha, int accumulate,
                                  char* smem) {
-  typename MF<T>::V acc[4];
+  typename MF<T>::V acc[2];
   mainloop_lds<T, TA, TB>(Ap, lda, Bp, ldb, n, m0, n0, smem, acc);
   T* Cs = (T*)smem;
   frag_to_cs<T, T>(acc, Cs, 1.0);
@@ -353,8 +355,8 @@ __device__ inline void gemm_tile(const T* __restrict__ Ap, int64_t lda, const T*
   const int row = t & 63;
   const int64_t gr = m0 + row;
 #pragma unroll 4
-  for (int q = 0; q < 16; ++q) {
-    const int col = (t >> 6) + 4 * q;
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int col = (t >> 6) + NW * q;
     const int64_t gc = n0 + col;
     if (gr < n && gc < n) {
       const T v = (T)(alpha * (double)Cs[col * CSTR + row]);
@@ -397,19 +399,19 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
   const int t_in = h.t_in, t_out = h.t_out;
   W* Cs = (W*)smem;
   if (t_in == WT) {
-    typename MF<W>::V acc[4];
+    typename MF<W>::V acc[2];
     mainloop_lds<W, false, false>((const W*)h.pin, n, h.ysrc, h.ldy, n, m0, n0, smem, acc);
     frag_to_cs<W, W>(acc, Cs, h.yscale);
   } else if (t_in == 1) {   // FP32 product below an FP64 working precision
-    typename MF<float>::V acc[4];
+    typename MF<float>::V acc[2];
     mainloop_lds<float, false, false>((const float*)h.pin, n, h.yf32, n, n, m0, n0, smem, acc);
     frag_to_cs<float, W>(acc, Cs, 1.0);
   } else if (t_in == 2) {
-    f4v acc[4];
+    f4v acc[2];
     mainloop_bf16((const uint16_t*)h.pin, h.ybf16, Kp, n, m0, n0, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else if (t_in == 3) {
-    f4v acc[4];
+    f4v acc[2];
     mainloop_fp8((const uint8_t*)h.pin, (const uint8_t*)h.pin + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   }
@@ -419,8 +421,8 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
   const int t = threadIdx.x;
   const int row = t & 63;
   const int64_t gr = m0 + row;
-  for (int q = 0; q < 16; ++q) {
-    const int col = (t >> 6) + 4 * q;
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int col = (t >> 6) + NW * q;
     const int64_t gc = n0 + col;
     const bool in = gr < n && gc < n;
     const W v = (t_in < 0) ? W(0) : Cs[col * CSTR + row];
@@ -437,13 +439,11 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
   if (t_out < 2) return;
   // pass 2 (row-major): pack into the K-contiguous low-precision layout
   if (t_out == 2) {
-    const int r = t >> 2, seg = (t & 3) * 16;
-    union { uint4 q[2]; uint16_t h[16]; } o;
+    const int r = t >> 3, seg = (t & 7) * 8;
+    union { uint4 q; uint16_t h[8]; } o;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) o.h[e] = bf16_bits_rne((float)Cs[(seg + e) * CSTR + r]);
-    uint4* dst = (uint4*)((uint16_t*)h.pout + (m0 + r) * Kp + n0 + seg);
-    dst[0] = o.q[0];
-    dst[1] = o.q[1];
+    for (int e = 0; e < 8; ++e) o.h[e] = bf16_bits_rne((float)Cs[(seg + e) * CSTR + r]);
+    *(uint4*)((uint16_t*)h.pout + (m0 + r) * Kp + n0 + seg) = o.q;
   } else if (t < 128) {
     const int r = t >> 1, blk = t & 1;
     float vals[32];
@@ -608,13 +608,13 @@ __device__ inline void plan_matrix(const PlanArgs& a, const Layout& L, char* ws,
         const double o = __shfl_xor(v, off, 64);
         if (o > v || o != o) v = o;
       }
-      if (lane == 0) red[ii * 4 + w] = v;
+      if (lane == 0) red[ii * NW + w] = v;
     }
     __syncthreads();
     if (t < 8 && i0 + t <= a.nB) {
-      double v = red[t * 4];
-      for (int k = 1; k < 4; ++k) {
-        const double o = red[t * 4 + k];
+      double v = red[t * NW];
+      for (int k = 1; k < NW; ++k) {
+        const double o = red[t * NW + k];
         if (o > v || o != o) v = o;
       }
       norms[i0 + t] = v;

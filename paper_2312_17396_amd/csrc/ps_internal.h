@@ -6,7 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/ps.h"
+#include "ps.h"
 
 namespace psk {
 

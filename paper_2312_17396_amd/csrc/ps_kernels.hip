@@ -116,7 +116,7 @@ hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_
 template <typename W>
 __global__ __launch_bounds__(NT) void k_assemble(AssembleArgs a, Coefs cf) {
   const int w = threadIdx.x >> 6;
-  const int64_t col = (int64_t)blockIdx.x * 4 + w;
+  const int64_t col = (int64_t)blockIdx.x * NW + w;
   if (col >= a.n) return;  // no block-wide synchronisation below
   const int64_t b = blockIdx.z;
   char* ws = a.ws + b * a.ws_stride;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(NT) void k_assemble(AssembleArgs a, Coefs cf) {
 }
 
 hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, int batch, hipStream_t st) {
-  dim3 grid((unsigned)((a.n + 3) / 4), (unsigned)((a.n + kRowChunk - 1) / kRowChunk), batch), block(NT);
+  dim3 grid((unsigned)((a.n + NW - 1) / NW), (unsigned)((a.n + kRowChunk - 1) / kRowChunk), batch), block(NT);
   if (working == 0) hipLaunchKernelGGL(k_assemble<double>, grid, block, 0, st, a, c);
   else hipLaunchKernelGGL(k_assemble<float>, grid, block, 0, st, a, c);
   return hipGetLastError();
