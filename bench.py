@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "plain", "both"], default="both",
                     help="restrict the timed modes (profiling runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary workloads (batched, Pade/cos, adjoint)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run three 256 MiB device-to-device copies (known traffic, for counter scaling)")
     return ap.parse_args()
@@ -61,11 +63,12 @@ def load_traffic():
     counter summary, if it was taken on the current kernel source."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_gemm_f64_n1024.json")
-    src = os.path.join(ROOT, "paper_2312_17396_amd", "csrc", "ps_kernels.hip")
+    csrc = os.path.join(ROOT, "paper_2312_17396_amd", "csrc")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if rec.get("kernel_source_sha256") != h:
+        h1 = hashlib.sha256(open(os.path.join(csrc, "ps_kernels.hip"), "rb").read()).hexdigest()
+        h2 = hashlib.sha256(open(os.path.join(csrc, "ps_device.h"), "rb").read()).hexdigest()
+        if rec.get("kernel_source_sha256") != h1 or rec.get("device_header_sha256") != h2:
             return None
         return rec.get("hbm_bytes_per_launch")
     except Exception:
@@ -178,11 +181,85 @@ def main():
                         "tflops": round(flops_per_step / res["plain"] / 1e12, 3)}
         out["speedup_mixed_vs_plain"] = round(res["plain"] / res["mixed"], 4)
 
+    if not args.no_extra:
+        out["extra"] = extra_workloads(ps, inputs, torch)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mats, outs_mixed=[ps.ps_expm(a, M, s=S, sigma=sg, mode="mixed")
                                                              for a, sg in zip(mats, sigmas)],
                                            norms=norms, sigmas=sigmas)
     print(json.dumps(out))
+
+
+def _time(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def extra_workloads(ps, inputs, torch):
+    """Secondary workloads of the hot path (each a few seconds):
+    batched   4096 matrices, n uniform in {8..256}, ||A||_1 ~ U[0.05, 4], Taylor
+              m = 18, s chosen per matrix, FP32: one persistent launch replayed
+              from a hipGraph vs a loop of single-matrix calls;
+    pade_cos  n = 2048 FP64, A = Q diag(lambda) Q^T: Pade [13/13] p and q from one
+              power table (s = 4) and Taylor cos of degree 12 in A^2 (s = 4);
+    grad      64 FP32 matrices of order 512: forward + hand-written adjoint."""
+    res = {}
+    dev = torch.device("cuda:0")
+    # ---- batched
+    mats, ts = inputs.batch_uneven()
+    sig = [inputs.squarings_for(t) for t in ts]
+    A = [torch.tensor(a, dtype=torch.float32, device=dev) for a in mats]
+    flops = sum(2.0 * a.shape[0] ** 3 * (3 + 4 + sg) for a, sg in zip(mats, sig))   # s=4/5: 7 GEMMs + squarings
+    out = {"matrices": len(A), "m": 18, "dtype": "f32"}
+    for mode in ("fixed", "mixed"):
+        g = ps.BatchedGraph(A, 18, sigma=sig, mode=mode)
+        t = _time(g.launch, 5, torch)
+        g.close()
+        out[mode] = {"ms": round(t * 1e3, 3), "evals_per_s": round(len(A) / t, 1),
+                     "tflops_credited": round(flops / t / 1e12, 2)}
+    sub = list(range(0, len(A), 8))          # per-matrix loop on every 8th matrix, scaled
+    wsl = [ps.expm_workspace(A[i], 18, 0, sig[i]) for i in sub]
+    outs = [torch.empty_like(A[i]) for i in sub]
+
+    def loop():
+        for k, i in enumerate(sub):
+            ps.ps_expm(A[i], 18, s=0, sigma=sig[i], mode="mixed", out=outs[k], workspace=wsl[k])
+    t = _time(loop, 1, torch) * len(A) / len(sub)
+    out["per_matrix_loop_mixed"] = {"ms": round(t * 1e3, 2), "evals_per_s": round(len(A) / t, 1),
+                                    "note": "loop of ps_expm calls timed on every 8th matrix, scaled"}
+    out["speedup_persistent_vs_loop"] = round(t / (out["mixed"]["ms"] * 1e-3), 2)
+    res["batched_uneven_4096"] = out
+    del A, outs, wsl
+    # ---- Pade pair and cos at n = 2048
+    Aq = torch.tensor(inputs.orthosim_2048(), dtype=torch.float64, device=dev)
+    p, q = ps.coef_pade_exp(13)
+    c = ps.coef_taylor_cos(12)
+    out = {"n": 2048, "dtype": "f64"}
+    for mode in ("fixed", "mixed"):
+        tp = _time(lambda: ps.ps_eval_multi(Aq, [p, q], s=4, mode=mode), 5, torch)
+        tc = _time(lambda: ps.ps_eval_multi(Aq, [c], s=4, square_arg=True, mode=mode), 5, torch)
+        out[mode] = {"pade_pair_ms": round(tp * 1e3, 3), "pade_tflops_credited": round(9 * 2 * 2048 ** 3 / tp / 1e12, 2),
+                     "cos_ms": round(tc * 1e3, 3), "cos_tflops_credited": round(6 * 2 * 2048 ** 3 / tc / 1e12, 2)}
+    res["pade_cos_2048"] = out
+    del Aq
+    # ---- adjoint batch
+    An, Gn = inputs.grad_batch_512()
+    At = torch.tensor(An, device=dev)
+    Gt = torch.tensor(Gn, device=dev)
+    sigma = inputs.squarings_for(max(float(x) for x in torch.linalg.matrix_norm(At.double(), ord=1).cpu()))
+    tf = _time(lambda: ps.ps_expm_strided_batched(At, 18, s=5, sigma=sigma, mode="mixed"), 3, torch)
+    tb = _time(lambda: ps.ps_expm_backward(At, Gt, 18, s=5, sigma=sigma), 3, torch)
+    gem_f = 4 + 3 + sigma
+    res["grad_batch_512"] = {"batch": 64, "n": 512, "sigma": sigma, "dtype": "f32",
+                             "forward_ms": round(tf * 1e3, 3), "backward_ms": round(tb * 1e3, 3),
+                             "backward_tflops_credited": round(64 * (gem_f + 2 * gem_f) * 2 * 512 ** 3 / tb / 1e12, 2)}
+    return res
 
 
 def cpu_baseline(mats, outs_mixed, norms, sigmas):

@@ -56,7 +56,7 @@ struct BatchArgs {
 };
 
 template <typename W>
-constexpr int persist_smem() { return 4 * SLAB * (int)sizeof(W); }
+constexpr int persist_smem() { return 2 * STAGE * (int)sizeof(W); }
 
 // modelled relative cost of one n^3 product per tier (inverse MFMA rates)
 __device__ inline double tier_cost(int t) { return t == 0 ? 2.0 : t == 1 ? 1.0 : t == 2 ? 1.0 / 16 : 1.0 / 32; }
@@ -122,7 +122,8 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
   const Layout& L = it.L[pick];
   if (t == 0 && a.chosen) a.chosen[idx] = L.s;
   char* ws = a.ws + it.ws_off;
-  const int nt = (int)((n + kTile - 1) / kTile);
+  const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
+  const int ntiles = ntm * ntn;
   const int64_t se = (int64_t)(L.slot / sizeof(W));
   W* pw = (W*)(ws + L.off_pow);
   // ---- 1. power table: X_2 = beta^2 (A A), X_{j+1} = beta (X_j A)
@@ -130,9 +131,9 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
     const W* src = (j == 2) ? A : pw + (int64_t)(j - 3) * se;
     const int64_t lds = (j == 2) ? lda : n;
     const double alpha = (j == 2) ? beta * beta : beta;
-    for (int tile = 0; tile < nt * nt; ++tile)
-      gemm_tile<W, false, false>(src, lds, A, lda, pw + (int64_t)(j - 2) * se, n, n, (int64_t)(tile % nt) * kTile,
-                                 (int64_t)(tile / nt) * kTile, alpha, 0, smem);
+    for (int tile = 0; tile < ntiles; ++tile)
+      gemm_tile<W, false, false>(src, lds, A, lda, pw + (int64_t)(j - 2) * se, n, n, (int64_t)(tile % ntm) * kTileM,
+                                 (int64_t)(tile / ntm) * kTileN, alpha, 0, smem);
   }
   // ---- 2. blocks, norms, low-precision copies of Y
   AssembleArgs aa;
@@ -205,8 +206,8 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
     h.bsrc = (const W*)(ws + L.off_B) + (int64_t)(cast ? i0 : i - 1) * se;
     h.outw = final_out ? fin : (W*)h.pout;
     h.ldo = final_out ? ldfin : n;
-    for (int tile = 0; tile < nt * nt; ++tile)
-      horner_tile<W>(h, (int64_t)(tile % nt) * kTile, (int64_t)(tile / nt) * kTile, smem);
+    for (int tile = 0; tile < ntiles; ++tile)
+      horner_tile<W>(h, (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, smem);
   }
   // ---- 5. squarings
   if (square) {
@@ -215,9 +216,9 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
       const W* src = bufs[(q - 1) & 1];
       W* dst = (q == sigma) ? (W*)it.E : bufs[q & 1];
       const int64_t ldd = (q == sigma) ? it.lde : n;
-      for (int tile = 0; tile < nt * nt; ++tile)
-        gemm_tile<W, false, false>(src, n, src, n, dst, ldd, n, (int64_t)(tile % nt) * kTile,
-                                   (int64_t)(tile / nt) * kTile, 1.0, 0, smem);
+      for (int tile = 0; tile < ntiles; ++tile)
+        gemm_tile<W, false, false>(src, n, src, n, dst, ldd, n, (int64_t)(tile % ntm) * kTileM,
+                                   (int64_t)(tile / ntm) * kTileN, 1.0, 0, smem);
     }
   }
 }

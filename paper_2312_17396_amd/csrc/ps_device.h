@@ -1,7 +1,7 @@
 // Device building blocks of the PS kernels, shared by the grid kernels
 // (ps_kernels.hip) and the persistent batched kernel (ps_batched.hip).
-// Every function here works on one 64x64 output tile, one column, or one
-// matrix with the 256 threads of a workgroup.
+// Every function here works on one 64 x kTileN output tile, one column, or
+// one matrix with the NT threads of a workgroup.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <type_traits>
@@ -17,28 +17,32 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 
-constexpr int NT = 512;               // threads per workgroup: 8 waves, two per SIMD
+constexpr int NT = kTileM * kTileN / 8;  // threads per workgroup: one wave per 32x16 output block
+                                         // (64x64 tiles: 8 waves, two per SIMD)
 constexpr int NW = NT / 64;           // waves per workgroup
-#ifndef PS_BKL
-#define PS_BKL 32
-#endif
-#ifndef PS_LPAD
-#define PS_LPAD 16
-#endif
 #ifndef PS_KCHAINS
 #define PS_KCHAINS 2
 #endif
-constexpr int BKL = PS_BKL;           // K slab of the LDS main loop
-constexpr int LROW = kTile + PS_LPAD; // padded LDS row (elements): with 16 the two half-wave passes of
-                                      // a fragment read (rows k and k+1, 640 B apart) hit disjoint banks
+constexpr int BKL = 32;               // K slab of the LDS main loop
+constexpr int LROWA = kTileM + 16;    // padded LDS rows (elements): a fragment read covers k-rows
+constexpr int LROWB = kTileN + 16;    //   k and k+1 in one half-wave pass; 640 B (384 B) apart, the
+                                      //   two rows land on disjoint banks
 constexpr int KCH = PS_KCHAINS;       // independent accumulator chains per MFMA block (k-step parity)
-constexpr int CSTR = kTile + 1;       // epilogue tile column stride (elements)
-constexpr int SLAB = BKL * LROW;      // elements of one operand slab in LDS
-constexpr int SMEM_BYTES = 4 * SLAB * 8;   // 80 KiB: two stages of A and B slabs (FP64)
-constexpr int RUN = BKL * kTile / NT; // consecutive elements each thread moves per operand and slab (4)
-constexpr int TILE_Q = kTile * kTile / NT;  // tile elements per thread in the epilogue passes (8)
+constexpr int CSTR = kTileM + 1;      // epilogue tile column stride (elements)
+constexpr int SLABA = BKL * LROWA;    // elements of the A slab of one stage
+constexpr int SLABB = BKL * LROWB;    // elements of the B slab of one stage
+constexpr int STAGE = SLABA + SLABB;
+constexpr int SMEM_BYTES = 2 * STAGE * 8;    // two stages (FP64): 80 KiB (64x64 tiles)
+constexpr int RUNA = BKL * kTileM / NT;      // consecutive elements each thread moves per slab
+constexpr int RUNB = BKL * kTileN / NT;
+constexpr int TPA = kTileM / RUNA;           // threads per k-row of a normal A slab
+constexpr int TPB = kTileN / RUNB;           // threads per k-row of a transposed B slab
+constexpr int TILE_Q = kTileM * kTileN / NT; // tile elements per thread in the epilogue passes (8)
 
-// Wave layout of a 64x64 output tile: wave w owns rows [32 (w & 1), +32) and
+static_assert(kTileM == 64 && (kTileN == 64 || kTileN == 32), "tile shape");
+static_assert(RUNA % 2 == 0 && RUNB % 2 == 0 && TPA * RUNA == kTileM && TPB * RUNB == kTileN, "slab split");
+
+// Wave layout of an output tile: wave w owns rows [32 (w & 1), +32) and
 // columns [16 (w >> 1), +16) as two 16x16 MFMA blocks stacked in M.
 __device__ inline int wave_row0() { return ((threadIdx.x >> 6) & 1) * 32; }
 __device__ inline int wave_col0() { return (threadIdx.x >> 7) * 16; }
@@ -48,16 +52,16 @@ __device__ inline int wave_col0() { return (threadIdx.x >> 7) * 16; }
 // XCD is given a contiguous range of tiles, walked in groups of 4 tile-rows,
 // so the workgroups sharing an L2 also share A row panels and B column panels.
 // ---------------------------------------------------------------------------
-__device__ inline void tile_of_block(int nt, int& tm, int& tn) {
-  const int total = nt * nt;
+__device__ inline void tile_of_block(int ntm, int ntn, int& tm, int& tn) {
+  const int total = ntm * ntn;
   int bid = blockIdx.x;
   int t = bid;
   if ((total & 7) == 0) t = (bid & 7) * (total >> 3) + (bid >> 3);
   const int GM = 4;
-  const int per_group = GM * nt;
+  const int per_group = GM * ntn;
   const int group = t / per_group;
   const int first = group * GM;
-  const int gsize = min(nt - first, GM);
+  const int gsize = min(ntm - first, GM);
   const int local = t - group * per_group;
   tm = first + local % gsize;
   tn = local / gsize;
@@ -75,80 +79,95 @@ template <> struct MF<float> {
   static __device__ inline int row(int v, int g) { return 4 * g + v; }
 };
 
-// ---- global -> register slab loads.  Each thread moves RUN consecutive
-// elements (a contiguous run in memory) of the 64 x BKL A slab and of the
-// BKL x 64 B slab; runs fully in bounds and 16-byte aligned use vector loads,
-// the rest guarded element loads (zero fill).  Runs along k (A transposed,
-// B normal) are laid out lane -> column so that each LDS store instruction of
-// a wave writes 64 consecutive elements of one k-row (no bank conflicts).
-template <typename T>
-__device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim, T r[RUN]) {
+// ---- global -> register slab loads.  Each thread moves a run of RUNA (A)
+// or RUNB (B) consecutive elements (contiguous in memory) of the 64 x BKL A
+// slab and the BKL x kTileN B slab; runs fully in bounds and 16-byte aligned use
+// vector loads, the rest guarded element loads (zero fill).  Runs along k
+// (A transposed, B normal) are laid out lane -> row / column so that each LDS
+// store instruction of a wave writes consecutive elements of one k-row.
+template <typename T, int R>
+__device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim, T r[R]) {
   if (full && (((uintptr_t)p) & 15) == 0) {
     typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
     constexpr int W = 16 / sizeof(T);
 #pragma unroll
-    for (int i = 0; i < RUN; i += W) {
+    for (int i = 0; i < R; i += W) {
       v2 x = *(const v2*)(p + i);
 #pragma unroll
       for (int j = 0; j < W; ++j) r[i + j] = x[j];
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < RUN; ++i) r[i] = (i < lim) ? p[i] : T(0);
+    for (int i = 0; i < R; ++i) r[i] = (i < lim) ? p[i] : T(0);
   }
 }
 // A(m,k): TA = false -> A[m + k lda] (run along m), true -> A[k + m lda] (run along k)
 template <typename T, bool TA>
-__device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, int64_t m0, int64_t k0, int t, T r[RUN]) {
+__device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, int64_t m0, int64_t k0, int t,
+                              T r[RUNA]) {
   if (!TA) {
-    const int kk = t >> 4, mm = (t & 15) * RUN;
-    const int64_t k = k0 + kk, m = m0 + mm;
-    const int64_t lim = (k < n) ? min<int64_t>(RUN, n - m) : 0;
-    load_run<T>(A + m + k * lda, lim >= RUN, lim, r);
-  } else {
-    const int mm = t & 63, kk = (t >> 6) * RUN;
+#ifdef PS_ANORM_LANEROW
+    const int mm = t & 63, kk = (t >> 6) * RUNA;
     const int64_t m = m0 + mm, k = k0 + kk;
-    const int64_t lim = (m < n) ? min<int64_t>(RUN, n - k) : 0;
-    load_run<T>(A + k + m * lda, lim >= RUN, lim, r);
+#pragma unroll
+    for (int i = 0; i < RUNA; ++i) r[i] = (m < n && k + i < n) ? A[m + (k + i) * lda] : T(0);
+#else
+    const int kk = t / TPA, mm = (t % TPA) * RUNA;
+    const int64_t k = k0 + kk, m = m0 + mm;
+    const int64_t lim = (k < n) ? min<int64_t>(RUNA, n - m) : 0;
+    load_run<T, RUNA>(A + m + k * lda, lim >= RUNA, lim, r);
+#endif
+  } else {
+    const int mm = t & 63, kk = (t >> 6) * RUNA;
+    const int64_t m = m0 + mm, k = k0 + kk;
+    const int64_t lim = (m < n) ? min<int64_t>(RUNA, n - k) : 0;
+    load_run<T, RUNA>(A + k + m * lda, lim >= RUNA, lim, r);
   }
 }
 template <typename T, bool TA>
-__device__ inline void store_a(T* As, int t, const T r[RUN]) {
+__device__ inline void store_a(T* As, int t, const T r[RUNA]) {
   if (!TA) {
-    const int kk = t >> 4, mm = (t & 15) * RUN;
+#ifdef PS_ANORM_LANEROW
+    const int mm = t & 63, kk = (t >> 6) * RUNA;
 #pragma unroll
-    for (int i = 0; i < RUN; ++i) As[kk * LROW + mm + i] = r[i];
+    for (int i = 0; i < RUNA; ++i) As[(kk + i) * LROWA + mm] = r[i];
+#else
+    const int kk = t / TPA, mm = (t % TPA) * RUNA;
+#pragma unroll
+    for (int i = 0; i < RUNA; ++i) As[kk * LROWA + mm + i] = r[i];
+#endif
   } else {
-    const int mm = t & 63, kk = (t >> 6) * RUN;
+    const int mm = t & 63, kk = (t >> 6) * RUNA;
 #pragma unroll
-    for (int i = 0; i < RUN; ++i) As[(kk + i) * LROW + mm] = r[i];
+    for (int i = 0; i < RUNA; ++i) As[(kk + i) * LROWA + mm] = r[i];
   }
 }
 // B(k,j): TB = false -> B[k + j ldb] (run along k), true -> B[j + k ldb] (run along j)
 template <typename T, bool TB>
-__device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, int64_t n0, int64_t k0, int t, T r[RUN]) {
+__device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, int64_t n0, int64_t k0, int t,
+                              T r[RUNB]) {
   if (!TB) {
-    const int jj = t & 63, kk = (t >> 6) * RUN;
+    const int jj = t % kTileN, kk = (t / kTileN) * RUNB;
     const int64_t j = n0 + jj, k = k0 + kk;
-    const int64_t lim = (j < n) ? min<int64_t>(RUN, n - k) : 0;
-    load_run<T>(B + k + j * ldb, lim >= RUN, lim, r);
+    const int64_t lim = (j < n) ? min<int64_t>(RUNB, n - k) : 0;
+    load_run<T, RUNB>(B + k + j * ldb, lim >= RUNB, lim, r);
   } else {
-    const int kk = t >> 4, jj = (t & 15) * RUN;
+    const int kk = t / TPB, jj = (t % TPB) * RUNB;
     const int64_t k = k0 + kk, j = n0 + jj;
-    const int64_t lim = (k < n) ? min<int64_t>(RUN, n - j) : 0;
-    load_run<T>(B + j + k * ldb, lim >= RUN, lim, r);
+    const int64_t lim = (k < n) ? min<int64_t>(RUNB, n - j) : 0;
+    load_run<T, RUNB>(B + j + k * ldb, lim >= RUNB, lim, r);
   }
 }
 template <typename T, bool TB>
-__device__ inline void store_b(T* Bs, int t, const T r[RUN]) {
+__device__ inline void store_b(T* Bs, int t, const T r[RUNB]) {
   if (!TB) {
-    const int jj = t & 63, kk = (t >> 6) * RUN;
+    const int jj = t % kTileN, kk = (t / kTileN) * RUNB;
 #pragma unroll
-    for (int i = 0; i < RUN; ++i) Bs[(kk + i) * LROW + jj] = r[i];
+    for (int i = 0; i < RUNB; ++i) Bs[(kk + i) * LROWB + jj] = r[i];
   } else {
-    const int kk = t >> 4, jj = (t & 15) * RUN;
+    const int kk = t / TPB, jj = (t % TPB) * RUNB;
 #pragma unroll
-    for (int i = 0; i < RUN; ++i) Bs[kk * LROW + jj + i] = r[i];
+    for (int i = 0; i < RUNB; ++i) Bs[kk * LROWB + jj + i] = r[i];
   }
 }
 
@@ -159,8 +178,8 @@ __device__ inline void mma_slab(const T* as, const T* bs, int wr, int wc, int g,
   for (int ks = 0; ks < BKL / 4; ++ks) {
     const int k = ks * 4 + g;
     const int ch = (ks % KCH) * 2;
-    const T a0 = as[k * LROW + wr + c], a1 = as[k * LROW + wr + 16 + c];
-    const T b0 = bs[k * LROW + wc + c];
+    const T a0 = as[k * LROWA + wr + c], a1 = as[k * LROWA + wr + 16 + c];
+    const T b0 = bs[k * LROWB + wc + c];
     acc[ch] = MF<T>::mma(a0, b0, acc[ch]);
     acc[ch + 1] = MF<T>::mma(a1, b0, acc[ch + 1]);
   }
@@ -174,17 +193,16 @@ __device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const 
                                     int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
-  T* const As0 = (T*)smem;
-  T* const Bs0 = (T*)smem + SLAB;
+  T* const S = (T*)smem;   // stage q: A slab at S + q STAGE, B slab after it
   typename MF<T>::V chains[2 * KCH];
 #pragma unroll
   for (int i = 0; i < 2 * KCH; ++i) chains[i] = typename MF<T>::V{0, 0, 0, 0};
   const int64_t nk = (n + BKL - 1) / BKL;
-  T ra[RUN], rb[RUN];
+  T ra[RUNA], rb[RUNB];
   load_a<T, TA>(A, lda, n, m0, 0, t, ra);
   load_b<T, TB>(B, ldb, n, n0, 0, t, rb);
-  store_a<T, TA>(As0, t, ra);
-  store_b<T, TB>(Bs0, t, rb);
+  store_a<T, TA>(S, t, ra);
+  store_b<T, TB>(S + SLABA, t, rb);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int cur = (int)(kt & 1);
@@ -193,10 +211,10 @@ __device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const 
       load_a<T, TA>(A, lda, n, m0, (kt + 1) * BKL, t, ra);
       load_b<T, TB>(B, ldb, n, n0, (kt + 1) * BKL, t, rb);
     }
-    mma_slab<T>(As0 + cur * 2 * SLAB, Bs0 + cur * 2 * SLAB, wr, wc, g, c, chains);
+    mma_slab<T>(S + cur * STAGE, S + cur * STAGE + SLABA, wr, wc, g, c, chains);
     if (more) {
-      store_a<T, TA>(As0 + (cur ^ 1) * 2 * SLAB, t, ra);
-      store_b<T, TB>(Bs0 + (cur ^ 1) * 2 * SLAB, t, rb);
+      store_a<T, TA>(S + (cur ^ 1) * STAGE, t, ra);
+      store_b<T, TB>(S + (cur ^ 1) * STAGE + SLABA, t, rb);
     }
     __syncthreads();
   }
@@ -439,13 +457,13 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
   if (t_out < 2) return;
   // pass 2 (row-major): pack into the K-contiguous low-precision layout
   if (t_out == 2) {
-    const int r = t >> 3, seg = (t & 7) * 8;
+    const int r = t / (kTileN / 8), seg = (t % (kTileN / 8)) * 8;   // NT = 64 rows x kTileN/8 segments
     union { uint4 q; uint16_t h[8]; } o;
 #pragma unroll
     for (int e = 0; e < 8; ++e) o.h[e] = bf16_bits_rne((float)Cs[(seg + e) * CSTR + r]);
     *(uint4*)((uint16_t*)h.pout + (m0 + r) * Kp + n0 + seg) = o.q;
-  } else if (t < 128) {
-    const int r = t >> 1, blk = t & 1;
+  } else if (t < kTileM * kTileN / 32) {
+    const int r = t % kTileM, blk = t / kTileM;   // one E8M0 block = 32 columns of a row
     float vals[32];
     float amax = 0.0f;
 #pragma unroll
@@ -593,13 +611,22 @@ __device__ inline void plan_matrix(const PlanArgs& a, const Layout& L, char* ws,
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) mx[ii] = 0.0;
     for (int64_t c = t; c < n; c += NT) {
+      double sum[8];
 #pragma unroll
-      for (int ii = 0; ii < 8; ++ii) {
-        if (i0 + ii > a.nB) break;
-        double v = 0.0;
-        for (int64_t ch = 0; ch < nch; ++ch) v += colsum[((int64_t)(i0 + ii) * nch + ch) * n + c];
-        if (v > mx[ii] || v != v) mx[ii] = v;
+      for (int ii = 0; ii < 8; ++ii) sum[ii] = 0.0;
+      // all (block, chunk) loads of this column are independent and predicated,
+      // so they are in flight together
+#pragma unroll 4
+      for (int64_t ch = 0; ch < nch; ++ch) {
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii) {
+          const double v = (i0 + ii <= a.nB) ? colsum[((int64_t)(i0 + ii) * nch + ch) * n + c] : 0.0;
+          sum[ii] += v;
+        }
       }
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii)
+        if (sum[ii] > mx[ii] || sum[ii] != sum[ii]) mx[ii] = sum[ii];
     }
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) {
@@ -621,29 +648,43 @@ __device__ inline void plan_matrix(const PlanArgs& a, const Layout& L, char* ws,
     }
     __syncthreads();
   }
+  // plan in LDS (thread 0), then copied to the workspace Plan by all threads
+  __shared__ int s_tier[PS_MAX_BLOCKS];
+  __shared__ double s_u[PS_MAX_BLOCKS];
+  __shared__ int s_nu;
+  __shared__ double s_ny;
   if (t == 0) {
-  Plan* P = (Plan*)(ws + L.off_plan);
-  double nb[PS_MAX_BLOCKS];
-  for (int i = 0; i < a.nB; ++i) nb[i] = norms[i];
-  if (a.trivial_last) nb[a.r] = a.abs_cm;
-  const double ny = norms[a.nB];
-  for (int i = 0; i <= a.r; ++i) P->normB[i] = nb[i];
-  P->normY = ny;
-  if (a.use_override) {
-    for (int i = 0; i <= a.r; ++i) {
-      P->tier[i] = (i == 0) ? a.working : a.override_tier[i];
-      P->u[i] = tier_unit_roundoff(P->tier[i]);
+    // norms[nB] holds ||Y||; with s | m, nB = r and slot r then receives
+    // ||B_r|| = |c_m| (B_r = c_m I), so ||Y|| is read out first
+    const double ny = norms[a.nB];
+    s_ny = ny;
+    if (a.trivial_last) norms[a.r] = a.abs_cm;
+    if (a.use_override) {
+      for (int i = 0; i <= a.r; ++i) {
+        s_tier[i] = (i == 0) ? a.working : a.override_tier[i];
+        s_u[i] = tier_unit_roundoff(s_tier[i]);
+      }
+      s_nu = a.r + 1;
+      for (int i = 1; i <= a.r; ++i) if (s_tier[i] != a.working) { s_nu = i; break; }
+    } else if (a.mode == PS_MODE_FIXED) {
+      for (int i = 0; i <= a.r; ++i) { s_tier[i] = a.working; s_u[i] = tier_unit_roundoff(a.working); }
+      s_nu = a.r + 1;
+    } else {
+      int nu;
+      plan_tiers(a.r, norms, ny, a.working, a.mask, a.delta, s_tier, s_u, &nu);
+      s_nu = nu;
     }
-    P->nu = a.r + 1;
-    for (int i = 1; i <= a.r; ++i) if (P->tier[i] != a.working) { P->nu = i; break; }
-  } else if (a.mode == PS_MODE_FIXED) {
-    for (int i = 0; i <= a.r; ++i) { P->tier[i] = a.working; P->u[i] = tier_unit_roundoff(a.working); }
-    P->nu = a.r + 1;
-  } else {
-    int nu;
-    plan_tiers(a.r, nb, ny, a.working, a.mask, a.delta, P->tier, P->u, &nu);
-    P->nu = nu;
   }
+  __syncthreads();
+  Plan* P = (Plan*)(ws + L.off_plan);
+  if (t <= a.r) {
+    P->tier[t] = s_tier[t];
+    P->u[t] = s_u[t];
+    P->normB[t] = norms[t];
+  }
+  if (t == 0) {
+    P->normY = s_ny;
+    P->nu = s_nu;
   }
   __syncthreads();
 }

@@ -32,24 +32,24 @@
 namespace psk {
 
 // ---------------------------------------------------------------------------
-// k_gemm: one 64x64 tile per workgroup
+// k_gemm: one 64x32 tile per workgroup
 // ---------------------------------------------------------------------------
 template <typename T, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void k_gemm(int64_t n, MatArg A, MatArg B, MatArg C, double alpha, int accumulate) {
   __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
-  const int nt = (int)((n + kTile - 1) / kTile);
+  const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
   int tm, tn;
-  tile_of_block(nt, tm, tn);
+  tile_of_block(ntm, ntn, tm, tn);
   const int64_t b = blockIdx.z;
   gemm_tile<T, TA, TB>((const T*)A.p + b * A.stride, A.ld, (const T*)B.p + b * B.stride, B.ld,
-                       (T*)C.p + b * C.stride, C.ld, n, (int64_t)tm * kTile, (int64_t)tn * kTile, alpha, accumulate,
-                       smem);
+                       (T*)C.p + b * C.stride, C.ld, n, (int64_t)tm * kTileM, (int64_t)tn * kTileN, alpha,
+                       accumulate, smem);
 }
 
 hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, MatArg B, int transB,
                        MatArg C, double alpha, int accumulate, hipStream_t st) {
-  const int nt = (int)((n + kTile - 1) / kTile);
-  dim3 grid(nt * nt, 1, batch), block(NT);
+  const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
+  dim3 grid(ntm * ntn, 1, batch), block(NT);
 #define PS_LAUNCH_GEMM(T, ta, tb) \
   hipLaunchKernelGGL((k_gemm<T, ta, tb>), grid, block, 0, st, n, A, B, C, alpha, accumulate)
   if (working == 0) {
@@ -75,9 +75,9 @@ __global__ __launch_bounds__(NT) void k_horner(HornerArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   const Layout& L = a.L;
-  const int nt = (int)((a.n + kTile - 1) / kTile);
+  const int ntm = (int)((a.n + kTileM - 1) / kTileM), ntn = (int)((a.n + kTileN - 1) / kTileN);
   int tm, tn;
-  tile_of_block(nt, tm, tn);
+  tile_of_block(ntm, ntn, tm, tn);
   const int64_t b = blockIdx.z;
   char* ws = a.ws + b * a.ws_stride;
   const Plan* plan = (const Plan*)(ws + L.off_plan);
@@ -99,12 +99,12 @@ __global__ __launch_bounds__(NT) void k_horner(HornerArgs a) {
   h.pout = ws + a.off_pout;
   h.outw = a.final_out ? ((W*)a.out.p + b * a.out.stride) : (W*)(ws + a.off_pout);
   h.ldo = a.final_out ? a.out.ld : a.n;
-  horner_tile<W>(h, (int64_t)tm * kTile, (int64_t)tn * kTile, smem);
+  horner_tile<W>(h, (int64_t)tm * kTileM, (int64_t)tn * kTileN, smem);
 }
 
 hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_t st) {
-  const int nt = (int)((a.n + kTile - 1) / kTile);
-  dim3 grid(nt * nt, 1, batch), block(NT);
+  const int ntm = (int)((a.n + kTileM - 1) / kTileM), ntn = (int)((a.n + kTileN - 1) / kTileN);
+  dim3 grid(ntm * ntn, 1, batch), block(NT);
   if (working == 0) hipLaunchKernelGGL(k_horner<double>, grid, block, 0, st, a);
   else hipLaunchKernelGGL(k_horner<float>, grid, block, 0, st, a);
   return hipGetLastError();
