@@ -23,7 +23,10 @@ constexpr int NW = NT / 64;           // waves per workgroup
 #ifndef PS_KCHAINS
 #define PS_KCHAINS 2
 #endif
-constexpr int BKL = 32;               // K slab of the LDS main loop
+#ifndef PS_BKL
+#define PS_BKL 32
+#endif
+constexpr int BKL = PS_BKL;           // K slab of the LDS main loop
 constexpr int LROWA = kTileM + 16;    // padded LDS rows (elements): a fragment read covers k-rows
 constexpr int LROWB = kTileN + 16;    //   k and k+1 in one half-wave pass; 640 B (384 B) apart, the
                                       //   two rows land on disjoint banks
@@ -85,9 +88,9 @@ template <> struct MF<float> {
 // vector loads, the rest guarded element loads (zero fill).  Runs along k
 // (A transposed, B normal) are laid out lane -> row / column so that each LDS
 // store instruction of a wave writes consecutive elements of one k-row.
-template <typename T, int R>
+template <typename T, int R, bool FULL>
 __device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim, T r[R]) {
-  if (full && (((uintptr_t)p) & 15) == 0) {
+  if (FULL || (full && (((uintptr_t)p) & 15) == 0)) {
     typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
     constexpr int W = 16 / sizeof(T);
 #pragma unroll
@@ -102,7 +105,7 @@ __device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim,
   }
 }
 // A(m,k): TA = false -> A[m + k lda] (run along m), true -> A[k + m lda] (run along k)
-template <typename T, bool TA>
+template <typename T, bool TA, bool FULL>
 __device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, int64_t m0, int64_t k0, int t,
                               T r[RUNA]) {
   if (!TA) {
@@ -115,13 +118,13 @@ __device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, i
     const int kk = t / TPA, mm = (t % TPA) * RUNA;
     const int64_t k = k0 + kk, m = m0 + mm;
     const int64_t lim = (k < n) ? min<int64_t>(RUNA, n - m) : 0;
-    load_run<T, RUNA>(A + m + k * lda, lim >= RUNA, lim, r);
+    load_run<T, RUNA, FULL>(A + m + k * lda, lim >= RUNA, lim, r);
 #endif
   } else {
     const int mm = t & 63, kk = (t >> 6) * RUNA;
     const int64_t m = m0 + mm, k = k0 + kk;
     const int64_t lim = (m < n) ? min<int64_t>(RUNA, n - k) : 0;
-    load_run<T, RUNA>(A + k + m * lda, lim >= RUNA, lim, r);
+    load_run<T, RUNA, FULL>(A + k + m * lda, lim >= RUNA, lim, r);
   }
 }
 template <typename T, bool TA>
@@ -143,19 +146,19 @@ __device__ inline void store_a(T* As, int t, const T r[RUNA]) {
   }
 }
 // B(k,j): TB = false -> B[k + j ldb] (run along k), true -> B[j + k ldb] (run along j)
-template <typename T, bool TB>
+template <typename T, bool TB, bool FULL>
 __device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, int64_t n0, int64_t k0, int t,
                               T r[RUNB]) {
   if (!TB) {
     const int jj = t % kTileN, kk = (t / kTileN) * RUNB;
     const int64_t j = n0 + jj, k = k0 + kk;
     const int64_t lim = (j < n) ? min<int64_t>(RUNB, n - k) : 0;
-    load_run<T, RUNB>(B + k + j * ldb, lim >= RUNB, lim, r);
+    load_run<T, RUNB, FULL>(B + k + j * ldb, lim >= RUNB, lim, r);
   } else {
     const int kk = t / TPB, jj = (t % TPB) * RUNB;
     const int64_t k = k0 + kk, j = n0 + jj;
     const int64_t lim = (k < n) ? min<int64_t>(RUNB, n - j) : 0;
-    load_run<T, RUNB>(B + j + k * ldb, lim >= RUNB, lim, r);
+    load_run<T, RUNB, FULL>(B + j + k * ldb, lim >= RUNB, lim, r);
   }
 }
 template <typename T, bool TB>
@@ -186,10 +189,11 @@ __device__ inline void mma_slab(const T* as, const T* bs, int wr, int wc, int g,
 }
 
 // ---- FP64 / FP32 main loop: acc[bi] += A-tile x B-tile over all of K for the
-// wave's two 16x16 blocks.  Two LDS stages; the global loads of slab kt+1 are
-// issued before the MFMAs of slab kt and stored to the other stage after them.
-template <typename T, bool TA, bool TB>
-__device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+// wave's two 16x16 blocks.  Two LDS stages and two register sets: the global
+// loads of slab kt+2 are issued before the MFMAs of slab kt, and slab kt+1
+// (loaded one iteration earlier) is stored to the other stage after them.
+template <typename T, bool TA, bool TB, bool FULL>
+__device__ inline void mainloop_lds_impl(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
                                     int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
@@ -198,25 +202,35 @@ __device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const 
 #pragma unroll
   for (int i = 0; i < 2 * KCH; ++i) chains[i] = typename MF<T>::V{0, 0, 0, 0};
   const int64_t nk = (n + BKL - 1) / BKL;
-  T ra[RUNA], rb[RUNB];
-  load_a<T, TA>(A, lda, n, m0, 0, t, ra);
-  load_b<T, TB>(B, ldb, n, n0, 0, t, rb);
-  store_a<T, TA>(S, t, ra);
-  store_b<T, TB>(S + SLABA, t, rb);
+  // two register sets: the global loads of slab kt+2 are issued while slab
+  // kt+1 is still in flight, so each load has two slab times to arrive.  The
+  // loads and LDS stores are unconditional (past the last slab the last slab
+  // is fetched again and stored into the idle stage): a branch around them
+  // would make the memory-counter wait before each store cover the newer
+  // loads as well, which cancels the prefetch.
+  T ra0[RUNA], rb0[RUNB], ra1[RUNA], rb1[RUNB];
+  load_a<T, TA, FULL>(A, lda, n, m0, 0, t, ra0);
+  load_b<T, TB, FULL>(B, ldb, n, n0, 0, t, rb0);
+  const int64_t k1 = min<int64_t>(1, nk - 1) * BKL;
+  load_a<T, TA, FULL>(A, lda, n, m0, k1, t, ra1);
+  load_b<T, TB, FULL>(B, ldb, n, n0, k1, t, rb1);
+  store_a<T, TA>(S, t, ra0);
+  store_b<T, TB>(S + SLABA, t, rb0);
   __syncthreads();
-  for (int64_t kt = 0; kt < nk; ++kt) {
+  auto step = [&](int64_t kt, T* rna, T* rnb, const T* rfa, const T* rfb) {
+    // rna/rnb: free set (receives slab kt+2); rfa/rfb: slab kt+1, in flight
     const int cur = (int)(kt & 1);
-    const bool more = kt + 1 < nk;
-    if (more) {
-      load_a<T, TA>(A, lda, n, m0, (kt + 1) * BKL, t, ra);
-      load_b<T, TB>(B, ldb, n, n0, (kt + 1) * BKL, t, rb);
-    }
-    mma_slab<T>(S + cur * STAGE, S + cur * STAGE + SLABA, wr, wc, g, c, chains);
-    if (more) {
-      store_a<T, TA>(S + (cur ^ 1) * STAGE, t, ra);
-      store_b<T, TB>(S + (cur ^ 1) * STAGE + SLABA, t, rb);
-    }
+    const int64_t kn = min<int64_t>(kt + 2, nk - 1) * BKL;
+    load_a<T, TA, FULL>(A, lda, n, m0, kn, t, rna);
+    load_b<T, TB, FULL>(B, ldb, n, n0, kn, t, rnb);
+    if (kt < nk) mma_slab<T>(S + cur * STAGE, S + cur * STAGE + SLABA, wr, wc, g, c, chains);
+    store_a<T, TA>(S + (cur ^ 1) * STAGE, t, rfa);
+    store_b<T, TB>(S + (cur ^ 1) * STAGE + SLABA, t, rfb);
     __syncthreads();
+  };
+  for (int64_t kt = 0; kt < nk; kt += 2) {
+    step(kt, ra0, rb0, ra1, rb1);
+    step(kt + 1, ra1, rb1, ra0, rb0);
   }
   acc[0] = chains[0];
   acc[1] = chains[1];
@@ -225,6 +239,24 @@ __device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const 
     acc[0] += chains[2 * ch];
     acc[1] += chains[2 * ch + 1];
   }
+}
+
+// Full-tile fast path: when every tile and K slab is whole (n a multiple of 64)
+// and both operands allow aligned 16-byte loads at every run, the slab loads
+// are unconditional vector loads.  Besides saving the bounds arithmetic this
+// keeps the loop free of divergent branches around the loads, so the memory
+// counter waits before each LDS store cover only the slab being stored and
+// the next slab's loads stay in flight.
+template <typename T>
+__device__ inline bool full_tiles(const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n) {
+  constexpr int64_t V = 16 / sizeof(T);
+  return (n % 64) == 0 && (lda % V) == 0 && (ldb % V) == 0 && ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0;
+}
+template <typename T, bool TA, bool TB>
+__device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                    int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
+  if (full_tiles(A, lda, B, ldb, n)) mainloop_lds_impl<T, TA, TB, true>(A, lda, B, ldb, n, m0, n0, smem, acc);
+  else mainloop_lds_impl<T, TA, TB, false>(A, lda, B, ldb, n, m0, n0, smem, acc);
 }
 
 // accumulator fragments -> LDS tile Cs[col * CSTR + row] (type W)
@@ -266,73 +298,138 @@ __device__ inline uint16_t bf16_bits_rne(float x) {
   return (uint16_t)(u >> 16);
 }
 
-// P: row-major [Mp][Kp] bf16 bits; Yb: [Np][Kp] (column j of Y contiguous in k)
-__device__ inline void mainloop_bf16(const uint16_t* __restrict__ P, const uint16_t* __restrict__ Yb, int64_t Kp,
-                                     int64_t n, int64_t m0, int64_t n0, f4v acc[2]) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const int wr = wave_row0(), wc = wave_col0();
-  acc[0] = f4v{0, 0, 0, 0};
-  acc[1] = f4v{0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < n; k0 += 32) {
-    const int64_t kb = k0 + 8 * g;
-    union U { uint4 q; uint16_t h[8]; bf8v v; } a[2], bb;
+// Register pipeline over K slabs for the low-precision main loops: the loads
+// of PF slabs are in flight while one slab is multiplied, so a wave waits for
+// memory about once per PF slabs instead of once per slab.  The ring slots
+// are expanded by template recursion, so every slot index is a compile-time
+// constant and the ring lives in VGPRs.
+// ---- BF16 / FP8 main loop.  The operands are packed K-contiguous: row r of
+// P_i (and column j of Y) is a run of Kp elements, FP8 rows followed by E8M0
+// scales (one byte per 32 elements).  A slab is 128 bytes of K per row (FP8:
+// 128 elements, BF16: 64); the workgroup stages the 64 A rows and 64 B
+// columns of a slab in LDS (each thread one 16-byte chunk of each, K beyond n
+// zeroed there), so every byte is fetched from memory once per workgroup and
+// by wide coalesced loads; the waves then read their MFMA fragments from LDS.
+// Two LDS stages and two register sets, as in the FP64/FP32 loop.
+constexpr int LP_RS = 144;                      // LDS row stride (bytes): 16-byte fragment reads of
+                                                //   16 consecutive rows hit distinct banks
+constexpr int LP_OPER = 64 * LP_RS;             // one operand slab
+constexpr int LP_STAGE = 2 * LP_OPER + 2 * 64 * 4;   // A, B, then A and B scale words
+static_assert(2 * LP_STAGE <= SMEM_BYTES, "low-precision stages fit the tile LDS");
+
+struct LpRegs { uint4 a, b; uint32_t s; };
+
+// zero the elements >= n of a 16-byte chunk whose first element is k (EB bytes per element)
+template <int EB>
+__device__ inline uint4 lp_mask(uint4 v, int64_t k, int64_t n) {
+  constexpr int PW = 4 / EB;   // elements per 32-bit word
+  union { uint4 q; uint32_t w[4]; } u;
+  u.q = v;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) a[bi].q = *(const uint4*)(P + (m0 + wr + 16 * bi + c) * Kp + kb);
-    bb.q = *(const uint4*)(Yb + (n0 + wc + c) * Kp + kb);
-    if (kb + 8 > n) {
+  for (int wd = 0; wd < 4; ++wd) {
+    const int64_t nv = n - (k + PW * wd);
+    const uint32_t mk = nv >= PW ? 0xffffffffu : nv <= 0 ? 0u : (1u << (8 * EB * nv)) - 1u;
+    u.w[wd] &= mk;
+  }
+  return u.q;
+}
+
+template <bool FP8>
+__device__ inline void lp_load(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+                               const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t rsb,
+                               int64_t Ks, int64_t n, int64_t m0, int64_t n0, int64_t i, int t, LpRegs& r) {
+  constexpr int EB = FP8 ? 1 : 2;
+  const int row = t >> 3, ch = t & 7;
+  const int64_t kbyte = 128 * i + 16 * ch;
+  r.a = *(const uint4*)(A + (m0 + row) * rsb + kbyte);
+  r.b = *(const uint4*)(B + (n0 + row) * rsb + kbyte);
+  const int64_t k = kbyte / EB;
+  if (k + 16 / EB > n) {
+    r.a = lp_mask<EB>(r.a, k, n);
+    r.b = lp_mask<EB>(r.b, k, n);
+  }
+  if (FP8 && t < 128) {
+    // one word = the 4 E8M0 scales of this slab for one row of A (t < 64) or
+    // one column of B; blocks wholly past n get the neutral scale 2^0
+    r.s = (t < 64) ? *(const uint32_t*)(As + (m0 + t) * Ks + 4 * i)
+                   : *(const uint32_t*)(Bs + (n0 + t - 64) * Ks + 4 * i);
 #pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (kb + e >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb.h[e] = 0; }
-    }
-    acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0].v, bb.v, acc[0], 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1].v, bb.v, acc[1], 0, 0, 0);
+    for (int bk = 0; bk < 4; ++bk)
+      if ((4 * i + bk) * 32 >= n) r.s = (r.s & ~(0xffu << (8 * bk))) | (127u << (8 * bk));
   }
 }
 
-// P8: [Mp][Kp] E4M3 bytes, Ps: [Mp][Kp/32] E8M0 scales; Y8, Ys likewise per column.
+template <bool FP8>
+__device__ inline void lp_store(char* st, int t, const LpRegs& r) {
+  const int row = t >> 3, ch = t & 7;
+  *(uint4*)(st + row * LP_RS + 16 * ch) = r.a;
+  *(uint4*)(st + LP_OPER + row * LP_RS + 16 * ch) = r.b;
+  if (FP8 && t < 128) *(uint32_t*)(st + 2 * LP_OPER + 4 * t) = r.s;
+}
+
+template <bool FP8>
+__device__ inline void lp_mma(const char* st, int wr, int wc, int g, int c, f4v acc[2]) {
+  const char* a0p = st + (wr + c) * LP_RS + 16 * g;
+  const char* a1p = a0p + 16 * LP_RS;
+  const char* bp = st + LP_OPER + (wc + c) * LP_RS + 16 * g;
+  if (FP8) {
+    union U { uint4 q[2]; i8v v; } a0, a1, bb;
+    a0.q[0] = *(const uint4*)a0p; a0.q[1] = *(const uint4*)(a0p + 64);
+    a1.q[0] = *(const uint4*)a1p; a1.q[1] = *(const uint4*)(a1p + 64);
+    bb.q[0] = *(const uint4*)bp;  bb.q[1] = *(const uint4*)(bp + 64);
+    const uint8_t* sc = (const uint8_t*)(st + 2 * LP_OPER);
+    const int sa0 = sc[(wr + c) * 4 + g], sa1 = sc[(wr + 16 + c) * 4 + g];
+    const int sb = sc[256 + (wc + c) * 4 + g];
+    acc[0] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a0.v, bb.v, acc[0], 0, 0, 0, sa0, 0, sb);
+    acc[1] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a1.v, bb.v, acc[1], 0, 0, 0, sa1, 0, sb);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      union U { uint4 q; bf8v v; } a0, a1, bb;
+      a0.q = *(const uint4*)(a0p + 64 * j);
+      a1.q = *(const uint4*)(a1p + 64 * j);
+      bb.q = *(const uint4*)(bp + 64 * j);
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0.v, bb.v, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1.v, bb.v, acc[1], 0, 0, 0);
+    }
+  }
+}
+
+// FP8 (FP8 = true): A = P8 [Mp][Kp] bytes, As = its scales [Mp][Kp/32], B = Y8, Bs = its scales.
+// BF16: A = P [Mp][Kp] bf16 bits, B = Yb [Mp][Kp]; As, Bs unused.
 // The scaled f8f6f4 16x16x128 MFMA orders K inside a 128-slab as: lane group
 // g = l/16 holds slab elements [16g, 16g+16) in bytes 0..15 and
 // [64+16g, 64+16g+16) in bytes 16..31, and the E8M0 scale of the 32-element
 // slab block b of row (column) l%16 is the one passed by lane l%16 + 16b.
-// Loading each lane's halves from those two offsets makes every hardware
+// Reading each lane's halves from those two offsets makes every hardware
 // scale block coincide with one 32-element block of the packed layout.
-__device__ inline void mainloop_fp8(const uint8_t* __restrict__ P8, const uint8_t* __restrict__ Ps,
-                                    const uint8_t* __restrict__ Y8, const uint8_t* __restrict__ Ys, int64_t Kp,
-                                    int64_t n, int64_t m0, int64_t n0, f4v acc[2]) {
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+template <bool FP8>
+__device__ inline void mainloop_lowp(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+                                     const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t Kp,
+                                     int64_t n, int64_t m0, int64_t n0, char* smem, f4v acc[2]) {
+  const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
+  const int64_t rsb = FP8 ? Kp : 2 * Kp;             // row stride in bytes
   const int64_t Ks = Kp / 32;
+  const int64_t ns = FP8 ? (n + 127) / 128 : (n + 63) / 64;
   acc[0] = f4v{0, 0, 0, 0};
   acc[1] = f4v{0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < n; k0 += 128) {
-    const int64_t klo = k0 + 16 * g;        // bytes 0..15
-    const int64_t khi = k0 + 64 + 16 * g;   // bytes 16..31
-    const int64_t kblk = k0 / 32 + g;       // scale block this lane supplies
-    union U { uint4 q[2]; uint8_t h[32]; i8v v; } a[2], bb;
-    int sa[2], sb;
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      const int64_t r = m0 + wr + 16 * bi + c;
-      a[bi].q[0] = *(const uint4*)(P8 + r * Kp + klo);
-      a[bi].q[1] = *(const uint4*)(P8 + r * Kp + khi);
-      sa[bi] = Ps[r * Ks + kblk];
-    }
-    {
-      const int64_t col = n0 + wc + c;
-      bb.q[0] = *(const uint4*)(Y8 + col * Kp + klo);
-      bb.q[1] = *(const uint4*)(Y8 + col * Kp + khi);
-      sb = Ys[col * Ks + kblk];
-    }
-    if (k0 + 128 > n) {
-      if (kblk * 32 >= n) { sa[0] = sa[1] = sb = 127; }
-#pragma unroll
-      for (int e = 0; e < 32; ++e) {
-        const int64_t k = (e < 16) ? klo + e : khi + (e - 16);
-        if (k >= n) { a[0].h[e] = 0; a[1].h[e] = 0; bb.h[e] = 0; }
-      }
-    }
-    acc[0] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[0].v, bb.v, acc[0], 0, 0, 0, sa[0], 0, sb);
-    acc[1] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[1].v, bb.v, acc[1], 0, 0, 0, sa[1], 0, sb);
+  // loads and stores unconditional, as in mainloop_lds_impl
+  LpRegs r0, r1;
+  lp_load<FP8>(A, As, B, Bs, rsb, Ks, n, m0, n0, 0, t, r0);
+  lp_load<FP8>(A, As, B, Bs, rsb, Ks, n, m0, n0, min<int64_t>(1, ns - 1), t, r1);
+  lp_store<FP8>(smem, t, r0);
+  __syncthreads();
+  auto step = [&](int64_t kt, LpRegs& rn, const LpRegs& rf) {
+    const int cur = (int)(kt & 1);
+    lp_load<FP8>(A, As, B, Bs, rsb, Ks, n, m0, n0, min<int64_t>(kt + 2, ns - 1), t, rn);
+    if (kt < ns) lp_mma<FP8>(smem + cur * LP_STAGE, wr, wc, g, c, acc);
+    lp_store<FP8>(smem + (cur ^ 1) * LP_STAGE, t, rf);
+    __syncthreads();
+  };
+  for (int64_t kt = 0; kt < ns; kt += 2) {
+    step(kt, r0, r1);
+    step(kt + 1, r1, r0);
   }
 }
 
@@ -426,11 +523,12 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
     frag_to_cs<float, W>(acc, Cs, 1.0);
   } else if (t_in == 2) {
     f4v acc[2];
-    mainloop_bf16((const uint16_t*)h.pin, h.ybf16, Kp, n, m0, n0, acc);
+    mainloop_lowp<false>((const uint8_t*)h.pin, nullptr, (const uint8_t*)h.ybf16, nullptr, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else if (t_in == 3) {
     f4v acc[2];
-    mainloop_fp8((const uint8_t*)h.pin, (const uint8_t*)h.pin + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, acc);
+    const uint8_t* p8 = (const uint8_t*)h.pin;
+    mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   }
   __syncthreads();
@@ -439,12 +537,21 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
   const int t = threadIdx.x;
   const int row = t & 63;
   const int64_t gr = m0 + row;
+  W bq[TILE_Q];   // all loads of B_{i-1} issued before any store
+#pragma unroll
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int64_t gc = n0 + (t >> 6) + NW * q;
+    const bool in = gr < n && gc < n;
+    const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
+    bq[q] = in ? x : W(0);
+  }
+#pragma unroll
   for (int q = 0; q < TILE_Q; ++q) {
     const int col = (t >> 6) + NW * q;
     const int64_t gc = n0 + col;
     const bool in = gr < n && gc < n;
     const W v = (t_in < 0) ? W(0) : Cs[col * CSTR + row];
-    const W bb = in ? h.bsrc[gr + gc * n] : W(0);
+    const W bb = bq[q];
     if (t_out == WT) {
       if (in) h.outw[gr + gc * h.ldo] = bb + v;
     } else if (t_out == 1) {
@@ -514,77 +621,93 @@ __device__ inline void assemble_column(const AssembleArgs& a, const Coefs& cf, c
   uint8_t* y8 = (uint8_t*)(ws + L.off_yfp8);
   uint8_t* y8s = (uint8_t*)(ws + L.off_yfp8s);
 
-  // this wave's rows: row chunk `chunk` (kRowChunk rows) of column `col`
+  // this wave's rows: row chunk `chunk` (kRowChunk rows) of column `col`,
+  // RPL rows per lane, 64 apart
+  constexpr int RPL = kRowChunk / 64;
   const int64_t r_begin = chunk * kRowChunk;
   const int64_t r_end = min<int64_t>(n, r_begin + kRowChunk);
-  const int64_t r_stop = r_begin + round_up(r_end - r_begin, 64);   // all lanes step together
   const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
+  int64_t rw[RPL];
+  bool valid[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    rw[q] = r_begin + lane + 64 * q;
+    valid[q] = rw[q] < r_end;
+  }
+  // this lane's elements of column `col` of X_j; the loads are unconditional
+  // (rows past the end read row r_begin) so that all of them are in flight
+  // together
+  auto load_x = [&](int j, W out[RPL]) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int64_t rr = valid[q] ? rw[q] : r_begin;
+      const W x = (j == 1) ? (W)(x1s * (double)X1[rr + col * a.X1.ld]) : pw[(int64_t)(j - 2) * se + rr + col * n];
+      out[q] = valid[q] ? x : W(0);
+    }
+  };
+  W y[RPL];
+  load_x(s, y);
+  // Y statistics and low-precision copies
   double ysum = 0.0;
-  // blocks in chunks of 8 so their running column sums stay in registers
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    ysum += fabs((double)y[q]);
+    if (valid[q] && want32) yf32[rw[q] + col * n] = (float)y[q];
+    if (valid[q] && want16) ybf[col * Kp + rw[q]] = bf16_bits_rne((float)y[q]);
+    if (want8) {
+      // E8M0 block = 32 consecutive rows = one half-wave
+      float av = fabsf((float)y[q]);
+#pragma unroll
+      for (int off = 16; off >= 1; off >>= 1) av = fmaxf(av, __shfl_xor(av, off, 64));
+      const int sbyte = e8m0_for(av);
+      if (valid[q]) {
+        float qv = ldexpf((float)y[q], -(sbyte - 127));
+        qv = fminf(fmaxf(qv, -448.0f), 448.0f);
+        const int wv = __builtin_amdgcn_cvt_pk_fp8_f32(qv, 0.0f, 0, false);
+        y8[col * Kp + rw[q]] = (uint8_t)(wv & 0xff);
+        if ((rw[q] & 31) == 0) y8s[col * Ks + rw[q] / 32] = (uint8_t)sbyte;
+      }
+    }
+  }
+  // blocks in chunks of 8 so their running values stay in registers
   for (int i0 = 0; i0 < nB; i0 += 8) {
-    double bsum[8];
+    W bv[RPL][8];
 #pragma unroll
-    for (int ii = 0; ii < 8; ++ii) bsum[ii] = 0.0;
-    for (int64_t rw = r_begin + lane; rw < r_stop; rw += 64) {
-      const bool valid = rw < r_end;
-      W y = W(0);
-      if (valid) {
-        if (s == 1) y = (W)(x1s * (double)X1[rw + col * a.X1.ld]);
-        else y = pw[(int64_t)(s - 2) * se + rw + col * n];
-      }
-      if (i0 == 0) {
-        // Y statistics and copies (first chunk of blocks only)
-        ysum += fabs((double)y);
-        if (valid && want32) yf32[rw + col * n] = (float)y;
-        if (valid && want16) ybf[col * Kp + rw] = bf16_bits_rne((float)y);
-        if (want8) {
-          float av = fabsf((float)y);
+    for (int ii = 0; ii < 8; ++ii) {
+      const int i = i0 + ii;
+      const W c0 = (i < nB && s * i <= m) ? (W)cf.c[s * i] : W(0);
 #pragma unroll
-          for (int off = 16; off >= 1; off >>= 1) av = fmaxf(av, __shfl_xor(av, off, 64));
-          const int sbyte = e8m0_for(av);
-          if (valid) {
-            float q = ldexpf((float)y, -(sbyte - 127));
-            q = fminf(fmaxf(q, -448.0f), 448.0f);
-            const int wv = __builtin_amdgcn_cvt_pk_fp8_f32(q, 0.0f, 0, false);
-            y8[col * Kp + rw] = (uint8_t)(wv & 0xff);
-          }
-          if ((rw & 31) == 0) y8s[col * Ks + rw / 32] = (uint8_t)sbyte;
-        }
-      }
-      if (!valid) continue;
-      W bv[8];
+      for (int q = 0; q < RPL; ++q) bv[q][ii] = (rw[q] == col) ? c0 : W(0);
+    }
+#pragma unroll 2
+    for (int j = 1; j < s; ++j) {
+      W xj[RPL];
+      load_x(j, xj);
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii) {
-        const int i = i0 + ii;
-        bv[ii] = W(0);
-        if (i < nB && s * i <= m) bv[ii] = (rw == col) ? (W)cf.c[s * i] : W(0);
-      }
-      for (int j = 1; j < s; ++j) {
-        W xj;
-        if (j == 1) xj = (W)(x1s * (double)X1[rw + col * a.X1.ld]);
-        else xj = pw[(int64_t)(j - 2) * se + rw + col * n];
+        const int k = s * (i0 + ii) + j;
+        if (i0 + ii < nB && k <= m) {
+          const W ck = (W)cf.c[k];
 #pragma unroll
-        for (int ii = 0; ii < 8; ++ii) {
-          const int k = s * (i0 + ii) + j;
-          if (i0 + ii < nB && k <= m) bv[ii] += (W)cf.c[k] * xj;
-        }
-      }
-#pragma unroll
-      for (int ii = 0; ii < 8; ++ii) {
-        const int i = i0 + ii;
-        if (i < nB) {
-          bsum[ii] += fabs((double)bv[ii]);
-          W outv = bv[ii];
-          if (a.trivial_last && i == r - 1) outv += (W)cf.c[m] * y;   // step r: c_m I * Y
-          Bm[(int64_t)i * se + rw + col * n] = outv;
+          for (int q = 0; q < RPL; ++q) bv[q][ii] += ck * xj[q];
         }
       }
     }
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) {
-      double v = bsum[ii];
+      const int i = i0 + ii;
+      if (i >= nB) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        if (!valid[q]) continue;
+        v += fabs((double)bv[q][ii]);
+        W outv = bv[q][ii];
+        if (a.trivial_last && i == r - 1) outv += (W)cf.c[m] * y[q];   // step r: c_m I * Y
+        Bm[(int64_t)i * se + rw[q] + col * n] = outv;
+      }
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0 && i0 + ii < nB) colsum[((int64_t)(i0 + ii) * nch + chunk) * n + col] = v;
+      if (lane == 0) colsum[((int64_t)i * nch + chunk) * n + col] = v;
     }
   }
   double v = ysum;
@@ -614,14 +737,15 @@ __device__ inline void plan_matrix(const PlanArgs& a, const Layout& L, char* ws,
       double sum[8];
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii) sum[ii] = 0.0;
-      // all (block, chunk) loads of this column are independent and predicated,
-      // so they are in flight together
+      // all (block, chunk) loads of this column are independent, so they are
+      // in flight together
 #pragma unroll 4
       for (int64_t ch = 0; ch < nch; ++ch) {
 #pragma unroll
         for (int ii = 0; ii < 8; ++ii) {
-          const double v = (i0 + ii <= a.nB) ? colsum[((int64_t)(i0 + ii) * nch + ch) * n + c] : 0.0;
-          sum[ii] += v;
+          const int i = min(i0 + ii, a.nB);   // clamped: every load is unconditional
+          const double v = colsum[((int64_t)i * nch + ch) * n + c];
+          sum[ii] += (i0 + ii <= a.nB) ? v : 0.0;
         }
       }
 #pragma unroll

@@ -26,17 +26,21 @@
 //   f32 16x16x4, bf16 16x16x32, f8f6f4 16x16x128 : D[4(l/16) + v][l%16]
 //   operands (f64, f32, bf16): lane l holds A[l%16][kb + e] and
 //   B[kb + e][l%16] with kb = (l/16) * (K/4), e over K/4 consecutive elements;
-//   f8f6f4 16x16x128 interleaves K and its scales, see mainloop_fp8.
+//   f8f6f4 16x16x128 interleaves K and its scales, see mainloop_lowp.
 #include "ps_device.h"
 
 namespace psk {
 
 // ---------------------------------------------------------------------------
-// k_gemm: one 64x32 tile per workgroup
+// k_gemm: one 64 x kTileN tile per workgroup
 // ---------------------------------------------------------------------------
 template <typename T, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void k_gemm(int64_t n, MatArg A, MatArg B, MatArg C, double alpha, int accumulate) {
+#ifdef PS_GEMM_SMEM_EXTRA
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES + PS_GEMM_SMEM_EXTRA];
+#else
   __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+#endif
   const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
   int tm, tn;
   tile_of_block(ntm, ntn, tm, tn);
@@ -71,7 +75,7 @@ hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, 
 // k_horner: one tile of one Horner step per workgroup
 // ---------------------------------------------------------------------------
 template <typename W>
-__global__ __launch_bounds__(NT) void k_horner(HornerArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_horner(HornerArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   const Layout& L = a.L;
