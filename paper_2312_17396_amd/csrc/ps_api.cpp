@@ -254,6 +254,7 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
     for (int k = 0; k <= L.m; ++k) cf.c[k] = (double)(float)cf.c[k];
   AssembleArgs aa;
   aa.n = n;
+  aa.nv = n;
   aa.m = L.m;
   aa.s = L.s;
   aa.r = L.r;

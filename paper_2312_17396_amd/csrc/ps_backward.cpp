@@ -173,6 +173,7 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
     for (int k = 0; k <= m; ++k) cf.c[k] = c[k];
     AssembleArgs aa;
     aa.n = n;
+    aa.nv = n;
     aa.m = m;
     aa.s = s;
     aa.r = r;

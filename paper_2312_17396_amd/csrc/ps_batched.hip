@@ -1,14 +1,24 @@
-// Many matrices of uneven order in one persistent launch.
+// Many matrices of uneven order, evaluated together.
 //
-// Each workgroup repeatedly takes the next matrix from a device work counter
-// (matrices ordered by decreasing modelled cost, so the large ones start
-// first) and runs the whole evaluation for it with its own 256 threads:
-// X = 2^-sigma A, the power table, the block assembly with norms, the
-// precision plan (section 2, eq. (choose-ui); section 4.1.1 tiers), the
-// Horner chain in the planned tiers and the squarings (eq. (scal-idea)).
-// Phases are separated by workgroup barriers only; no grid-wide
-// synchronisation exists, every workgroup leaves the loop once the counter
-// passes the batch size.
+// The evaluation of every matrix goes through the same phases: choice of the
+// block size, X = 2^-sigma A and the power table, the block assembly with
+// norms, the precision plan (section 2, eq. (choose-ui); section 4.1.1
+// tiers), the Horner chain in the planned tiers and the squarings
+// (eq. (scal-idea)).  Each phase step is one launch over the whole batch: a
+// task table built on the host at set-up lists (matrix, output tile) pairs,
+// largest matrices first, and workgroup g takes task g.  Matrices that have
+// no work in a step (a smaller block size, fewer squarings) leave at once.
+// Every matrix is first copied into a zero-padded square of order
+// np = ceil(n / 64) 64 inside its workspace region, and all later phases work
+// on order np: every tile and K slab is then whole, so the GEMM and Horner
+// tiles take the unconditional vector-load path.  The padding stays exactly
+// zero through every phase (the identity terms of the blocks are placed on
+// the first n diagonal entries only), adding zeros does not change the
+// sums, and only rows and columns < n reach the output: the results are the
+// same as those of the unpadded single-matrix path.
+// A batch is thus a fixed sequence of about s + r + sigma + 5 launches, which
+// ps_batched_prepare captures into one hipGraph; the plan and the block-size
+// choice are made on the device, so nothing returns to the host in between.
 //
 // The block size is chosen per matrix among floor(sqrt m) and ceil(sqrt m)
 // (the two equally cheap choices of the paper's section 1) by the modelled
@@ -37,26 +47,38 @@ struct BatchItem {
   void* E;
   int64_t lde;
   int64_t ws_off;       // byte offset of the matrix's workspace region
+  int64_t off_x1;       // byte offset (in the region) of the zero-padded copy of A
+  int64_t nv;           // order n of the matrix; the layouts are for the padded order
   int sigma;
   int s_fixed;          // 0: choose between L[0] (floor sqrt m) and L[1] (ceil sqrt m)
   Layout L[2];
 };
 
+// per-matrix descriptor resolved on the device once the block size is chosen
+struct BatchRes {
+  char* ws;             // the matrix's workspace region
+  const void* X1;       // zero-padded copy of A, order L.n, leading dimension L.n
+  void* E;
+  int64_t lde;
+  int64_t nv;           // order of the matrix (<= L.n)
+  int sigma;
+  Layout L;             // the chosen layout (padded order)
+};
+
 struct BatchArgs {
   const BatchItem* items;
-  const int* order;
-  int* counter;
+  BatchRes* res;
+  const int* tile_tasks;  // (matrix << 8) | tile, largest matrices first
+  const int* col_tasks;   // (matrix << 8) | group of NW columns
+  int* pick;              // per matrix: 0 -> L[0], 1 -> L[1]
+  int* chosen;            // per matrix: chosen block size (for reports)
   int batch;
   int mode;
   unsigned mask;
   double delta;
   char* ws;
-  int* chosen;          // per matrix: chosen block size (for reports)
   Coefs cf;
 };
-
-template <typename W>
-constexpr int persist_smem() { return 2 * STAGE * (int)sizeof(W); }
 
 // modelled relative cost of one n^3 product per tier (inverse MFMA rates)
 __device__ inline double tier_cost(int t) { return t == 0 ? 2.0 : t == 1 ? 1.0 : t == 2 ? 1.0 / 16 : 1.0 / 32; }
@@ -85,19 +107,20 @@ __device__ inline double apriori_cost(const Layout& L, const Coefs& cf, double x
   return c;
 }
 
+__device__ inline int tiles_m(int64_t n) { return (int)((n + kTileM - 1) / kTileM); }
+
+// ---- block size: ||X||_1 = 2^-sigma ||A||_1, then the cheaper of the two layouts
 template <typename W>
-__device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, char* smem, double* red, double* norms) {
+__global__ __launch_bounds__(NT) void k_bchoose(BatchArgs a) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
+  __shared__ double red[NW + 1];
+  const int b = blockIdx.x;
+  const BatchItem& it = a.items[b];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const W* A = (const W*)it.A;
-  const int64_t lda = it.lda;
-  const int64_t n = it.L[0].n;
-  const int sigma = it.sigma;
-  const double beta = ldexp(1.0, -sigma);
-  // ---- block size
   int pick = 1;
   if (!it.s_fixed && it.L[0].s != it.L[1].s) {
-    // ||X||_1 = beta * max column abs sum of A
+    const W* A = (const W*)it.A;
+    const int64_t n = it.nv, lda = it.lda;
     double mx = 0.0;
     for (int64_t c = w; c < n; c += NW) {
       double v = 0.0;
@@ -110,50 +133,107 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
     if (t == 0) {
       double x = red[0];
       for (int k = 1; k < NW; ++k) if (red[k] > x || red[k] != red[k]) x = red[k];
-      x *= beta;
+      x *= ldexp(1.0, -it.sigma);
       const double c0 = apriori_cost(it.L[0], a.cf, x, WT, a.mask, a.delta);
       const double c1 = apriori_cost(it.L[1], a.cf, x, WT, a.mask, a.delta);
       red[NW] = (c0 < c1) ? 0.0 : 1.0;
     }
     __syncthreads();
     pick = red[NW] != 0.0 ? 1 : 0;
-    __syncthreads();
   }
-  const Layout& L = it.L[pick];
-  if (t == 0 && a.chosen) a.chosen[idx] = L.s;
-  char* ws = a.ws + it.ws_off;
-  const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
-  const int ntiles = ntm * ntn;
+  if (t == 0) {
+    a.pick[b] = pick;
+    if (a.chosen) a.chosen[b] = it.L[pick].s;
+    BatchRes& r = a.res[b];
+    r.ws = a.ws + it.ws_off;
+    r.X1 = a.ws + it.ws_off + it.off_x1;
+    r.E = it.E;
+    r.lde = it.lde;
+    r.nv = it.nv;
+    r.sigma = it.sigma;
+    r.L = it.L[pick];
+  }
+}
+
+// ---- zero-padded copy of A: one 64 x kTileN tile of the padded square per workgroup
+template <typename W>
+__global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
+  const int task = a.tile_tasks[blockIdx.x];
+  const int b = task >> 8, tile = task & 255;
+  const BatchItem& it = a.items[b];
+  const int64_t np = it.L[0].n, n = it.nv;
+  const int ntm = tiles_m(np);
+  const int64_t m0 = (int64_t)(tile % ntm) * kTileM, n0 = (int64_t)(tile / ntm) * kTileN;
+  const W* A = (const W*)it.A;
+  W* X = (W*)(a.ws + it.ws_off + it.off_x1);
+  const int t = threadIdx.x, row = t & 63;
+  W v[TILE_Q];
+#pragma unroll
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int64_t gr = m0 + row, gc = n0 + (t >> 6) + NW * q;
+    const bool in = gr < n && gc < n;
+    const W x = A[(in ? gr : 0) + (in ? gc : 0) * it.lda];
+    v[q] = in ? x : W(0);
+  }
+#pragma unroll
+  for (int q = 0; q < TILE_Q; ++q) X[m0 + row + (n0 + (t >> 6) + NW * q) * np] = v[q];
+}
+
+// ---- power table step j: X_2 = beta^2 (A A), X_j = beta (X_{j-1} A)
+template <typename W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower(BatchArgs a, int j) {
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  const int task = a.tile_tasks[blockIdx.x];
+  const int b = task >> 8, tile = task & 255;
+  const BatchRes& it = a.res[b];
+  const Layout& L = it.L;
+  if (j > L.s) return;   // uniform: the whole workgroup leaves
+  const int64_t n = L.n;
+  const int ntm = tiles_m(n);
+  const W* X1 = (const W*)it.X1;
+  const double beta = ldexp(1.0, -it.sigma);
   const int64_t se = (int64_t)(L.slot / sizeof(W));
-  W* pw = (W*)(ws + L.off_pow);
-  // ---- 1. power table: X_2 = beta^2 (A A), X_{j+1} = beta (X_j A)
-  for (int j = 2; j <= L.s; ++j) {
-    const W* src = (j == 2) ? A : pw + (int64_t)(j - 3) * se;
-    const int64_t lds = (j == 2) ? lda : n;
-    const double alpha = (j == 2) ? beta * beta : beta;
-    for (int tile = 0; tile < ntiles; ++tile)
-      gemm_tile<W, false, false>(src, lds, A, lda, pw + (int64_t)(j - 2) * se, n, n, (int64_t)(tile % ntm) * kTileM,
-                                 (int64_t)(tile / ntm) * kTileN, alpha, 0, smem);
-  }
-  // ---- 2. blocks, norms, low-precision copies of Y
+  W* pw = (W*)(it.ws + L.off_pow);
+  const W* src = (j == 2) ? X1 : pw + (int64_t)(j - 3) * se;
+  gemm_tile<W, false, false>(src, n, X1, n, pw + (int64_t)(j - 2) * se, n, n, n, (int64_t)(tile % ntm) * kTileM,
+                             (int64_t)(tile / ntm) * kTileN, (j == 2) ? beta * beta : beta, 0, smem);
+}
+
+// ---- blocks, norms, low-precision copies of Y: one wave per column
+template <typename W>
+__global__ __launch_bounds__(NT) void k_bassemble(BatchArgs a) {
+  const int task = a.col_tasks[blockIdx.x];
+  const int b = task >> 8, grp = task & 255;
+  const BatchRes& it = a.res[b];
+  const Layout& L = it.L;
+  const int64_t col = (int64_t)grp * NW + (threadIdx.x >> 6);
+  if (col >= L.n) return;   // no workgroup barrier below
   AssembleArgs aa;
-  aa.n = n;
+  aa.n = L.n;
+  aa.nv = it.nv;
   aa.m = L.m;
   aa.s = L.s;
   aa.r = L.r;
   aa.nB = L.nB;
   aa.trivial_last = L.trivial_last;
-  aa.X1 = MatArg{A, lda, 0};
-  aa.x1_scale = beta;
-  aa.ws = ws;
+  aa.X1 = MatArg{it.X1, L.n, 0};
+  aa.x1_scale = ldexp(1.0, -it.sigma);
+  aa.ws = it.ws;
   aa.ws_stride = 0;
   aa.L = L;
   aa.tier_mask = a.mode == PS_MODE_MIXED ? a.mask : 0u;
-  const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
-  for (int64_t c = w; c < n; c += NW)
-    for (int64_t ch = 0; ch < nch; ++ch) assemble_column<W>(aa, a.cf, ws, A, c, ch);
-  __syncthreads();
-  // ---- 3. plan
+  assemble_column<W>(aa, a.cf, aa.ws, (const W*)it.X1, col, 0);
+}
+
+// ---- precision plan: one workgroup per matrix
+template <typename W>
+__global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
+  constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
+  __shared__ double red[NT];
+  __shared__ double norms[PS_MAX_BLOCKS + 1];
+  const int b = blockIdx.x;
+  const BatchRes& it = a.res[b];
+  const Layout& L = it.L;
   PlanArgs pa;
   pa.r = L.r;
   pa.mode = a.mode;
@@ -164,22 +244,40 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
   pa.delta = a.delta;
   pa.abs_cm = fabs(a.cf.c[L.m]);
   pa.use_override = 0;
-  pa.ws = ws;
+  pa.ws = it.ws;
   pa.ws_stride = 0;
   pa.L = L;
-  plan_matrix(pa, L, ws, red, norms);
+  plan_matrix(pa, L, pa.ws, red, norms);
+}
+
+// ---- Horner step k: k = -1 casts B_{i0} into the format of step i0; k >= 0
+// is step i = i0 - k.  The cast writes P0; step k reads P0 (k even) or P1
+// (k odd) and writes the other buffer.
+template <typename W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bhorner(BatchArgs a, int k) {
+  constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  const int task = a.tile_tasks[blockIdx.x];
+  const int b = task >> 8, tile = task & 255;
+  const BatchRes& it = a.res[b];
+  const Layout& L = it.L;
+  const int i0 = L.first_step;
+  if (k >= i0) return;   // uniform
+  const int64_t n = L.n;
+  const int ntm = tiles_m(n);
+  char* ws = it.ws;
   const Plan* P = (const Plan*)(ws + L.off_plan);
-  // ---- 4. Horner chain
-  const bool square = sigma > 0;
-  W* R = (W*)(ws + L.off_R);
+  const int64_t se = (int64_t)(L.slot / sizeof(W));
+  const W* pw = (const W*)(ws + L.off_pow);
+  const bool square = it.sigma > 0;
   HornerTile<W> h;
   h.n = n;
   h.Mp = L.Mp;
   h.Kp = L.Kp;
   if (L.s == 1) {
-    h.ysrc = A;
-    h.ldy = lda;
-    h.yscale = beta;
+    h.ysrc = (const W*)it.X1;
+    h.ldy = n;
+    h.yscale = ldexp(1.0, -it.sigma);
   } else {
     h.ysrc = pw + (int64_t)(L.s - 2) * se;
     h.ldy = n;
@@ -189,59 +287,39 @@ __device__ void run_matrix(const BatchArgs& a, const BatchItem& it, int idx, cha
   h.ybf16 = (const uint16_t*)(ws + L.off_ybf16);
   h.yfp8 = (const uint8_t*)(ws + L.off_yfp8);
   h.yfp8s = (const uint8_t*)(ws + L.off_yfp8s);
-  W* fin = square ? R : (W*)it.E;
-  const int64_t ldfin = square ? n : it.lde;
-  const int i0 = L.first_step;
-  for (int k = -1; k < i0; ++k) {
-    // k = -1: cast of B_{i0}; k >= 0: step i = i0 - k
-    const int i = i0 - k;
-    const bool cast = (k < 0);
-    const bool final_out = cast ? (i0 == 0) : (i == 1);
-    h.t_in = cast ? -1 : P->tier[i];
-    h.t_out = final_out ? WT : P->tier[cast ? i0 : i - 1];
-    // the cast writes P0; step k >= 0 reads P0 (k even) or P1 (k odd) and writes the other
-    h.pin = ws + ((k & 1) ? L.off_P1 : L.off_P0);
-    h.pout = ws + ((k & 1) ? L.off_P0 : L.off_P1);
-    if (cast) h.pout = ws + L.off_P0;
-    h.bsrc = (const W*)(ws + L.off_B) + (int64_t)(cast ? i0 : i - 1) * se;
-    h.outw = final_out ? fin : (W*)h.pout;
-    h.ldo = final_out ? ldfin : n;
-    for (int tile = 0; tile < ntiles; ++tile)
-      horner_tile<W>(h, (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, smem);
-  }
-  // ---- 5. squarings
-  if (square) {
-    W* bufs[2] = {R, (W*)(ws + L.off_P0)};
-    for (int q = 1; q <= sigma; ++q) {
-      const W* src = bufs[(q - 1) & 1];
-      W* dst = (q == sigma) ? (W*)it.E : bufs[q & 1];
-      const int64_t ldd = (q == sigma) ? it.lde : n;
-      for (int tile = 0; tile < ntiles; ++tile)
-        gemm_tile<W, false, false>(src, n, src, n, dst, ldd, n, (int64_t)(tile % ntm) * kTileM,
-                                   (int64_t)(tile / ntm) * kTileN, 1.0, 0, smem);
-    }
-  }
+  const int i = i0 - k;
+  const bool cast = (k < 0);
+  const bool final_out = cast ? (i0 == 0) : (i == 1);
+  h.t_in = cast ? -1 : P->tier[i];
+  h.t_out = final_out ? WT : P->tier[cast ? i0 : i - 1];
+  h.pin = ws + ((k & 1) ? L.off_P1 : L.off_P0);
+  h.pout = cast ? ws + L.off_P0 : ws + ((k & 1) ? L.off_P0 : L.off_P1);
+  h.bsrc = (const W*)(ws + L.off_B) + (int64_t)(cast ? i0 : i - 1) * se;
+  h.outw = final_out ? (square ? (W*)(ws + L.off_R) : (W*)it.E) : (W*)h.pout;
+  h.ldo = final_out ? (square ? n : it.lde) : n;
+  h.nv = (final_out && !square) ? it.nv : n;
+  horner_tile<W>(h, (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, smem);
 }
 
+// ---- squaring q (1..sigma): R_q = R_{q-1}^2, R_0 in L.off_R, ping-pong with P0
 template <typename W>
-__global__ __launch_bounds__(NT) void k_ps_persistent(BatchArgs a) {
-  __shared__ __attribute__((aligned(16))) char smem[persist_smem<W>()];
-  __shared__ double red[NT];
-  __shared__ double norms[PS_MAX_BLOCKS + 1];
-  __shared__ int s_idx;
-  for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(a.counter, 1);
-    __syncthreads();
-    const int idx = s_idx;
-    __syncthreads();
-    if (idx >= a.batch) break;   // uniform across the workgroup
-    const int b = a.order[idx];
-    run_matrix<W>(a, a.items[b], b, smem, red, norms);
-  }
-}
-
-__global__ void k_zero_counter(int* c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bsquare(BatchArgs a, int q) {
+  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  const int task = a.tile_tasks[blockIdx.x];
+  const int b = task >> 8, tile = task & 255;
+  const BatchRes& it = a.res[b];
+  if (q > it.sigma) return;   // uniform
+  const Layout& L = it.L;
+  const int64_t n = L.n;
+  const int ntm = tiles_m(n);
+  char* ws = it.ws;
+  W* const r0 = (W*)(ws + L.off_R);
+  W* const r1 = (W*)(ws + L.off_P0);
+  const W* src = (q & 1) ? r0 : r1;
+  W* dst = (q == it.sigma) ? (W*)it.E : ((q & 1) ? r1 : r0);
+  const int64_t ldd = (q == it.sigma) ? it.lde : n;
+  gemm_tile<W, false, false>(src, n, src, n, dst, ldd, n, (q == it.sigma) ? it.nv : n, (int64_t)(tile % ntm) * kTileM,
+                             (int64_t)(tile / ntm) * kTileN, 1.0, 0, smem);
 }
 
 }  // namespace psk
@@ -269,8 +347,9 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan2 {
   std::vector<BatchItem> items;
-  std::vector<int> order;
-  size_t off_items, off_order, off_counter, off_chosen, off_mats, total;
+  std::vector<int> tile_tasks, col_tasks;
+  int smax = 1, kmax = 0, sigmax = 0;
+  size_t off_items, off_res, off_tiles, off_cols, off_pick, off_chosen, total;
 };
 
 int s_floor(int m) {
@@ -289,7 +368,7 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
                      const void* const* A, const int64_t* lda, void* const* E, const int64_t* lde, Plan2& P,
                      bool need_ptrs) {
   if (dt != PS_F64 && dt != PS_F32) return bfail(PS_ERR_ARG, "dtype must be PS_F64 or PS_F32");
-  if (batch < 1 || batch > (1 << 24)) return bfail(PS_ERR_ARG, "batch = %d out of range", batch);
+  if (batch < 1 || batch > (1 << 22)) return bfail(PS_ERR_ARG, "batch = %d out of range", batch);
   if (!n) return bfail(PS_ERR_ARG, "n == NULL");
   if (m < 0 || m > kMaxDegree) return bfail(PS_ERR_ARG, "degree m = %d out of range", m);
   const int esize = dt == PS_F64 ? 8 : 4;
@@ -307,12 +386,15 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
     memset(&it, 0, sizeof it);
     const int s0 = sb ? sb : s_floor(m), s1 = sb ? sb : s_ceil(m);
     if (m / s0 + 1 > PS_MAX_BLOCKS || m / s1 + 1 > PS_MAX_BLOCKS) return bfail(PS_ERR_ARG, "too many blocks");
-    it.L[0] = make_layout(dt, nb, m, s0, 1, 0);
-    it.L[1] = make_layout(dt, nb, m, s1, 1, 0);
+    const int64_t np = (nb + kTileM - 1) / kTileM * kTileM;   // padded order
+    it.L[0] = make_layout(dt, np, m, s0, 1, 0);
+    it.L[1] = make_layout(dt, np, m, s1, 1, 0);
     it.s_fixed = sb != 0;
     it.sigma = sg;
+    it.nv = nb;
     it.ws_off = (int64_t)off;
-    off += al256(std::max(it.L[0].bytes, it.L[1].bytes));
+    it.off_x1 = (int64_t)al256(std::max(it.L[0].bytes, it.L[1].bytes));
+    off += it.off_x1 + al256((size_t)(np * np) * esize);
     if (need_ptrs) {
       if (!A || !E || !lda || !lde || !A[b] || !E[b]) return bfail(PS_ERR_ARG, "NULL pointer for matrix %d", b);
       if (lda[b] < nb || lde[b] < nb) return bfail(PS_ERR_ARG, "leading dimension < n for matrix %d", b);
@@ -327,16 +409,30 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
     }
     const int gem = (std::max(s0, s1) - 1) + (m / s0) + sg;
     cost[b] = (double)nb * nb * nb * gem;
+    P.smax = std::max(P.smax, std::max(s0, s1));
+    P.kmax = std::max(P.kmax, std::max(it.L[0].first_step, it.L[1].first_step));
+    P.sigmax = std::max(P.sigmax, sg);
   }
-  P.order.resize(batch);
-  std::iota(P.order.begin(), P.order.end(), 0);
-  std::stable_sort(P.order.begin(), P.order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  P.off_mats = 0;
+  // task tables, largest matrices first so the long tiles start early
+  std::vector<int> order(batch);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  P.tile_tasks.clear();
+  P.col_tasks.clear();
+  for (int b : order) {
+    const int64_t nb = n[b];
+    const int nt = (int)(((nb + kTileM - 1) / kTileM) * ((nb + kTileN - 1) / kTileN));   // tiles of the padded square
+    for (int t = 0; t < nt; ++t) P.tile_tasks.push_back((b << 8) | t);
+    const int ng = (int)((P.items[b].L[0].n + NW - 1) / NW);   // columns of the padded square
+    for (int g = 0; g < ng; ++g) P.col_tasks.push_back((b << 8) | g);
+  }
   P.off_items = al256(off);
-  P.off_order = al256(P.off_items + sizeof(BatchItem) * (size_t)batch);
-  P.off_chosen = al256(P.off_order + sizeof(int) * (size_t)batch);
-  P.off_counter = al256(P.off_chosen + sizeof(int) * (size_t)batch);
-  P.total = al256(P.off_counter + 256);
+  P.off_res = al256(P.off_items + sizeof(BatchItem) * (size_t)batch);
+  P.off_tiles = al256(P.off_res + sizeof(BatchRes) * (size_t)batch);
+  P.off_cols = al256(P.off_tiles + sizeof(int) * P.tile_tasks.size());
+  P.off_pick = al256(P.off_cols + sizeof(int) * P.col_tasks.size());
+  P.off_chosen = al256(P.off_pick + sizeof(int) * (size_t)batch);
+  P.total = al256(P.off_chosen + sizeof(int) * (size_t)batch);
   return PS_OK;
 }
 
@@ -366,31 +462,43 @@ ps_status upload_and_args(const Plan2& P, char* ws, hipStream_t st, BatchArgs& b
   hipError_t e = hipMemcpyAsync(ws + P.off_items, P.items.data(), sizeof(BatchItem) * P.items.size(),
                                 hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + P.off_order, P.order.data(), sizeof(int) * P.order.size(), hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(ws + P.off_tiles, P.tile_tasks.data(), sizeof(int) * P.tile_tasks.size(),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ws + P.off_cols, P.col_tasks.data(), sizeof(int) * P.col_tasks.size(), hipMemcpyHostToDevice,
+                       st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors are released on return
   if (e != hipSuccess) return bfail(PS_ERR_HIP, "descriptor upload: %s", hipGetErrorString(e));
   ba.items = (const BatchItem*)(ws + P.off_items);
-  ba.order = (const int*)(ws + P.off_order);
-  ba.counter = (int*)(ws + P.off_counter);
+  ba.res = (BatchRes*)(ws + P.off_res);
+  ba.tile_tasks = (const int*)(ws + P.off_tiles);
+  ba.col_tasks = (const int*)(ws + P.off_cols);
+  ba.pick = (int*)(ws + P.off_pick);
   ba.chosen = (int*)(ws + P.off_chosen);
   ba.batch = (int)P.items.size();
   ba.ws = ws;
   return PS_OK;
 }
 
-ps_status launch_batch(int W, const BatchArgs& ba, hipStream_t st) {
-  int dev = 0, cus = 256, per = 1;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  hipError_t e;
-  if (W == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ps_persistent<double>, NT, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_ps_persistent<float>, NT, 0);
-  if (e != hipSuccess || per < 1) per = 1;
-  const int grid = std::max(1, std::min(ba.batch, cus * per));
-  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, ba.counter);
-  if (W == 0) hipLaunchKernelGGL(k_ps_persistent<double>, dim3(grid), dim3(NT), 0, st, ba);
-  else hipLaunchKernelGGL(k_ps_persistent<float>, dim3(grid), dim3(NT), 0, st, ba);
-  e = hipGetLastError();
-  if (e != hipSuccess) return bfail(PS_ERR_HIP, "persistent launch: %s", hipGetErrorString(e));
+// the fixed launch sequence of a batch (stream-ordered; captured by ps_batched_prepare)
+ps_status launch_batch(int W, const BatchArgs& ba, const Plan2& P, hipStream_t st) {
+  const dim3 blk(NT);
+  const unsigned nmat = (unsigned)ba.batch, ntile = (unsigned)P.tile_tasks.size(), ncol = (unsigned)P.col_tasks.size();
+#define PS_BLAUNCH(KER, GRID, ...)                                                          \
+  do {                                                                                       \
+    if (W == 0) hipLaunchKernelGGL(KER<double>, dim3(GRID), blk, 0, st, ba, ##__VA_ARGS__); \
+    else hipLaunchKernelGGL(KER<float>, dim3(GRID), blk, 0, st, ba, ##__VA_ARGS__);         \
+  } while (0)
+  PS_BLAUNCH(k_bchoose, nmat);
+  PS_BLAUNCH(k_bpad, ntile);
+  for (int j = 2; j <= P.smax; ++j) PS_BLAUNCH(k_bpower, ntile, j);
+  PS_BLAUNCH(k_bassemble, ncol);
+  PS_BLAUNCH(k_bplan, nmat);
+  for (int k = -1; k < P.kmax; ++k) PS_BLAUNCH(k_bhorner, ntile, k);
+  for (int q = 1; q <= P.sigmax; ++q) PS_BLAUNCH(k_bsquare, ntile, q);
+#undef PS_BLAUNCH
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bfail(PS_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
   return PS_OK;
 }
 
@@ -443,7 +551,7 @@ ps_status ps_expm_batched(ps_dtype dtype, int batch, const int32_t* n, const voi
   hipStream_t st = (hipStream_t)stream;
   ps_status r = batched_common(dtype, batch, n, A, lda, coef, m, s, sigma, E, lde, opts, ws, ws_bytes, stream, P, ba);
   if (r) return ps_set_error(r, g_batch_err.c_str());
-  if ((r = launch_batch(dtype == PS_F64 ? 0 : 1, ba, st))) return ps_set_error(r, g_batch_err.c_str());
+  if ((r = launch_batch(dtype == PS_F64 ? 0 : 1, ba, P, st))) return ps_set_error(r, g_batch_err.c_str());
   if (tiers_out) {
     std::vector<int> chosen(batch);
     hipError_t e = hipMemcpyAsync(chosen.data(), ba.chosen, sizeof(int) * batch, hipMemcpyDeviceToHost, st);
@@ -478,7 +586,7 @@ ps_status ps_batched_prepare(ps_dtype dtype, int batch, const int32_t* n, const 
   ps_batched_exec* h = new ps_batched_exec();
   e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    r = launch_batch(dtype == PS_F64 ? 0 : 1, ba, cap);
+    r = launch_batch(dtype == PS_F64 ? 0 : 1, ba, P, cap);
     hipError_t e2 = hipStreamEndCapture(cap, &h->graph);
     if (r == PS_OK && e2 != hipSuccess) e = e2;
   }

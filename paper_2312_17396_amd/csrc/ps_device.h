@@ -84,24 +84,31 @@ template <> struct MF<float> {
 
 // ---- global -> register slab loads.  Each thread moves a run of RUNA (A)
 // or RUNB (B) consecutive elements (contiguous in memory) of the 64 x BKL A
-// slab and the BKL x kTileN B slab; runs fully in bounds and 16-byte aligned use
-// vector loads, the rest guarded element loads (zero fill).  Runs along k
-// (A transposed, B normal) are laid out lane -> row / column so that each LDS
-// store instruction of a wave writes consecutive elements of one k-row.
+// slab and the BKL x kTileN B slab.  On the full-tile path every run is one
+// or two 16-byte vector loads; otherwise runs fully inside the n x n matrix
+// and 16-byte aligned still use vector loads and the rest guarded element
+// loads (zero fill).  Runs along k (A transposed, B normal) are laid out
+// lane -> row / column so that each LDS store instruction of a wave writes
+// consecutive elements of one k-row.
+//
+// Run of R elements p[x0 + i + y ld], i < R, of an n x n matrix stored with
+// leading dimension ld (x the contiguous index).
 template <typename T, int R, bool FULL>
-__device__ inline void load_run(const T* __restrict__ p, bool full, int64_t lim, T r[R]) {
-  if (FULL || (full && (((uintptr_t)p) & 15) == 0)) {
-    typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int W = 16 / sizeof(T);
+__device__ inline void load_run(const T* __restrict__ p, int64_t ld, int64_t n, int64_t x0, int64_t y, T r[R]) {
+  typedef T v2 __attribute__((ext_vector_type(16 / sizeof(T))));
+  constexpr int W = 16 / sizeof(T);
+  const T* q = p + x0 + y * ld;
+  const int64_t lim = (y < n) ? min<int64_t>(R, n - x0) : 0;
+  if (FULL || (lim >= R && (((uintptr_t)q) & 15) == 0)) {
 #pragma unroll
     for (int i = 0; i < R; i += W) {
-      v2 x = *(const v2*)(p + i);
+      v2 x = *(const v2*)(q + i);
 #pragma unroll
       for (int j = 0; j < W; ++j) r[i + j] = x[j];
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < R; ++i) r[i] = (i < lim) ? p[i] : T(0);
+    for (int i = 0; i < R; ++i) r[i] = (i < lim) ? q[i] : T(0);
   }
 }
 // A(m,k): TA = false -> A[m + k lda] (run along m), true -> A[k + m lda] (run along k)
@@ -109,36 +116,19 @@ template <typename T, bool TA, bool FULL>
 __device__ inline void load_a(const T* __restrict__ A, int64_t lda, int64_t n, int64_t m0, int64_t k0, int t,
                               T r[RUNA]) {
   if (!TA) {
-#ifdef PS_ANORM_LANEROW
-    const int mm = t & 63, kk = (t >> 6) * RUNA;
-    const int64_t m = m0 + mm, k = k0 + kk;
-#pragma unroll
-    for (int i = 0; i < RUNA; ++i) r[i] = (m < n && k + i < n) ? A[m + (k + i) * lda] : T(0);
-#else
     const int kk = t / TPA, mm = (t % TPA) * RUNA;
-    const int64_t k = k0 + kk, m = m0 + mm;
-    const int64_t lim = (k < n) ? min<int64_t>(RUNA, n - m) : 0;
-    load_run<T, RUNA, FULL>(A + m + k * lda, lim >= RUNA, lim, r);
-#endif
+    load_run<T, RUNA, FULL>(A, lda, n, m0 + mm, k0 + kk, r);
   } else {
     const int mm = t & 63, kk = (t >> 6) * RUNA;
-    const int64_t m = m0 + mm, k = k0 + kk;
-    const int64_t lim = (m < n) ? min<int64_t>(RUNA, n - k) : 0;
-    load_run<T, RUNA, FULL>(A + k + m * lda, lim >= RUNA, lim, r);
+    load_run<T, RUNA, FULL>(A, lda, n, k0 + kk, m0 + mm, r);
   }
 }
 template <typename T, bool TA>
 __device__ inline void store_a(T* As, int t, const T r[RUNA]) {
   if (!TA) {
-#ifdef PS_ANORM_LANEROW
-    const int mm = t & 63, kk = (t >> 6) * RUNA;
-#pragma unroll
-    for (int i = 0; i < RUNA; ++i) As[(kk + i) * LROWA + mm] = r[i];
-#else
     const int kk = t / TPA, mm = (t % TPA) * RUNA;
 #pragma unroll
     for (int i = 0; i < RUNA; ++i) As[kk * LROWA + mm + i] = r[i];
-#endif
   } else {
     const int mm = t & 63, kk = (t >> 6) * RUNA;
 #pragma unroll
@@ -151,14 +141,10 @@ __device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, i
                               T r[RUNB]) {
   if (!TB) {
     const int jj = t % kTileN, kk = (t / kTileN) * RUNB;
-    const int64_t j = n0 + jj, k = k0 + kk;
-    const int64_t lim = (j < n) ? min<int64_t>(RUNB, n - k) : 0;
-    load_run<T, RUNB, FULL>(B + k + j * ldb, lim >= RUNB, lim, r);
+    load_run<T, RUNB, FULL>(B, ldb, n, k0 + kk, n0 + jj, r);
   } else {
     const int kk = t / TPB, jj = (t % TPB) * RUNB;
-    const int64_t k = k0 + kk, j = n0 + jj;
-    const int64_t lim = (k < n) ? min<int64_t>(RUNB, n - j) : 0;
-    load_run<T, RUNB, FULL>(B + j + k * ldb, lim >= RUNB, lim, r);
+    load_run<T, RUNB, FULL>(B, ldb, n, n0 + jj, k0 + kk, r);
   }
 }
 template <typename T, bool TB>
@@ -175,7 +161,7 @@ __device__ inline void store_b(T* Bs, int t, const T r[RUNB]) {
 }
 
 template <typename T>
-__device__ inline void mma_slab(const T* as, const T* bs, int wr, int wc, int g, int c,
+__device__ __forceinline__ void mma_slab(const T* as, const T* bs, int wr, int wc, int g, int c,
                                 typename MF<T>::V acc[2 * KCH]) {
 #pragma unroll
   for (int ks = 0; ks < BKL / 4; ++ks) {
@@ -193,7 +179,7 @@ __device__ inline void mma_slab(const T* as, const T* bs, int wr, int wc, int g,
 // loads of slab kt+2 are issued before the MFMAs of slab kt, and slab kt+1
 // (loaded one iteration earlier) is stored to the other stage after them.
 template <typename T, bool TA, bool TB, bool FULL>
-__device__ inline void mainloop_lds_impl(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+__device__ __forceinline__ void mainloop_lds_impl(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
                                     int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
@@ -253,7 +239,7 @@ __device__ inline bool full_tiles(const T* A, int64_t lda, const T* B, int64_t l
   return (n % 64) == 0 && (lda % V) == 0 && (ldb % V) == 0 && ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0;
 }
 template <typename T, bool TA, bool TB>
-__device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+__device__ __forceinline__ void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
                                     int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
   if (full_tiles(A, lda, B, ldb, n)) mainloop_lds_impl<T, TA, TB, true>(A, lda, B, ldb, n, m0, n0, smem, acc);
   else mainloop_lds_impl<T, TA, TB, false>(A, lda, B, ldb, n, m0, n0, smem, acc);
@@ -261,7 +247,7 @@ __device__ inline void mainloop_lds(const T* __restrict__ A, int64_t lda, const 
 
 // accumulator fragments -> LDS tile Cs[col * CSTR + row] (type W)
 template <typename T, typename W>
-__device__ inline void frag_to_cs(const typename MF<T>::V acc[2], W* Cs, double scale) {
+__device__ __forceinline__ void frag_to_cs(const typename MF<T>::V acc[2], W* Cs, double scale) {
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
 #pragma unroll
@@ -274,7 +260,7 @@ __device__ inline void frag_to_cs(const typename MF<T>::V acc[2], W* Cs, double 
     }
 }
 
-__device__ inline void frag_f32_to_cs_any(const f4v acc[2], double* Csd, float* Csf, bool isd) {
+__device__ __forceinline__ void frag_f32_to_cs_any(const f4v acc[2], double* Csd, float* Csf, bool isd) {
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
 #pragma unroll
@@ -335,7 +321,7 @@ __device__ inline uint4 lp_mask(uint4 v, int64_t k, int64_t n) {
 }
 
 template <bool FP8>
-__device__ inline void lp_load(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+__device__ __forceinline__ void lp_load(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
                                const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t rsb,
                                int64_t Ks, int64_t n, int64_t m0, int64_t n0, int64_t i, int t, LpRegs& r) {
   constexpr int EB = FP8 ? 1 : 2;
@@ -360,7 +346,7 @@ __device__ inline void lp_load(const uint8_t* __restrict__ A, const uint8_t* __r
 }
 
 template <bool FP8>
-__device__ inline void lp_store(char* st, int t, const LpRegs& r) {
+__device__ __forceinline__ void lp_store(char* st, int t, const LpRegs& r) {
   const int row = t >> 3, ch = t & 7;
   *(uint4*)(st + row * LP_RS + 16 * ch) = r.a;
   *(uint4*)(st + LP_OPER + row * LP_RS + 16 * ch) = r.b;
@@ -368,7 +354,7 @@ __device__ inline void lp_store(char* st, int t, const LpRegs& r) {
 }
 
 template <bool FP8>
-__device__ inline void lp_mma(const char* st, int wr, int wc, int g, int c, f4v acc[2]) {
+__device__ __forceinline__ void lp_mma(const char* st, int wr, int wc, int g, int c, f4v acc[2]) {
   const char* a0p = st + (wr + c) * LP_RS + 16 * g;
   const char* a1p = a0p + 16 * LP_RS;
   const char* bp = st + LP_OPER + (wc + c) * LP_RS + 16 * g;
@@ -404,7 +390,7 @@ __device__ inline void lp_mma(const char* st, int wr, int wc, int g, int c, f4v 
 // Reading each lane's halves from those two offsets makes every hardware
 // scale block coincide with one 32-element block of the packed layout.
 template <bool FP8>
-__device__ inline void mainloop_lowp(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+__device__ __forceinline__ void mainloop_lowp(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
                                      const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t Kp,
                                      int64_t n, int64_t m0, int64_t n0, char* smem, f4v acc[2]) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
@@ -457,10 +443,12 @@ __device__ inline uint32_t pack4_e4m3(float a, float b, float c, float d) {
 // one output tile of C = alpha op(A) op(B) (+ C); ends with a barrier so the
 // caller may reuse smem for the next tile
 // ---------------------------------------------------------------------------
+// n: order of the operands (extent of the product); nv <= n: the order of the
+// part of C that is written (rows and columns < nv).
 template <typename T, bool TA, bool TB>
-__device__ inline void gemm_tile(const T* __restrict__ Ap, int64_t lda, const T* __restrict__ Bp, int64_t ldb,
-                                 T* Cp, int64_t ldc, int64_t n, int64_t m0, int64_t n0, double alpha, int accumulate,
-                                 char* smem) {
+__device__ __forceinline__ void gemm_tile(const T* __restrict__ Ap, int64_t lda, const T* __restrict__ Bp, int64_t ldb,
+                                 T* Cp, int64_t ldc, int64_t n, int64_t nv, int64_t m0, int64_t n0, double alpha,
+                                 int accumulate, char* smem) {
   typename MF<T>::V acc[2];
   mainloop_lds<T, TA, TB>(Ap, lda, Bp, ldb, n, m0, n0, smem, acc);
   T* Cs = (T*)smem;
@@ -473,7 +461,7 @@ __device__ inline void gemm_tile(const T* __restrict__ Ap, int64_t lda, const T*
   for (int q = 0; q < TILE_Q; ++q) {
     const int col = (t >> 6) + NW * q;
     const int64_t gc = n0 + col;
-    if (gr < n && gc < n) {
+    if (gr < nv && gc < nv) {
       const T v = (T)(alpha * (double)Cs[col * CSTR + row]);
       T* dst = Cp + gr + gc * ldc;
       if (accumulate) *dst = *dst + v;
@@ -505,10 +493,11 @@ struct HornerTile {
   char* pout;               // next operand buffer (t_out below working)
   W* outw;                  // working-precision output (t_out = working tier)
   int64_t ldo;
+  int64_t nv;               // rows and columns < nv of outw are written (nv <= n)
 };
 
 template <typename W>
-__device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n0, char* smem) {
+__device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n0, char* smem) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;   // working tier
   const int64_t n = h.n, Kp = h.Kp;
   const int t_in = h.t_in, t_out = h.t_out;
@@ -553,7 +542,7 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
     const W v = (t_in < 0) ? W(0) : Cs[col * CSTR + row];
     const W bb = bq[q];
     if (t_out == WT) {
-      if (in) h.outw[gr + gc * h.ldo] = bb + v;
+      if (gr < h.nv && gc < h.nv) h.outw[gr + gc * h.ldo] = bb + v;
     } else if (t_out == 1) {
       if (in) ((float*)h.pout)[gr + gc * n] = (float)bb + (float)v;
     } else {
@@ -601,7 +590,7 @@ __device__ inline void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n
 // low-precision copies of Y.  No workgroup barrier inside.
 // ---------------------------------------------------------------------------
 template <typename W>
-__device__ inline void assemble_column(const AssembleArgs& a, const Coefs& cf, char* ws, const W* X1, int64_t col,
+__device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coefs& cf, char* ws, const W* X1, int64_t col,
                                        int64_t chunk) {
   const Layout& L = a.L;
   const int64_t n = a.n;
@@ -677,9 +666,9 @@ __device__ inline void assemble_column(const AssembleArgs& a, const Coefs& cf, c
       const int i = i0 + ii;
       const W c0 = (i < nB && s * i <= m) ? (W)cf.c[s * i] : W(0);
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) bv[q][ii] = (rw[q] == col) ? c0 : W(0);
+      for (int q = 0; q < RPL; ++q) bv[q][ii] = (rw[q] == col && col < a.nv) ? c0 : W(0);
     }
-#pragma unroll 2
+#pragma unroll 4
     for (int j = 1; j < s; ++j) {
       W xj[RPL];
       load_x(j, xj);
@@ -721,7 +710,7 @@ __device__ inline void assemble_column(const AssembleArgs& a, const Coefs& cf, c
 // the Plan; ends with a barrier.  red: NT doubles, norms: PS_MAX_BLOCKS+1
 // doubles, both in LDS.
 // ---------------------------------------------------------------------------
-__device__ inline void plan_matrix(const PlanArgs& a, const Layout& L, char* ws, double* red, double* norms) {
+__device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, char* ws, double* red, double* norms) {
   const int64_t n = L.n;
   const double* colsum = (const double*)(ws + L.off_colsum);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;

@@ -88,6 +88,7 @@ hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, 
 // Column pass: B_0..B_r, folded last step, column abs sums, low-precision Y copies.
 struct AssembleArgs {
   int64_t n;
+  int64_t nv;           // order of the matrix inside n (rows, columns >= nv are zero padding)
   int m, s, r, nB, trivial_last;
   MatArg X1;            // X_1 = x1_scale * X1
   double x1_scale;

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(NT) void k_gemm(int64_t n, MatArg A, MatArg B, MatA
   tile_of_block(ntm, ntn, tm, tn);
   const int64_t b = blockIdx.z;
   gemm_tile<T, TA, TB>((const T*)A.p + b * A.stride, A.ld, (const T*)B.p + b * B.stride, B.ld,
-                       (T*)C.p + b * C.stride, C.ld, n, (int64_t)tm * kTileM, (int64_t)tn * kTileN, alpha,
+                       (T*)C.p + b * C.stride, C.ld, n, n, (int64_t)tm * kTileM, (int64_t)tn * kTileN, alpha,
                        accumulate, smem);
 }
 
@@ -103,6 +103,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.pout = ws + a.off_pout;
   h.outw = a.final_out ? ((W*)a.out.p + b * a.out.stride) : (W*)(ws + a.off_pout);
   h.ldo = a.final_out ? a.out.ld : a.n;
+  h.nv = a.n;
   horner_tile<W>(h, (int64_t)tm * kTileM, (int64_t)tn * kTileN, smem);
 }
 
