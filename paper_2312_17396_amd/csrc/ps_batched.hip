@@ -121,12 +121,29 @@ __global__ __launch_bounds__(NT) void k_bchoose(BatchArgs a) {
   if (!it.s_fixed && it.L[0].s != it.L[1].s) {
     const W* A = (const W*)it.A;
     const int64_t n = it.nv, lda = it.lda;
+    // column sums, four columns of four row blocks per step: the sixteen
+    // loads of a step are unconditional (clamped indices) and in flight together
     double mx = 0.0;
-    for (int64_t c = w; c < n; c += NW) {
-      double v = 0.0;
-      for (int64_t rw = lane; rw < n; rw += 64) v += fabs((double)A[rw + c * lda]);
-      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (v > mx || v != v) mx = v;
+    for (int64_t c0 = 4 * w; c0 < n; c0 += 4 * NW) {
+      double v[4];
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        const int64_t c = c0 + cc;
+        v[cc] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {   // n <= 256 = 4 x 64 rows
+          const int64_t rw = lane + 64 * q;
+          const bool in = rw < n && c < n;
+          const double x = fabs((double)A[(in ? rw : 0) + (in ? c : 0) * lda]);
+          v[cc] += in ? x : 0.0;
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        double u = v[cc];
+        for (int off = 32; off >= 1; off >>= 1) u += __shfl_xor(u, off, 64);
+        if (c0 + cc < n && (u > mx || u != u)) mx = u;
+      }
     }
     if (lane == 0) red[w] = mx;
     __syncthreads();
@@ -182,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
 // ---- power table step j: X_2 = beta^2 (A A), X_j = beta (X_{j-1} A)
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower(BatchArgs a, int j) {
-  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
   const int b = task >> 8, tile = task & 255;
   const BatchRes& it = a.res[b];
@@ -256,7 +273,7 @@ __global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bhorner(BatchArgs a, int k) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
-  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
   const int b = task >> 8, tile = task & 255;
   const BatchRes& it = a.res[b];
@@ -304,7 +321,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // ---- squaring q (1..sigma): R_q = R_{q-1}^2, R_0 in L.off_R, ping-pong with P0
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bsquare(BatchArgs a, int q) {
-  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
   const int b = task >> 8, tile = task & 255;
   const BatchRes& it = a.res[b];

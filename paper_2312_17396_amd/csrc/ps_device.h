@@ -35,7 +35,11 @@ constexpr int CSTR = kTileM + 1;      // epilogue tile column stride (elements)
 constexpr int SLABA = BKL * LROWA;    // elements of the A slab of one stage
 constexpr int SLABB = BKL * LROWB;    // elements of the B slab of one stage
 constexpr int STAGE = SLABA + SLABB;
-constexpr int SMEM_BYTES = 2 * STAGE * 8;    // two stages (FP64): 80 KiB (64x64 tiles)
+// LDS of one tile workgroup with working type W: two FP64/FP32 slab stages
+// (80 KiB for FP64, 40 KiB for FP32, so up to four FP32 workgroups share a
+// compute unit); the low-precision stages and the epilogue tile fit in it
+template <typename W>
+constexpr int smem_bytes() { return 2 * STAGE * (int)sizeof(W); }
 constexpr int RUNA = BKL * kTileM / NT;      // consecutive elements each thread moves per slab
 constexpr int RUNB = BKL * kTileN / NT;
 constexpr int TPA = kTileM / RUNA;           // threads per k-row of a normal A slab
@@ -178,16 +182,18 @@ __device__ __forceinline__ void mma_slab(const T* as, const T* bs, int wr, int w
 // wave's two 16x16 blocks.  Two LDS stages and two register sets: the global
 // loads of slab kt+2 are issued before the MFMAs of slab kt, and slab kt+1
 // (loaded one iteration earlier) is stored to the other stage after them.
+// The loop multiplies K slabs [sb, se) (se > sb).
 template <typename T, bool TA, bool TB, bool FULL>
 __device__ __forceinline__ void mainloop_lds_impl(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
-                                    int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
+                                    int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2],
+                                    int64_t sb, int64_t se) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
   T* const S = (T*)smem;   // stage q: A slab at S + q STAGE, B slab after it
   typename MF<T>::V chains[2 * KCH];
 #pragma unroll
   for (int i = 0; i < 2 * KCH; ++i) chains[i] = typename MF<T>::V{0, 0, 0, 0};
-  const int64_t nk = (n + BKL - 1) / BKL;
+  const int64_t nk = se - sb;
   // two register sets: the global loads of slab kt+2 are issued while slab
   // kt+1 is still in flight, so each load has two slab times to arrive.  The
   // loads and LDS stores are unconditional (past the last slab the last slab
@@ -195,9 +201,9 @@ __device__ __forceinline__ void mainloop_lds_impl(const T* __restrict__ A, int64
   // would make the memory-counter wait before each store cover the newer
   // loads as well, which cancels the prefetch.
   T ra0[RUNA], rb0[RUNB], ra1[RUNA], rb1[RUNB];
-  load_a<T, TA, FULL>(A, lda, n, m0, 0, t, ra0);
-  load_b<T, TB, FULL>(B, ldb, n, n0, 0, t, rb0);
-  const int64_t k1 = min<int64_t>(1, nk - 1) * BKL;
+  const int64_t k0 = sb * BKL, k1 = (sb + min<int64_t>(1, nk - 1)) * BKL;
+  load_a<T, TA, FULL>(A, lda, n, m0, k0, t, ra0);
+  load_b<T, TB, FULL>(B, ldb, n, n0, k0, t, rb0);
   load_a<T, TA, FULL>(A, lda, n, m0, k1, t, ra1);
   load_b<T, TB, FULL>(B, ldb, n, n0, k1, t, rb1);
   store_a<T, TA>(S, t, ra0);
@@ -206,7 +212,7 @@ __device__ __forceinline__ void mainloop_lds_impl(const T* __restrict__ A, int64
   auto step = [&](int64_t kt, T* rna, T* rnb, const T* rfa, const T* rfb) {
     // rna/rnb: free set (receives slab kt+2); rfa/rfb: slab kt+1, in flight
     const int cur = (int)(kt & 1);
-    const int64_t kn = min<int64_t>(kt + 2, nk - 1) * BKL;
+    const int64_t kn = (sb + min<int64_t>(kt + 2, nk - 1)) * BKL;
     load_a<T, TA, FULL>(A, lda, n, m0, kn, t, rna);
     load_b<T, TB, FULL>(B, ldb, n, n0, kn, t, rnb);
     if (kt < nk) mma_slab<T>(S + cur * STAGE, S + cur * STAGE + SLABA, wr, wc, g, c, chains);
@@ -241,8 +247,9 @@ __device__ inline bool full_tiles(const T* A, int64_t lda, const T* B, int64_t l
 template <typename T, bool TA, bool TB>
 __device__ __forceinline__ void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
                                     int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
-  if (full_tiles(A, lda, B, ldb, n)) mainloop_lds_impl<T, TA, TB, true>(A, lda, B, ldb, n, m0, n0, smem, acc);
-  else mainloop_lds_impl<T, TA, TB, false>(A, lda, B, ldb, n, m0, n0, smem, acc);
+  const int64_t nk = (n + BKL - 1) / BKL;
+  if (full_tiles(A, lda, B, ldb, n)) mainloop_lds_impl<T, TA, TB, true>(A, lda, B, ldb, n, m0, n0, smem, acc, 0, nk);
+  else mainloop_lds_impl<T, TA, TB, false>(A, lda, B, ldb, n, m0, n0, smem, acc, 0, nk);
 }
 
 // accumulator fragments -> LDS tile Cs[col * CSTR + row] (type W)
@@ -301,7 +308,8 @@ constexpr int LP_RS = 144;                      // LDS row stride (bytes): 16-by
                                                 //   16 consecutive rows hit distinct banks
 constexpr int LP_OPER = 64 * LP_RS;             // one operand slab
 constexpr int LP_STAGE = 2 * LP_OPER + 2 * 64 * 4;   // A, B, then A and B scale words
-static_assert(2 * LP_STAGE <= SMEM_BYTES, "low-precision stages fit the tile LDS");
+static_assert(2 * LP_STAGE <= smem_bytes<float>(), "low-precision stages fit the tile LDS");
+static_assert(kTileN * CSTR * 4 <= smem_bytes<float>(), "epilogue tile fits the tile LDS");
 
 struct LpRegs { uint4 a, b; uint32_t s; };
 

@@ -36,11 +36,7 @@ namespace psk {
 // ---------------------------------------------------------------------------
 template <typename T, bool TA, bool TB>
 __global__ __launch_bounds__(NT) void k_gemm(int64_t n, MatArg A, MatArg B, MatArg C, double alpha, int accumulate) {
-#ifdef PS_GEMM_SMEM_EXTRA
-  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES + PS_GEMM_SMEM_EXTRA];
-#else
-  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
-#endif
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<T>()];
   const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
   int tm, tn;
   tile_of_block(ntm, ntn, tm, tn);
@@ -76,7 +72,7 @@ hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, 
 // ---------------------------------------------------------------------------
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_horner(HornerArgs a) {
-  __shared__ __attribute__((aligned(16))) char smem[SMEM_BYTES];
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   const Layout& L = a.L;
   const int ntm = (int)((a.n + kTileM - 1) / kTileM), ntn = (int)((a.n + kTileN - 1) / kTileN);
