@@ -10,11 +10,13 @@ resident in HBM.  `value` = evals/s of the mixed-precision path.
 Also reported:
   plain       the same workload with every product in FP64 (Algorithm 1)
   accuracy    relative 1-norm distance mixed vs plain (full matrices, GPU)
-  roofline    the dominant kernel (FP64 MFMA GEMM of the power table and the
-              squarings): algorithmic 2 n^3 flops per launch over its average
-              launch duration, from hipEvent pairs around the power-table and
-              squaring phases (library profile mode, same stream), for the
-              same K steps run again after the timed region
+  roofline    the dominant kernel, the FP64 MFMA GEMM tile kernel of the power
+              table (k_gemm_group: one launch per level of ceil(log2 j), one or
+              two n^3 products) and of the squarings (k_gemm): algorithmic
+              2 n^3 flops per product over the average time per product, from
+              hipEvent pairs around the power-table and squaring phases
+              (library profile mode, same stream), for the same K steps run
+              again after the timed region
   cpu_baseline  the CPU oracle's plain FP64 Algorithm 1 + squarings
               (OpenMP, all host cores) on one evaluation of each matrix, plus
               the GPU result's error against the dd oracle on sampled columns
@@ -147,9 +149,10 @@ def main():
             gemm_n += (S - 1) + sg
     avg_ms = gemm_ms / max(gemm_n, 1)
     achieved = 2.0 * N ** 3 / (avg_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_gemm<double> (FP64 MFMA 16x16x4, 64x64 tile)", "bound": "mfma",
+    roofline = {"kernel": "FP64 GEMM tile kernel (k_gemm_group power levels, k_gemm squarings; "
+                          "MFMA 16x16x4, 64x64 tiles)", "bound": "mfma",
                 "achieved": round(achieved, 2), "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_MFMA, 4), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "frac": round(achieved / PEAK_FP64_MFMA, 4), "avg_us_per_product": round(avg_ms * 1e3, 2),
                 "traffic": load_traffic()}
 
     main_mode = "mixed" if "mixed" in res else "plain"

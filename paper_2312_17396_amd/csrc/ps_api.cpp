@@ -237,12 +237,25 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
   if (ps_status e = tm.mark()) return e;
   // 1. power table
   if (J.build_powers && L.s >= 2) {
-    MatArg prev = J.X1;
-    for (int j = 2; j <= L.s; ++j) {
-      MatArg dst = ws_mat(J.ws, L.off_pow + (size_t)(j - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
-      const double alpha = (j == 2) ? J.beta * J.beta : J.beta;
-      PS_HIP(launch_gemm(W, n, J.batch, prev, 0, J.X1, 0, dst, alpha, 0, st));
-      prev = dst;
+    // X_j = X_a X_b (a = ceil(j/2), b = floor(j/2)), one grouped launch per
+    // level (j in (2^(l-1), 2^l]); X_1 = beta X1 enters through alpha
+    auto power = [&](int j) {
+      return j == 1 ? J.X1 : ws_mat(J.ws, L.off_pow + (size_t)(j - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
+    };
+    for (int top = 2; top / 2 < L.s; top *= 2) {
+      const int lo = top / 2 + 1, hi = std::min(top, L.s);   // level: j in (top/2, top]
+      for (int j0 = lo; j0 <= hi; j0 += kMaxGroup) {
+        GemmGroup g;
+        memset(&g, 0, sizeof g);
+        for (int j = j0; j <= std::min(hi, j0 + kMaxGroup - 1); ++j) {
+          const int a = pow_a(j), b = pow_b(j), k = g.count++;
+          g.A[k] = power(a);
+          g.B[k] = power(b);
+          g.C[k] = power(j);
+          g.alpha[k] = (a == 1 ? J.beta : 1.0) * (b == 1 ? J.beta : 1.0);
+        }
+        PS_HIP(launch_gemm_group(W, n, J.batch, g, st));
+      }
     }
   }
   if (ps_status e = tm.mark()) return e;

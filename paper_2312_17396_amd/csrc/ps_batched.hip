@@ -196,7 +196,7 @@ __global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
   for (int q = 0; q < TILE_Q; ++q) X[m0 + row + (n0 + (t >> 6) + NW * q) * np] = v[q];
 }
 
-// ---- power table step j: X_2 = beta^2 (A A), X_j = beta (X_{j-1} A)
+// ---- power table step j: X_j = X_a X_b (a = ceil(j/2), b = floor(j/2), X_1 = beta A)
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower(BatchArgs a, int j) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
@@ -211,9 +211,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const double beta = ldexp(1.0, -it.sigma);
   const int64_t se = (int64_t)(L.slot / sizeof(W));
   W* pw = (W*)(it.ws + L.off_pow);
-  const W* src = (j == 2) ? X1 : pw + (int64_t)(j - 3) * se;
-  gemm_tile<W, false, false>(src, n, X1, n, pw + (int64_t)(j - 2) * se, n, n, n, (int64_t)(tile % ntm) * kTileM,
-                             (int64_t)(tile / ntm) * kTileN, (j == 2) ? beta * beta : beta, 0, smem);
+  // X_j = X_a X_b, a = ceil(j/2), b = floor(j/2): the same products as the
+  // single-matrix path
+  const int pa = (j + 1) / 2, pb = j / 2;
+  const W* xa = (pa == 1) ? X1 : pw + (int64_t)(pa - 2) * se;
+  const W* xb = (pb == 1) ? X1 : pw + (int64_t)(pb - 2) * se;
+  const double alpha = (pa == 1 ? beta : 1.0) * (pb == 1 ? beta : 1.0);
+  gemm_tile<W, false, false>(xa, n, xb, n, pw + (int64_t)(j - 2) * se, n, n, n, (int64_t)(tile % ntm) * kTileM,
+                             (int64_t)(tile / ntm) * kTileN, alpha, 0, smem);
 }
 
 // ---- blocks, norms, low-precision copies of Y: one wave per column
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
   pa.ws = it.ws;
   pa.ws_stride = 0;
   pa.L = L;
-  plan_matrix(pa, L, pa.ws, red, norms);
+  plan_matrix<NT>(pa, L, pa.ws, red, norms);
 }
 
 // ---- Horner step k: k = -1 casts B_{i0} into the format of step i0; k >= 0

@@ -718,7 +718,11 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
 // the Plan; ends with a barrier.  red: NT doubles, norms: PS_MAX_BLOCKS+1
 // doubles, both in LDS.
 // ---------------------------------------------------------------------------
+// PT: threads of the workgroup (red holds 8 PT / 64 doubles).  The norms do
+// not depend on PT: a maximum is the same whatever the partition.
+template <int PT>
 __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, char* ws, double* red, double* norms) {
+  constexpr int PW = PT / 64;
   const int64_t n = L.n;
   const double* colsum = (const double*)(ws + L.off_colsum);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -730,7 +734,7 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
     double mx[8];
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) mx[ii] = 0.0;
-    for (int64_t c = t; c < n; c += NT) {
+    for (int64_t c = t; c < n; c += PT) {
       double sum[8];
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii) sum[ii] = 0.0;
@@ -749,20 +753,22 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
       for (int ii = 0; ii < 8; ++ii)
         if (sum[ii] > mx[ii] || sum[ii] != sum[ii]) mx[ii] = sum[ii];
     }
+    // wave maxima: the eight butterflies interleaved so their shuffles overlap
 #pragma unroll
-    for (int ii = 0; ii < 8; ++ii) {
-      double v = mx[ii];
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double o = __shfl_xor(v, off, 64);
-        if (o > v || o != o) v = o;
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) {
+        const double o = __shfl_xor(mx[ii], off, 64);
+        if (o > mx[ii] || o != o) mx[ii] = o;
       }
-      if (lane == 0) red[ii * NW + w] = v;
-    }
+    if (lane == 0)
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) red[ii * PW + w] = mx[ii];
     __syncthreads();
     if (t < 8 && i0 + t <= a.nB) {
-      double v = red[t * NW];
-      for (int k = 1; k < NW; ++k) {
-        const double o = red[t * NW + k];
+      double v = red[t * PW];
+      for (int k = 1; k < PW; ++k) {
+        const double o = red[t * PW + k];
         if (o > v || o != o) v = o;
       }
       norms[i0 + t] = v;

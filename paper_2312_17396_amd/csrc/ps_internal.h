@@ -85,6 +85,22 @@ struct MatArg {
 hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, MatArg B, int transB,
                        MatArg C, double alpha, int accumulate, hipStream_t st);
 
+// Several independent products of order n in one launch (up to 8):
+// C_k = alpha_k A_k B_k, no transposes; grid (tiles, count, batch).
+constexpr int kMaxGroup = 8;
+struct GemmGroup {
+  MatArg A[kMaxGroup], B[kMaxGroup], C[kMaxGroup];
+  double alpha[kMaxGroup];
+  int count;
+};
+hipError_t launch_gemm_group(int working, int64_t n, int batch, const GemmGroup& g, hipStream_t st);
+
+// Power table by binary splitting: X_j = X_a X_b with a = ceil(j/2),
+// b = floor(j/2) (X_1 = beta A).  Powers with the same ceil(log2 j) depend
+// only on lower ones, so each such level is one grouped launch.
+inline int pow_a(int j) { return (j + 1) / 2; }
+inline int pow_b(int j) { return j / 2; }
+
 // Column pass: B_0..B_r, folded last step, column abs sums, low-precision Y copies.
 struct AssembleArgs {
   int64_t n;

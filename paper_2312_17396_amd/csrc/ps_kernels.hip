@@ -46,6 +46,30 @@ __global__ __launch_bounds__(NT) void k_gemm(int64_t n, MatArg A, MatArg B, MatA
                        accumulate, smem);
 }
 
+// k_gemm_group: product blockIdx.y of a group, one 64 x kTileN tile per workgroup
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gemm_group(int64_t n, GemmGroup g) {
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<T>()];
+  const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
+  int tm, tn;
+  tile_of_block(ntm, ntn, tm, tn);
+  const int k = blockIdx.y;
+  const int64_t b = blockIdx.z;
+  const MatArg A = g.A[k], B = g.B[k], C = g.C[k];
+  gemm_tile<T, false, false>((const T*)A.p + b * A.stride, A.ld, (const T*)B.p + b * B.stride, B.ld,
+                             (T*)C.p + b * C.stride, C.ld, n, n, (int64_t)tm * kTileM, (int64_t)tn * kTileN,
+                             g.alpha[k], 0, smem);
+}
+
+hipError_t launch_gemm_group(int working, int64_t n, int batch, const GemmGroup& g, hipStream_t st) {
+  if (g.count < 1 || g.count > kMaxGroup) return hipErrorInvalidValue;
+  const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
+  dim3 grid(ntm * ntn, g.count, batch), block(NT);
+  if (working == 0) hipLaunchKernelGGL(k_gemm_group<double>, grid, block, 0, st, n, g);
+  else hipLaunchKernelGGL(k_gemm_group<float>, grid, block, 0, st, n, g);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, MatArg B, int transB,
                        MatArg C, double alpha, int accumulate, hipStream_t st) {
   const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
@@ -133,17 +157,19 @@ hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, i
 }
 
 // ---------------------------------------------------------------------------
-// k_plan: one workgroup per matrix
+// k_plan: one workgroup of 1024 threads per matrix (a column per thread up
+// to n = 1024, so the column-sum loads take one memory round trip)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_plan(PlanArgs a) {
-  __shared__ double red[NT];
+constexpr int PLAN_NT = 1024;
+__global__ __launch_bounds__(PLAN_NT) void k_plan(PlanArgs a) {
+  __shared__ double red[8 * PLAN_NT / 64];
   __shared__ double norms[PS_MAX_BLOCKS + 1];
   char* ws = a.ws + (int64_t)blockIdx.x * a.ws_stride;
-  plan_matrix(a, a.L, ws, red, norms);
+  plan_matrix<PLAN_NT>(a, a.L, ws, red, norms);
 }
 
 hipError_t launch_plan(const PlanArgs& a, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(k_plan, dim3(batch), dim3(NT), 0, st, a);
+  hipLaunchKernelGGL(k_plan, dim3(batch), dim3(PLAN_NT), 0, st, a);
   return hipGetLastError();
 }
 
