@@ -211,7 +211,9 @@ def extra_workloads(ps, inputs, torch):
               from a hipGraph vs a loop of single-matrix calls;
     pade_cos  n = 2048 FP64, A = Q diag(lambda) Q^T: Pade [13/13] p and q from one
               power table (s = 4) and Taylor cos of degree 12 in A^2 (s = 4);
-    grad      64 FP32 matrices of order 512: forward + hand-written adjoint."""
+    grad      64 FP32 matrices of order 512: forward + hand-written adjoint;
+    auto      the dense n = 1024 set with the scaling chosen by the alpha_m bound
+              (ps_expm_auto) instead of ceil(log2 ||A||_1)."""
     res = {}
     dev = torch.device("cuda:0")
     # ---- batched
@@ -262,6 +264,20 @@ def extra_workloads(ps, inputs, torch):
     res["grad_batch_512"] = {"batch": 64, "n": 512, "sigma": sigma, "dtype": "f32",
                              "forward_ms": round(tf * 1e3, 3), "backward_ms": round(tb * 1e3, 3),
                              "backward_tflops_credited": round(64 * (gem_f + 2 * gem_f) * 2 * 512 ** 3 / tb / 1e12, 2)}
+    del At, Gt
+    # ---- automatic scaling (alpha_m bound) on the dense n = 1024 set
+    mats = [torch.tensor(inputs.dense_1024(t), device=dev) for t in inputs.DENSE_NORMS]
+    wsa = [ps.auto_workspace(a, M, S) for a in mats]
+    outs = [torch.empty_like(a) for a in mats]
+    sig = [ps.ps_expm_auto(a, M, s=S, mode="mixed", out=o, workspace=w)[1] for a, o, w in zip(mats, outs, wsa)]
+
+    def auto_step():
+        for a, o, w in zip(mats, outs, wsa):
+            ps.ps_expm_auto(a, M, s=S, mode="mixed", out=o, workspace=w)
+    ta = _time(auto_step, 5, torch)
+    res["expm_auto_dense_1024"] = {"sigma_chosen": sig, "sigma_fixed_rule": [inputs.squarings_for(t) for t in inputs.DENSE_NORMS],
+                                   "ms_per_step": round(ta * 1e3, 3), "evals_per_s": round(len(mats) / ta, 1),
+                                   "note": "mixed tiers; includes the two norm read-backs of each call"}
     return res
 
 

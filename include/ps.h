@@ -150,6 +150,35 @@ ps_status ps_expm(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
                   void* E, int64_t lde, const ps_opts* opts, ps_report* report,
                   void* ws, size_t ws_bytes, void* stream);
 
+/* Automatic scaling for the Taylor approximant (section 3.2, eq.
+ * (alpha_m-X)).  theta_m: the largest theta with
+ * sum_{k>m} theta^k / k! <= u, u the unit roundoff of dtype (2^-53 or
+ * 2^-24), so that the truncation error of p_m at alpha = alpha_m(X) is at
+ * most u.  Host only.  0 <= m <= 170. */
+ps_status ps_theta_taylor(ps_dtype dtype, int m, double* theta);
+
+/* Workspace bytes for ps_expm_auto (the power table reaches
+ * max(s, d* + 1), d* = max{d : d(d-1) <= m+1}, and a squaring buffer). */
+ps_status ps_workspace_size_auto(ps_dtype dtype, int64_t n, int m, int s, size_t* bytes);
+
+/* E = p_m(2^-sigma A)^(2^sigma) with sigma chosen by the alpha_m bound:
+ *   sigma0 = the smallest sigma >= 0 with 2^-sigma ||A||_1 <= theta_m;
+ *   X0 = 2^-sigma0 A; the powers X0^2 .. X0^max(s, d*+1) are formed once;
+ *   alpha = 2^sigma0 max(||X0^d*||_1^(1/d*), ||X0^(d*+1)||_1^(1/(d*+1)));
+ *   sigma = the smallest sigma >= 0 with 2^-sigma alpha <= theta_m
+ *   (<= sigma0); with norm_guard != 0 also ||2^-sigma A||_1 <= s / e, the
+ *   norm under which section 3 guarantees the decay the mixed plan relies on.
+ * The PS evaluation reuses the power table (X^j = 2^(j (sigma0 - sigma)) X0^j,
+ * an exact rescaling).  Taylor coefficients 1/k!, m <= 170; s as in
+ * ps_expm.  The chosen sigma is written to *sigma_out (may be NULL).
+ * Norms are 1-norms of the column-major matrix.  The call synchronizes the
+ * stream twice (it reads two norms back to the host), so it cannot be
+ * captured into a graph.  Errors: PS_ERR_ARG also for non-finite input. */
+ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m, int s,
+                       int norm_guard, void* E, int64_t lde, const ps_opts* opts,
+                       ps_report* report, int* sigma_out, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* Several polynomials of one matrix sharing one power table (section 4:
  * the Pade numerator and denominator; the cosine, which is a polynomial in
  * X^2).  square_arg = 0: P_t = p_t(A); square_arg = 1: P_t = p_t(A^2)

@@ -15,6 +15,15 @@ TEST INFRASTRUCTURE ONLY (part of the oracle).
       d = floor((1 + sqrt(4m + 5)) / 2)  (section 3.2).
   extra_scaling(normX, s)  l_0 = ceil(log2(e ||X||_1 / s)), the number of
       extra squarings that would force ||X||_1 <= s/e (section 3.2).
+  theta_taylor(m, u)  the largest theta with sum_{k>m} theta^k / k! <= u, the
+      Taylor truncation error at the scalar alpha_m of eq. (alpha_m-X) with
+      the practical estimate xi(X) taken as 1 (50-digit decimal arithmetic,
+      bisection).
+  auto_sigma(A, m, s, u, norm_guard)  the scaling chosen by the alpha_m
+      bound: sigma0 from ||A||_1 <= 2^sigma0 theta_m, alpha_m of
+      X0 = 2^-sigma0 A from its powers (repeated multiplication in IEEE
+      double), sigma the smallest with 2^-sigma alpha_m(A) <= theta_m; with
+      norm_guard also ||2^-sigma A||_1 <= s / e (section 3.2).
 """
 from __future__ import annotations
 
@@ -65,3 +74,64 @@ def alpha_m(X, m: int) -> float:
 
 def extra_scaling(normX: float, s: int) -> int:
     return int(math.ceil(math.log2(math.e * normX / s)))
+
+
+def _taylor_tail_dec(t, m):
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 50
+        t = Decimal(t)
+        term = Decimal(1)
+        for k in range(1, m + 2):
+            term = term * t / k
+        total = term
+        k = m + 2
+        while True:
+            term = term * t / k
+            total += term
+            if term <= total * Decimal("1e-45"):
+                return total
+            k += 1
+
+
+def theta_taylor(m: int, u: float) -> float:
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 50
+        ud = Decimal(u)
+        lo, hi = Decimal(0), Decimal(1)
+        while _taylor_tail_dec(hi, m) <= ud:
+            hi *= 2
+        for _ in range(120):
+            mid = (lo + hi) / 2
+            if _taylor_tail_dec(mid, m) <= ud:
+                lo = mid
+            else:
+                hi = mid
+        return float(lo)
+
+
+def _smallest_shift(a: float, b: float) -> int:
+    """smallest k >= 0 with a <= 2^k b"""
+    k = 0
+    while a > math.ldexp(b, k):
+        k += 1
+    return k
+
+
+def auto_sigma(A, m: int, s: int, u: float, norm_guard: bool = False) -> int:
+    A = np.asarray(A, dtype=np.float64)
+    th = theta_taylor(m, u)
+    nA = norm1(A)
+    s0 = _smallest_shift(nA, th)
+    X0 = A * math.ldexp(1.0, -s0)
+    d = 1
+    while (d + 1) * d <= m + 1:
+        d += 1
+    Pd = np.linalg.matrix_power(X0, d)
+    Pd1 = Pd @ X0
+    a0 = max(norm1(Pd) ** (1.0 / d), norm1(Pd1) ** (1.0 / (d + 1)))
+    sig = min(s0, _smallest_shift(math.ldexp(a0, s0), th))
+    if norm_guard:
+        sig = max(sig, _smallest_shift(math.e * nA, float(s)))
+    return sig

@@ -75,6 +75,9 @@ _SIGS = {
     "ps_workspace_size": ([_i, _i64, _i, _i, _i, _szp], _i),
     "ps_eval": ([_i, _i64, _vp, _i64, _dp, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
     "ps_expm": ([_i, _i64, _vp, _i64, _dp, _i, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
+    "ps_theta_taylor": ([_i, _i, _dp], _i),
+    "ps_workspace_size_auto": ([_i, _i64, _i, _i, _szp], _i),
+    "ps_expm_auto": ([_i, _i64, _vp, _i64, _i, _i, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
     "ps_workspace_size_multi": ([_i, _i64, _i, _ip, _i, _i, _szp], _i),
     "ps_eval_multi": ([_i, _i64, _vp, _i64, _i, ctypes.POINTER(_dp), _ip, _i, _i, ctypes.POINTER(_vp), _i64p,
                        _op, _rp, _vp, _sz, _vp], _i),
@@ -250,6 +253,45 @@ def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
     _check(lib().ps_expm(dt, n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n, ctypes.byref(o),
                          ctypes.byref(rep) if rep is not None else None, wsp, wsb, _stream_ptr(A.device)))
     return (E, rep.to_dict()) if rep is not None else E
+
+
+def theta_taylor(m, dtype="f64"):
+    """Largest theta with sum_{k>m} theta^k/k! <= u (u = 2^-53 or 2^-24), host only."""
+    th = ctypes.c_double()
+    _check(lib().ps_theta_taylor(0 if dtype == "f64" else 1, int(m), ctypes.byref(th)))
+    return th.value
+
+
+def ps_expm_auto(A, m, s=0, norm_guard=False, mode="fixed", tier_mask=0, delta=10.0, report=False,
+                 profile=False, out=None, workspace=None):
+    """E = p_m(2^-sigma A)^(2^sigma) with sigma from the alpha_m bound (Taylor
+    coefficients); returns (E, sigma) or (E, sigma, report).  The norms are
+    those of the column-major view (the transpose of a row-major tensor)."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if workspace is None:
+        nbytes = ctypes.c_size_t()
+        _check(lib().ps_workspace_size_auto(dt, n, int(m), int(s), ctypes.byref(nbytes)))
+        ws, wsp, wsb = _workspace(nbytes.value, A.device)
+    else:
+        ws, wsp, wsb = workspace
+    E = torch.empty_like(A) if out is None else out
+    o, _k = _opts(mode, tier_mask, delta, None, profile)
+    rep = ps_report() if (report or profile) else None
+    sig = ctypes.c_int()
+    _check(lib().ps_expm_auto(dt, n, A.data_ptr(), n, int(m), int(s), int(bool(norm_guard)), E.data_ptr(), n,
+                              ctypes.byref(o), ctypes.byref(rep) if rep is not None else None, ctypes.byref(sig),
+                              wsp, wsb, _stream_ptr(A.device)))
+    return (E, sig.value, rep.to_dict()) if rep is not None else (E, sig.value)
+
+
+def auto_workspace(A, m, s=0):
+    """Pre-allocate a workspace for repeated ps_expm_auto calls of this shape."""
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_auto(_dtype_code(A), A.shape[0], int(m), int(s), ctypes.byref(nbytes)))
+    return _workspace(nbytes.value, A.device)
 
 
 def expm_workspace(A, m, s=0, sigma=0):

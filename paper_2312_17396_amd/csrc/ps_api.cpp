@@ -112,7 +112,7 @@ Opts read_opts(const ps_opts* o, int working) {
 
 namespace psk {
 
-Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg) {
+Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg, int npow_min) {
   Layout L;
   memset(&L, 0, sizeof L);
   L.n = n;
@@ -133,7 +133,7 @@ Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_a
   size_t packed16 = (size_t)L.Mp * L.Kp * 2;
   L.pslot = al256(std::max({L.slot, packed8, packed16}));
   size_t off = 0;
-  L.npow = (s >= 2 ? s - 1 : 0) + (square_arg ? 1 : 0);
+  L.npow = std::max((s >= 2 ? s - 1 : 0) + (square_arg ? 1 : 0), npow_min);
   L.off_pow = off;   off += L.npow * L.slot;
   L.off_B = off;     off += (size_t)L.nB * L.slot;
   L.off_P0 = off;    off += L.pslot;
@@ -191,6 +191,7 @@ struct Job {
   bool write_y;          // produce the low-precision copies of Y (first polynomial only)
   bool build_powers;     // run the power table (first polynomial only)
   bool skip_square;      // squarings handled by the caller
+  int pow_shift = 0;     // power slots hold 2^(-j pow_shift) X_j (prebuilt, exact rescaling)
 };
 
 MatArg ws_mat(char* ws, size_t off, int64_t n, size_t stride_bytes, int esize) {
@@ -275,6 +276,7 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
   aa.trivial_last = L.trivial_last;
   aa.X1 = J.X1;
   aa.x1_scale = J.beta;
+  aa.pow_shift = J.pow_shift;
   aa.ws = J.ws;
   aa.ws_stride = wss;
   aa.L = L;
@@ -314,7 +316,7 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
     ha.yscale = J.beta;
   } else {
     ha.ysrc = ws_mat(J.ws, L.off_pow + (size_t)(L.s - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
-    ha.yscale = 1.0;
+    ha.yscale = ldexp(1.0, L.s * J.pow_shift);
   }
   const int i0 = L.first_step;
   // cast of the first block into the operand format of step i0 (or the result)
@@ -391,6 +393,71 @@ ps_status ps_set_error(ps_status st, const char* msg) {
 // ===========================================================================
 // exported entry points
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// automatic scaling (section 3.2, eq. (alpha_m-X)): sigma from the alpha_m
+// bound on the Taylor truncation error
+// ---------------------------------------------------------------------------
+namespace {
+
+// Taylor remainder sum_{k > m} t^k / k! (t >= 0), long double
+long double taylor_tail(long double t, int m) {
+  long double term = 1.0L;
+  for (int k = 1; k <= m + 1; ++k) term *= t / k;
+  long double sum = term;
+  for (int k = m + 2; k < m + 2000; ++k) {
+    term *= t / k;
+    sum += term;
+    if (term <= sum * 1e-21L) break;
+  }
+  return sum;
+}
+
+// largest theta with taylor_tail(theta, m) <= u (bisection; the tail is increasing)
+double theta_taylor(int m, double u) {
+  long double lo = 0.0L, hi = 1.0L;
+  while (taylor_tail(hi, m) <= u && hi < 1e4L) hi *= 2;
+  for (int it = 0; it < 200; ++it) {
+    const long double mid = 0.5L * (lo + hi);
+    if (taylor_tail(mid, m) <= u) lo = mid;
+    else hi = mid;
+  }
+  return (double)lo;
+}
+
+// d* = max{d >= 1 : d (d - 1) <= m + 1}
+int alpha_dstar(int m) {
+  int d = 1;
+  while ((d + 1) * d <= m + 1) ++d;
+  return d;
+}
+
+// max over the workgroup pieces written by launch_norm1 (host side, after a sync)
+ps_status read_norm1(const double* dev, int64_t n, hipStream_t st, double* out) {
+  std::vector<double> h((size_t)norm1_groups(n));
+  PS_HIP(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  PS_HIP(hipStreamSynchronize(st));
+  double m = 0.0;
+  for (double v : h)
+    if (v > m || v != v) m = v;
+  *out = m;
+  return PS_OK;
+}
+
+int ceil_log2_ratio(double a, double b) {   // smallest k >= 0 with a <= 2^k b
+  if (!(a > b)) return 0;
+  int k = (int)std::ceil(std::log2(a / b));
+  while (k > 0 && std::ldexp(b, k - 1) >= a) --k;
+  while (std::ldexp(b, k) < a) ++k;
+  return k;
+}
+
+}  // namespace
+
+static Layout auto_layout(ps_dtype dtype, int64_t n, int m, int s) {
+  const int D = std::max(s, alpha_dstar(m) + 1);
+  return make_layout(dtype, n, m, s, 1, 0, D - 1);
+}
+
 extern "C" {
 
 int ps_version(void) { return 10000; }
@@ -538,6 +605,110 @@ static ps_status expm_impl(ps_dtype dtype, int batch, int64_t n, const void* A, 
   if (reports)
     for (int b = 0; b < batch; ++b)
       if (ps_status e = fill_report(L, J, b, &reports[b], st, o.profile ? ms : nullptr)) return e;
+  return PS_OK;
+}
+
+ps_status ps_theta_taylor(ps_dtype dtype, int m, double* theta) {
+  if (dtype != PS_F64 && dtype != PS_F32) return fail(PS_ERR_ARG, "dtype must be PS_F64 or PS_F32");
+  if (m < 0 || m > 170 || !theta) return fail(PS_ERR_ARG, "ps_theta_taylor: m in [0,170], theta != NULL");
+  *theta = theta_taylor(m, dtype == PS_F64 ? 0x1p-53 : 0x1p-24);
+  return PS_OK;
+}
+
+ps_status ps_workspace_size_auto(ps_dtype dtype, int64_t n, int m, int s, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  if (ps_status e = check_common(dtype, n, m, &s, 1)) return e;
+  *bytes = auto_layout(dtype, n, m, s).bytes;
+  return PS_OK;
+}
+
+ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m, int s, int norm_guard, void* E,
+                       int64_t lde, const ps_opts* opts, ps_report* report, int* sigma_out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (ps_status e = check_common(dtype, n, m, &s, 1)) return e;
+  if (m > 170) return fail(PS_ERR_ARG, "the automatic scaling uses the Taylor coefficients: m <= 170");
+  if (!A || !E) return fail(PS_ERR_ARG, "NULL matrix pointer");
+  if (lda < n || lde < n) return fail(PS_ERR_ARG, "leading dimension smaller than n");
+  const int esize = dtype == PS_F64 ? 8 : 4;
+  const size_t spanA = mat_span_bytes(n, lda, esize), spanE = mat_span_bytes(n, lde, esize);
+  if (overlap(A, spanA, E, spanE)) return fail(PS_ERR_ALIAS, "output overlaps the input matrix");
+  Opts o = read_opts(opts, dtype == PS_F64 ? 0 : 1);
+  if (ps_status e = check_opts(o)) return e;
+  if (o.override_tiers) return fail(PS_ERR_UNSUPPORTED, "tier_override is not supported by ps_expm_auto");
+  Layout L = auto_layout(dtype, n, m, s);
+  if (ps_status e = check_ws(ws, ws_bytes, L.bytes)) return e;
+  if (overlap(ws, L.bytes, E, spanE) || overlap(ws, L.bytes, A, spanA))
+    return fail(PS_ERR_ALIAS, "workspace overlaps a matrix argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int W = dtype == PS_F64 ? 0 : 1;
+  const double theta = theta_taylor(m, W == 0 ? 0x1p-53 : 0x1p-24);
+  const int dstar = alpha_dstar(m), D = std::max(s, dstar + 1);
+  double* wg = (double*)((char*)ws + L.off_colsum);   // scratch until the blocks are assembled
+  const MatArg X1{A, lda, 0};
+  auto power = [&](int j) { return j == 1 ? X1 : ws_mat((char*)ws, L.off_pow + (size_t)(j - 2) * L.slot, n, 0, esize); };
+  // 1. ||A||_1 and the first scaling sigma0 (||X0||_1 <= theta for X0 = 2^-sigma0 A)
+  double nA = 0.0;
+  PS_HIP(launch_norm1(W, n, X1, wg, st));
+  if (ps_status e = read_norm1(wg, n, st, &nA)) return e;
+  if (!std::isfinite(nA)) return fail(PS_ERR_ARG, "input matrix has non-finite entries");
+  const int sigma0 = ceil_log2_ratio(nA, theta);
+  if (sigma0 > kMaxSigma) return fail(PS_ERR_ARG, "||A||_1 = %g needs more than %d squarings", nA, kMaxSigma);
+  const double beta0 = ldexp(1.0, -sigma0);
+  // 2. X0^2 .. X0^D by the level schedule of the power table
+  for (int top = 2; top / 2 < D; top *= 2) {
+    const int lo = top / 2 + 1, hi = std::min(top, D);
+    for (int j0 = lo; j0 <= hi; j0 += kMaxGroup) {
+      GemmGroup g;
+      memset(&g, 0, sizeof g);
+      for (int j = j0; j <= std::min(hi, j0 + kMaxGroup - 1); ++j) {
+        const int a = pow_a(j), b = pow_b(j), k = g.count++;
+        g.A[k] = power(a);
+        g.B[k] = power(b);
+        g.C[k] = power(j);
+        g.alpha[k] = (a == 1 ? beta0 : 1.0) * (b == 1 ? beta0 : 1.0);
+      }
+      PS_HIP(launch_gemm_group(W, n, 1, g, st));
+    }
+  }
+  // 3. alpha_m(X0) = max(||X0^d*||^(1/d*), ||X0^(d*+1)||^(1/(d*+1))), sigma for A
+  double nd[2];
+  for (int q = 0; q < 2; ++q) {
+    const int d = dstar + q;
+    if (d == 1) {
+      nd[q] = beta0 * nA;
+      continue;
+    }
+    PS_HIP(launch_norm1(W, n, power(d), wg, st));
+    if (ps_status e = read_norm1(wg, n, st, &nd[q])) return e;
+  }
+  const double alpha0 = std::max(std::pow(nd[0], 1.0 / dstar), std::pow(nd[1], 1.0 / (dstar + 1)));
+  // alpha_m(A) = 2^sigma0 alpha_m(X0) <= ||A||_1, so sigma <= sigma0
+  int sigma = std::min(sigma0, ceil_log2_ratio(ldexp(alpha0, sigma0), theta));
+  if (norm_guard) sigma = std::max(sigma, ceil_log2_ratio(M_E * nA, (double)s));   // ||X||_1 <= s / e
+  if (sigma > kMaxSigma) return fail(PS_ERR_ARG, "the norm guard needs more than %d squarings", kMaxSigma);
+  // 4. evaluation on X = 2^-sigma A with the prebuilt powers: X^j = 2^(j (sigma0 - sigma)) X0^j
+  std::vector<double> c(m + 1);
+  ps_coef_taylor_exp(m, c.data());
+  L.sigma = sigma;
+  Job J;
+  J.L = &L;
+  J.batch = 1;
+  J.X1 = X1;
+  J.beta = ldexp(1.0, -sigma);
+  J.coef = c.data();
+  J.out = MatArg{E, lde, 0};
+  J.ws = (char*)ws;
+  J.ws_stride = L.bytes;
+  J.opts = o;
+  J.write_y = true;
+  J.build_powers = false;
+  J.skip_square = false;
+  J.pow_shift = sigma0 - sigma;
+  float ms[4] = {0, 0, 0, 0};
+  if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
+  if (sigma_out) *sigma_out = sigma;
+  if (report)
+    if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
   return PS_OK;
 }
 

@@ -181,6 +181,7 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
     aa.trivial_last = L.trivial_last;
     aa.X1 = Am;
     aa.x1_scale = beta;
+    aa.pow_shift = 0;
     aa.ws = base;
     aa.ws_stride = wss;
     aa.L = L;

@@ -240,6 +240,7 @@ __global__ __launch_bounds__(NT) void k_bassemble(BatchArgs a) {
   aa.trivial_last = L.trivial_last;
   aa.X1 = MatArg{it.X1, L.n, 0};
   aa.x1_scale = ldexp(1.0, -it.sigma);
+  aa.pow_shift = 0;
   aa.ws = it.ws;
   aa.ws_stride = 0;
   aa.L = L;
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(NT) void k_bassemble(BatchArgs a) {
 template <typename W>
 __global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
-  __shared__ double red[NT];
+  __shared__ double red[8 * NW];
   __shared__ double norms[PS_MAX_BLOCKS + 1];
   const int b = blockIdx.x;
   const BatchRes& it = a.res[b];

@@ -638,7 +638,8 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int64_t rr = valid[q] ? rw[q] : r_begin;
-      const W x = (j == 1) ? (W)(x1s * (double)X1[rr + col * a.X1.ld]) : pw[(int64_t)(j - 2) * se + rr + col * n];
+      const W x = (j == 1) ? (W)(x1s * (double)X1[rr + col * a.X1.ld])
+                           : (W)ldexp((double)pw[(int64_t)(j - 2) * se + rr + col * n], j * a.pow_shift);
       out[q] = valid[q] ? x : W(0);
     }
   };
@@ -676,7 +677,7 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
 #pragma unroll
       for (int q = 0; q < RPL; ++q) bv[q][ii] = (rw[q] == col && col < a.nv) ? c0 : W(0);
     }
-#pragma unroll 4
+#pragma unroll 2
     for (int j = 1; j < s; ++j) {
       W xj[RPL];
       load_x(j, xj);

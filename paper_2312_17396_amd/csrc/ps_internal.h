@@ -61,7 +61,7 @@ struct Layout {
   size_t bytes;        // total per matrix
 };
 
-Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg);
+Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg, int npow_min = 0);
 
 }  // namespace psk
 
@@ -108,6 +108,7 @@ struct AssembleArgs {
   int m, s, r, nB, trivial_last;
   MatArg X1;            // X_1 = x1_scale * X1
   double x1_scale;
+  int pow_shift;        // X_j = 2^(j pow_shift) * (power slot j), j >= 2 (exact rescaling)
   char* ws;             // base of matrix 0's region
   size_t ws_stride;     // bytes per matrix
   Layout L;
@@ -128,6 +129,11 @@ struct PlanArgs {
   Layout L;
 };
 hipError_t launch_plan(const PlanArgs& a, int batch, hipStream_t st);
+
+// 1-norm pieces: wgmax[g] = max over the columns of workgroup g (NW columns)
+// of the column abs sums of the n x n matrix X (leading dimension ld).
+hipError_t launch_norm1(int working, int64_t n, MatArg X, double* wgmax, hipStream_t st);
+inline int64_t norm1_groups(int64_t n) { return (n + 7) / 8; }
 
 // One Horner step: P_{i-1} = B_{i-1} + P_i Y (or, with cast_only, P = B_src
 // converted to the format of the consumer step).

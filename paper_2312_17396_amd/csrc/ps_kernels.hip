@@ -157,19 +157,56 @@ hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, i
 }
 
 // ---------------------------------------------------------------------------
-// k_plan: one workgroup of 1024 threads per matrix (a column per thread up
-// to n = 1024, so the column-sum loads take one memory round trip)
+// k_norm1: column abs sums (one wave per column), maximum per workgroup
 // ---------------------------------------------------------------------------
-constexpr int PLAN_NT = 1024;
-__global__ __launch_bounds__(PLAN_NT) void k_plan(PlanArgs a) {
-  __shared__ double red[8 * PLAN_NT / 64];
+template <typename W>
+__global__ __launch_bounds__(NT) void k_norm1(int64_t n, MatArg X, double* wgmax) {
+  __shared__ double red[NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t col = (int64_t)blockIdx.x * NW + w;
+  const W* x = (const W*)X.p;
+  double v = 0.0;
+  if (col < n) {
+    double part[4] = {0.0, 0.0, 0.0, 0.0};   // four independent partial sums per lane
+    for (int64_t r0 = 0; r0 < n; r0 += 256) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t rw = r0 + 64 * q + lane;
+        part[q] += (rw < n) ? fabs((double)x[rw + col * X.ld]) : 0.0;
+      }
+    }
+    v = (part[0] + part[1]) + (part[2] + part[3]);
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  }
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (t == 0) {
+    double m = red[0];
+    for (int k = 1; k < NW; ++k)
+      if (red[k] > m || red[k] != red[k]) m = red[k];
+    wgmax[blockIdx.x] = m;
+  }
+}
+
+hipError_t launch_norm1(int working, int64_t n, MatArg X, double* wgmax, hipStream_t st) {
+  const dim3 grid((unsigned)norm1_groups(n)), block(NT);
+  if (working == 0) hipLaunchKernelGGL(k_norm1<double>, grid, block, 0, st, n, X, wgmax);
+  else hipLaunchKernelGGL(k_norm1<float>, grid, block, 0, st, n, X, wgmax);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k_plan: one workgroup per matrix
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_plan(PlanArgs a) {
+  __shared__ double red[8 * NW];
   __shared__ double norms[PS_MAX_BLOCKS + 1];
   char* ws = a.ws + (int64_t)blockIdx.x * a.ws_stride;
-  plan_matrix<PLAN_NT>(a, a.L, ws, red, norms);
+  plan_matrix<NT>(a, a.L, ws, red, norms);
 }
 
 hipError_t launch_plan(const PlanArgs& a, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(k_plan, dim3(batch), dim3(PLAN_NT), 0, st, a);
+  hipLaunchKernelGGL(k_plan, dim3(batch), dim3(NT), 0, st, a);
   return hipGetLastError();
 }
 

@@ -111,3 +111,14 @@ def test_argument_validation_before_device_work(ps, args, code):
 def test_unimplemented_entry_points_report_unsupported(ps):
     L = ps.lib()
     assert L.ps_batched_launch(None, None) in (-1, -5)
+
+
+def test_theta_taylor_host_matches_oracle():
+    from oracle import metrics
+    import paper_2312_17396_amd as ps
+    for dt, u in (("f64", 2.0 ** -53), ("f32", 2.0 ** -24)):
+        for m in (0, 1, 2, 5, 10, 18, 30, 45, 60, 100, 170):
+            a, b = ps.theta_taylor(m, dt), metrics.theta_taylor(m, u)
+            assert abs(a - b) <= 1e-12 * b, (dt, m, a, b)
+    with pytest.raises(ps.PSError):
+        ps.theta_taylor(171)

@@ -90,6 +90,8 @@ def test_rotation_generator(ps):
 @pytest.mark.parametrize("n,m,s,sigma,t", [
     (1, 16, 4, 0, 1.0), (2, 7, 3, 0, 0.5), (17, 16, 4, 0, 1.0), (64, 16, 4, 0, 1.0), (100, 30, 6, 2, 4.0),
     (130, 13, 4, 0, 1.0), (200, 18, 5, 1, 2.0), (257, 30, 6, 0, 0.1), (96, 12, 1, 0, 0.3), (65, 9, 9, 0, 0.8),
+    # block sizes whose power table has levels of 4, 6 and 8 products per launch
+    (40, 100, 16, 0, 2.0), (24, 170, 14, 1, 3.0),
 ])
 @pytest.mark.parametrize("mode", ["fixed", "mixed"])
 def test_fp64_vs_oracle_small(ps, n, m, s, sigma, t, mode):

@@ -381,3 +381,38 @@ def test_gradient_oracle_polynomial_closed_form():
     gh, gl = oracle.expm_grad_dd(X, G, [0.0, 0.0, 1.0], 0, cols=[1, 4])
     want = (G @ X.T + X.T @ G)[:, [1, 4]]
     assert np.max(np.abs(gh + gl - want)) < 1e-14 * np.max(np.abs(want))
+
+
+# ---------------------------------------------- P10: truncation threshold of the alpha_m bound
+@pytest.mark.parametrize("u", [2.0 ** -53, 2.0 ** -24])
+def test_theta_taylor_closed_forms_and_bounds(u):
+    # m = 0: the tail is e^t - 1, so theta_0 = log1p(u) exactly
+    assert abs(metrics.theta_taylor(0, u) - math.log1p(u)) <= 1e-14 * u
+    # m = 1: e^t - 1 - t = u, theta_1 = sqrt(2u) (1 - sqrt(2u)/6 + O(u))
+    r = math.sqrt(2 * u)
+    assert abs(metrics.theta_taylor(1, u) / r - (1 - r / 6)) <= 4 * r * r
+    # all m: t^(m+1)/(m+1)! <= tail(t) <= t^(m+1)/(m+1)! / (1 - t/(m+2)) for t < m+2
+    for m in (2, 5, 10, 18, 30, 60, 100, 170):
+        th = metrics.theta_taylor(m, u)
+        lead = math.exp((math.lgamma(m + 2) + math.log(u)) / (m + 1))   # ((m+1)! u)^(1/(m+1))
+        assert th <= lead * (1 + 1e-12)
+        if lead < m + 2:
+            assert th >= lead * (1 - lead / (m + 2)) ** (1.0 / (m + 1)) * (1 - 1e-12)
+    ths = [metrics.theta_taylor(m, u) for m in range(0, 40)]
+    assert all(a < b for a, b in zip(ths, ths[1:]))
+
+
+def test_auto_sigma_on_the_nonnormal_example():
+    # A = [[-0.1, 1e6], [0, -0.1]] (eq. (nonnormal-mat-A)): ||A||_1 ~ 1e6 asks for
+    # 19 halvings, while alpha_m(A) = 2 alpha_m(A/2) ~ 1.3 (pinned above) is
+    # below theta_30 ~ 3.78: the alpha_m bound needs no scaling at all
+    A = np.array([[-0.1, 1e6], [0.0, -0.1]])
+    u = 2.0 ** -53
+    th = metrics.theta_taylor(30, u)
+    assert metrics.auto_sigma(A, 30, 6, u) == 0
+    assert math.ldexp(th, 18) < metrics.norm1(A) <= math.ldexp(th, 19)
+    # the norm guard forces ||X||_1 <= s/e: l_0 = ceil(log2(e ||A||_1 / 6)) = 19
+    assert metrics.auto_sigma(A, 30, 6, u, norm_guard=True) == math.ceil(math.log2(math.e * metrics.norm1(A) / 6))
+    # a normal matrix: alpha_m = ||A||_1 for a diagonal one, so sigma = sigma0
+    D = np.diag([-9.0, 3.0, 1.0])
+    assert metrics.auto_sigma(D, 30, 6, u) == math.ceil(math.log2(9.0 / th))
