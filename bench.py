@@ -213,7 +213,11 @@ def extra_workloads(ps, inputs, torch):
               power table (s = 4) and Taylor cos of degree 12 in A^2 (s = 4);
     grad      64 FP32 matrices of order 512: forward + hand-written adjoint;
     auto      the dense n = 1024 set with the scaling chosen by the alpha_m bound
-              (ps_expm_auto) instead of ceil(log2 ||A||_1)."""
+              (ps_expm_auto) instead of ceil(log2 ||A||_1);
+    dd        n = 1024, ||A||_1 = 1, Taylor m = 30 (theta_30 = 1.16 at u = 2^-106,
+              so no scaling), s = 6, double-double working precision: every
+              product in double-double vs the planned tiers below it."""
+    import numpy as np
     res = {}
     dev = torch.device("cuda:0")
     # ---- batched
@@ -278,6 +282,19 @@ def extra_workloads(ps, inputs, torch):
     res["expm_auto_dense_1024"] = {"sigma_chosen": sig, "sigma_fixed_rule": [inputs.squarings_for(t) for t in inputs.DENSE_NORMS],
                                    "ms_per_step": round(ta * 1e3, 3), "evals_per_s": round(len(mats) / ta, 1),
                                    "note": "mixed tiers; includes the two norm read-backs of each call"}
+    del mats, outs, wsa
+    # ---- double-double working precision
+    Ad = inputs.dense_1024(1.0)
+    Td = torch.tensor(np.stack([Ad, np.zeros_like(Ad)]), dtype=torch.float64, device=dev)
+    wsd = ps.dd_workspace(1024, 30, 6, 0)
+    Ed = torch.empty_like(Td)
+    out = {"n": 1024, "m": 30, "s": 6, "sigma": 0, "dtype": "dd"}
+    for mode in ("fixed", "mixed"):
+        _, rep = ps.ps_expm_dd(Td, 30, s=6, mode=mode, out=Ed, workspace=wsd, report=True)
+        t = _time(lambda: ps.ps_expm_dd(Td, 30, s=6, mode=mode, out=Ed, workspace=wsd), 3, torch)
+        out[mode] = {"ms": round(t * 1e3, 3), "tiers": [ps.TIER_NAMES[x] for x in rep["tier"][:rep["first_step"] + 1]]}
+    out["speedup_mixed_vs_fixed"] = round(out["fixed"]["ms"] / out["mixed"]["ms"], 3)
+    res["expm_dd_1024"] = out
     return res
 
 

@@ -54,7 +54,11 @@ typedef enum {
 } ps_status;
 
 /* Working (target) precision; also the element type of A and of the result. */
-typedef enum { PS_F64 = 0, PS_F32 = 1 } ps_dtype;
+typedef enum {
+  PS_F64 = 0,
+  PS_F32 = 1,
+  PS_DD = 2   /* double-double (two FP64 planes); ps_plan and the *_dd entry points only */
+} ps_dtype;
 
 /* Precision tiers of the Horner products (unit roundoffs 2^-53, 2^-24,
  * 2^-8, 2^-4).  FP8 is OCP E4M3 with a power-of-two (E8M0) scale per 32
@@ -178,6 +182,32 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
                        int norm_guard, void* E, int64_t lde, const ps_opts* opts,
                        ps_report* report, int* sigma_out, void* ws, size_t ws_bytes,
                        void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Double-double working precision (u = 2^-106) with the FP64, FP32, BF16 and
+ * MX-FP8 tiers below it: the multi-precision setting the paper is written
+ * for (sections 1 and 4, Table 1), with Algorithm 3's plan over five tiers
+ * (tier code 4 = double-double).
+ * A double-double matrix argument points to 2 ld n doubles: the hi plane
+ * (column-major, leading dimension ld) followed by the lo plane; each entry
+ * is hi + lo.
+ * ------------------------------------------------------------------------- */
+
+/* Workspace bytes for ps_expm_dd.  s = 0 selects ceil(sqrt(m)). */
+ps_status ps_workspace_size_dd(int64_t n, int m, int s, int sigma, size_t* bytes);
+
+/* E = p(2^-sigma A)^(2^sigma) in double-double (scaling and squaring
+ * around the PS evaluation, eq. (scal-idea)).  A, E: double-double n x n
+ * (lda, lde >= n), not overlapping.  coef: host array of 2 (m+1) doubles,
+ * hi parts c_0..c_m then lo parts, or NULL for the Taylor coefficients 1/k!
+ * rounded to double-double (m <= 170).  0 <= sigma <= 500.  opts: mode
+ * fixed (every product in double-double) or mixed (tiers 0..3 below it as
+ * the plan allows; tier_override unsupported).  report may be NULL.  The
+ * call synchronizes the stream once (coefficient upload) and again when a
+ * report is asked for. */
+ps_status ps_expm_dd(int64_t n, const double* A, int64_t lda, const double* coef, int m, int s, int sigma,
+                     double* E, int64_t lde, const ps_opts* opts, ps_report* report,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* Several polynomials of one matrix sharing one power table (section 4:
  * the Pade numerator and denominator; the cosine, which is a polynomial in

@@ -26,13 +26,14 @@ Paper passages followed:
   * Zero norms: when the denominator is zero every later product is exactly
     zero, so any precision is exact and u_i = +inf; when ||B_0|| = 0 but the
     denominator is not, u_i = 0 and the working precision is kept.
-Tier codes: 0 = FP64, 1 = FP32, 2 = BF16, 3 = FP8.
+Tier codes: 0 = FP64, 1 = FP32, 2 = BF16, 3 = FP8, 4 = double-double (the
+working precision of the paper's multi-precision setting, never a lower tier).
 """
 from __future__ import annotations
 
 import math
 
-U_TIER = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -8, 3: 2.0 ** -4}
+U_TIER = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -8, 3: 2.0 ** -4, 4: 2.0 ** -106}   # 4: double-double (working only)
 DELTA = 10.0
 
 

@@ -23,7 +23,7 @@ LIBPATH = os.environ.get("PS_LIBPATH") or os.path.join(HERE, "libps.so")
 
 PS_F64, PS_F32 = 0, 1
 TIER_F64, TIER_F32, TIER_BF16, TIER_FP8 = 0, 1, 2, 3
-TIER_NAMES = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp8"}
+TIER_NAMES = {0: "fp64", 1: "fp32", 2: "bf16", 3: "fp8", 4: "dd"}
 MODE_FIXED, MODE_MIXED = 0, 1
 MAX_BLOCKS = 64
 
@@ -78,6 +78,8 @@ _SIGS = {
     "ps_theta_taylor": ([_i, _i, _dp], _i),
     "ps_workspace_size_auto": ([_i, _i64, _i, _i, _szp], _i),
     "ps_expm_auto": ([_i, _i64, _vp, _i64, _i, _i, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
+    "ps_workspace_size_dd": ([_i64, _i, _i, _i, _szp], _i),
+    "ps_expm_dd": ([_i64, _vp, _i64, _dp, _i, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
     "ps_workspace_size_multi": ([_i, _i64, _i, _ip, _i, _i, _szp], _i),
     "ps_eval_multi": ([_i, _i64, _vp, _i64, _i, ctypes.POINTER(_dp), _ip, _i, _i, ctypes.POINTER(_vp), _i64p,
                        _op, _rp, _vp, _sz, _vp], _i),
@@ -292,6 +294,45 @@ def auto_workspace(A, m, s=0):
     nbytes = ctypes.c_size_t()
     _check(lib().ps_workspace_size_auto(_dtype_code(A), A.shape[0], int(m), int(s), ctypes.byref(nbytes)))
     return _workspace(nbytes.value, A.device)
+
+
+def ps_expm_dd(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
+               out=None, workspace=None):
+    """Double-double scaling and squaring around PS.  A: float64 tensor of
+    shape (2, n, n), A[0] the hi parts and A[1] the lo parts; coef: None
+    (Taylor 1/k! in double-double) or a pair (hi, lo) of length-(m+1)
+    sequences.  Returns the (2, n, n) result (and the report)."""
+    import torch
+    if A.dim() != 3 or A.shape[0] != 2 or A.shape[1] != A.shape[2] or A.dtype != torch.float64:
+        raise PSError(-1, "A must be a float64 tensor of shape (2, n, n)")
+    A = A.contiguous()
+    n = A.shape[1]
+    if workspace is None:
+        nbytes = ctypes.c_size_t()
+        _check(lib().ps_workspace_size_dd(n, int(m), int(s), int(sigma), ctypes.byref(nbytes)))
+        ws, wsp, wsb = _workspace(nbytes.value, A.device)
+    else:
+        ws, wsp, wsb = workspace
+    E = torch.empty_like(A) if out is None else out
+    if E.shape != A.shape or E.dtype != A.dtype or E.device != A.device or not E.is_contiguous():
+        raise PSError(-1, "out must be a contiguous float64 tensor of A's shape on A's device")
+    o, _k = _opts(mode, tier_mask, delta)
+    rep = ps_report() if report else None
+    c = None
+    if coef is not None:
+        hi, lo = coef
+        c = _darr(list(hi) + list(lo))
+    _check(lib().ps_expm_dd(n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n, ctypes.byref(o),
+                            ctypes.byref(rep) if rep is not None else None, wsp, wsb, _stream_ptr(A.device)))
+    return (E, rep.to_dict()) if rep is not None else E
+
+
+def dd_workspace(n, m, s=0, sigma=0, device="cuda:0"):
+    """Pre-allocate a workspace for repeated ps_expm_dd calls of this shape."""
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_dd(int(n), int(m), int(s), int(sigma), ctypes.byref(nbytes)))
+    import torch
+    return _workspace(nbytes.value, torch.device(device))
 
 
 def expm_workspace(A, m, s=0, sigma=0):

@@ -46,7 +46,6 @@ ps_status fail(ps_status st, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(PS_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kMaxSigma = 500;
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -522,11 +521,13 @@ ps_status ps_coef_pade_exp(int deg, double* p, double* q) {
 
 ps_status ps_plan(ps_dtype dtype, int r, const double* normB, double normY, const ps_opts* opts, int* tier,
                   double* u, int* nu) {
-  if (dtype != PS_F64 && dtype != PS_F32) return fail(PS_ERR_ARG, "dtype must be PS_F64 or PS_F32");
+  if (dtype != PS_F64 && dtype != PS_F32 && dtype != PS_DD)
+    return fail(PS_ERR_ARG, "dtype must be PS_F64, PS_F32 or PS_DD");
   if (r < 0 || r + 1 > PS_MAX_BLOCKS) return fail(PS_ERR_ARG, "r = %d out of range", r);
   if (!normB || !tier || !u || !nu) return fail(PS_ERR_ARG, "NULL output or norm array");
-  const int W = dtype == PS_F64 ? 0 : 1;
-  Opts o = read_opts(opts, W);
+  const int W = dtype == PS_F64 ? 0 : dtype == PS_F32 ? 1 : kTierDD;
+  Opts o = read_opts(opts, W == kTierDD ? 0 : W);
+  if (W == kTierDD) o.mask = (opts && opts->tier_mask ? opts->tier_mask : 0xFu) & 0xFu;   // every IEEE tier is lower
   if (o.mode == PS_MODE_FIXED) {
     for (int i = 0; i <= r; ++i) { tier[i] = W; u[i] = tier_unit_roundoff(W); }
     *nu = r + 1;

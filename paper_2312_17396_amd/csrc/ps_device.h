@@ -485,6 +485,43 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ Ap, int64_t lda,
 // adds B_{i-1} in the precision of t_out and writes the operand format that
 // the next step reads (or the working-precision result).  Ends with a barrier.
 // ---------------------------------------------------------------------------
+// Pack the tile Cs (column-major, CSTR) into the K-contiguous operand layout of
+// tier t_out: 2 = BF16 [Mp][Kp]; 3 = E4M3 [Mp][Kp] followed by the E8M0
+// scales [Mp][Kp/32] (one per 32 columns of a row).  The caller synchronizes.
+template <typename C>
+__device__ __forceinline__ void pack_tile_lowp(const C* Cs, int t_out, char* pout, int64_t Mp, int64_t Kp, int64_t m0,
+                                               int64_t n0) {
+  const int t = threadIdx.x;
+  if (t_out == 2) {
+    const int r = t / (kTileN / 8), seg = (t % (kTileN / 8)) * 8;   // NT = 64 rows x kTileN/8 segments
+    union { uint4 q; uint16_t h[8]; } o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o.h[e] = bf16_bits_rne((float)Cs[(seg + e) * CSTR + r]);
+    *(uint4*)((uint16_t*)pout + (m0 + r) * Kp + n0 + seg) = o.q;
+  } else if (t < kTileM * kTileN / 32) {
+    const int r = t % kTileM, blk = t / kTileM;   // one E8M0 block = 32 columns of a row
+    float vals[32];
+    float amax = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 32; ++e) {
+      vals[e] = (float)Cs[(32 * blk + e) * CSTR + r];
+      amax = fmaxf(amax, fabsf(vals[e]));
+    }
+    const int sbyte = e8m0_for(amax);
+    const int sexp = sbyte - 127;
+    union { uint4 q[2]; uint32_t wv[8]; } o;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      o.wv[e] = pack4_e4m3(ldexpf(vals[4 * e], -sexp), ldexpf(vals[4 * e + 1], -sexp),
+                           ldexpf(vals[4 * e + 2], -sexp), ldexpf(vals[4 * e + 3], -sexp));
+    uint8_t* p8 = (uint8_t*)pout;
+    uint4* dst = (uint4*)(p8 + (m0 + r) * Kp + n0 + 32 * blk);
+    dst[0] = o.q[0];
+    dst[1] = o.q[1];
+    p8[Mp * Kp + (m0 + r) * (Kp / 32) + n0 / 32 + blk] = (uint8_t)sbyte;
+  }
+}
+
 template <typename W>
 struct HornerTile {
   int64_t n, Mp, Kp;
@@ -560,34 +597,7 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
   __syncthreads();
   if (t_out < 2) return;
   // pass 2 (row-major): pack into the K-contiguous low-precision layout
-  if (t_out == 2) {
-    const int r = t / (kTileN / 8), seg = (t % (kTileN / 8)) * 8;   // NT = 64 rows x kTileN/8 segments
-    union { uint4 q; uint16_t h[8]; } o;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) o.h[e] = bf16_bits_rne((float)Cs[(seg + e) * CSTR + r]);
-    *(uint4*)((uint16_t*)h.pout + (m0 + r) * Kp + n0 + seg) = o.q;
-  } else if (t < kTileM * kTileN / 32) {
-    const int r = t % kTileM, blk = t / kTileM;   // one E8M0 block = 32 columns of a row
-    float vals[32];
-    float amax = 0.0f;
-#pragma unroll
-    for (int e = 0; e < 32; ++e) {
-      vals[e] = (float)Cs[(32 * blk + e) * CSTR + r];
-      amax = fmaxf(amax, fabsf(vals[e]));
-    }
-    const int sbyte = e8m0_for(amax);
-    const int sexp = sbyte - 127;
-    union { uint4 q[2]; uint32_t wv[8]; } o;
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      o.wv[e] = pack4_e4m3(ldexpf(vals[4 * e], -sexp), ldexpf(vals[4 * e + 1], -sexp),
-                           ldexpf(vals[4 * e + 2], -sexp), ldexpf(vals[4 * e + 3], -sexp));
-    uint8_t* p8 = (uint8_t*)h.pout;
-    uint4* dst = (uint4*)(p8 + (m0 + r) * Kp + n0 + 32 * blk);
-    dst[0] = o.q[0];
-    dst[1] = o.q[1];
-    p8[h.Mp * Kp + (m0 + r) * (Kp / 32) + n0 / 32 + blk] = (uint8_t)sbyte;
-  }
+  pack_tile_lowp<W>(Cs, t_out, h.pout, h.Mp, Kp, m0, n0);
   __syncthreads();
 }
 

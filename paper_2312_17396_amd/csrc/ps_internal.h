@@ -10,6 +10,7 @@
 
 namespace psk {
 
+constexpr int kMaxSigma = 500;  // largest number of squarings
 constexpr int kMaxDegree = 255;  // coefficients travel by value in kernel arguments
 #ifndef PS_TILE_N
 #define PS_TILE_N 64
@@ -42,8 +43,8 @@ struct Coefs {
 struct Layout {
   int64_t n;
   int m, s, r, sigma;
-  int working;         // 0 = FP64, 1 = FP32
-  int esize;           // bytes of the working type
+  int working;         // 0 = FP64, 1 = FP32, 4 = double-double
+  int esize;           // bytes of the working type (16: two FP64 planes)
   int trivial_last;    // s divides m: B_r = c_m I, step r folded into B_{r-1}
   int first_step;      // index of the first Horner product formed by a GEMM (0 = none)
   int square_arg;      // power table of A^2 instead of A
@@ -58,6 +59,7 @@ struct Layout {
   size_t off_yf32, off_ybf16, off_yfp8, off_yfp8s;
   size_t off_colsum;   // (nB + 1) * nchunks * n doubles: partial column abs sums of B_i and Y
   size_t off_plan;
+  size_t off_coef;     // double-double coefficients (hi[m+1], lo[m+1]); double-double path only
   size_t bytes;        // total per matrix
 };
 

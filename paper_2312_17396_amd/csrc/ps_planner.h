@@ -31,13 +31,17 @@
 
 namespace psk {
 
-// unit roundoff of tier t: FP64, FP32, BF16, FP8 (E4M3)
+// unit roundoff of tier t: FP64, FP32, BF16, FP8 (E4M3), and tier 4 =
+// double-double (working precision only, 2^-106)
+constexpr int kTierDD = 4;
 PS_HD inline double tier_unit_roundoff(int t) {
-  return t == 0 ? 0x1p-53 : t == 1 ? 0x1p-24 : t == 2 ? 0x1p-8 : 0x1p-4;
+  return t == 0 ? 0x1p-53 : t == 1 ? 0x1p-24 : t == 2 ? 0x1p-8 : t == 3 ? 0x1p-4 : 0x1p-106;
 }
+// the tiers below working tier w, highest precision first: w+1..3 (all of 0..3 below double-double)
+PS_HD inline int first_lower_tier(int w) { return w == kTierDD ? 0 : w + 1; }
 
-// normB[0..r], normY -> tier[0..r], u[0..r], *nu.  working_tier is 0 (FP64)
-// or 1 (FP32).  mask bit t allows tier t (the working tier always allowed).
+// normB[0..r], normY -> tier[0..r], u[0..r], *nu.  working_tier is 0 (FP64),
+// 1 (FP32) or kTierDD.  mask bit t allows tier t (the working tier always allowed).
 PS_HD inline void plan_tiers(int r, const double* normB, double normY, int working_tier,
                              unsigned mask, double delta, int* tier, double* u, int* nu_out) {
   const double uw = tier_unit_roundoff(working_tier);
@@ -58,7 +62,7 @@ PS_HD inline void plan_tiers(int r, const double* normB, double normY, int worki
   for (int i = 1; i <= r; ++i) {
     int best = working_tier;
     if (i >= nu) {
-      for (int t = working_tier + 1; t <= 3; ++t) {
+      for (int t = first_lower_tier(working_tier); t <= 3; ++t) {
         if (((mask >> t) & 1u) && tier_unit_roundoff(t) <= u[i]) best = t;
       }
     } else {

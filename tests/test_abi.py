@@ -58,11 +58,11 @@ def test_host_planner_matches_oracle_planner(ps):
         if trial % 17 == 0:
             nb[0] = 0.0
         ny = float(np.exp(rng.uniform(-30, 2))) if trial % 13 else 0.0
-        for wt in (0, 1):
+        for wt in (0, 1, 2):   # dtype codes: FP64, FP32, double-double (working tier 4)
             mask = int(rng.integers(0, 16))
             allowed = [t for t in range(4) if (mask >> t) & 1] if mask else [0, 1, 2, 3]
             t_lib, u_lib, nu_lib = ps.ps_plan(nb, ny, dtype=wt, mode="mixed", tier_mask=mask)
-            u_o, nu_o, t_o = oplan.plan(nb, ny, working_tier=wt, allowed=allowed)
+            u_o, nu_o, t_o = oplan.plan(nb, ny, working_tier=4 if wt == 2 else wt, allowed=allowed)
             assert t_lib == t_o and nu_lib == nu_o, (nb, ny, wt, mask)
             assert np.allclose(u_lib, u_o, rtol=1e-15, atol=0) or all(
                 (a == b) for a, b in zip(u_lib, u_o))
