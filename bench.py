@@ -39,6 +39,9 @@ S = 6
 PEAK_FP64_MFMA = 78.6   # TFLOP/s, MI355X dense FP64 matrix
 
 
+EXTRAS = ("batched", "pade_cos", "grad", "auto", "dd")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +52,8 @@ def parse():
                     help="restrict the timed modes (profiling runs)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary workloads (batched, Pade/cos, adjoint)")
+    ap.add_argument("--extra", default=",".join(EXTRAS),
+                    help="comma-separated subset of the secondary workloads: " + ",".join(EXTRAS))
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run three 256 MiB device-to-device copies (known traffic, for counter scaling)")
     return ap.parse_args()
@@ -80,7 +85,7 @@ def load_traffic():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU path is not built); "
+        print("bench.py: runs on one GPU only (no multi-GPU path is implemented); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -185,7 +190,10 @@ def main():
         out["speedup_mixed_vs_plain"] = round(res["plain"] / res["mixed"], 4)
 
     if not args.no_extra:
-        out["extra"] = extra_workloads(ps, inputs, torch)
+        which = set(x for x in args.extra.split(",") if x)
+        if not which <= set(EXTRAS):
+            sys.exit("unknown --extra entries: %s" % ",".join(sorted(which - set(EXTRAS))))
+        out["extra"] = extra_workloads(ps, inputs, torch, which)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mats, outs_mixed=[ps.ps_expm(a, M, s=S, sigma=sg, mode="mixed")
@@ -204,7 +212,7 @@ def _time(fn, reps, torch):
     return (time.perf_counter() - t0) / reps
 
 
-def extra_workloads(ps, inputs, torch):
+def extra_workloads(ps, inputs, torch, which=EXTRAS):
     """Secondary workloads of the hot path (each a few seconds):
     batched   4096 matrices, n uniform in {8..256}, ||A||_1 ~ U[0.05, 4], Taylor
               m = 18, s chosen per matrix, FP32: one persistent launch replayed
@@ -221,80 +229,85 @@ def extra_workloads(ps, inputs, torch):
     res = {}
     dev = torch.device("cuda:0")
     # ---- batched
-    mats, ts = inputs.batch_uneven()
-    sig = [inputs.squarings_for(t) for t in ts]
-    A = [torch.tensor(a, dtype=torch.float32, device=dev) for a in mats]
-    flops = sum(2.0 * a.shape[0] ** 3 * (3 + 4 + sg) for a, sg in zip(mats, sig))   # s=4/5: 7 GEMMs + squarings
-    out = {"matrices": len(A), "m": 18, "dtype": "f32"}
-    for mode in ("fixed", "mixed"):
-        g = ps.BatchedGraph(A, 18, sigma=sig, mode=mode)
-        t = _time(g.launch, 5, torch)
-        g.close()
-        out[mode] = {"ms": round(t * 1e3, 3), "evals_per_s": round(len(A) / t, 1),
-                     "tflops_credited": round(flops / t / 1e12, 2)}
-    sub = list(range(0, len(A), 8))          # per-matrix loop on every 8th matrix, scaled
-    wsl = [ps.expm_workspace(A[i], 18, 0, sig[i]) for i in sub]
-    outs = [torch.empty_like(A[i]) for i in sub]
+    if "batched" in which:
+        mats, ts = inputs.batch_uneven()
+        sig = [inputs.squarings_for(t) for t in ts]
+        A = [torch.tensor(a, dtype=torch.float32, device=dev) for a in mats]
+        flops = sum(2.0 * a.shape[0] ** 3 * (3 + 4 + sg) for a, sg in zip(mats, sig))   # s=4/5: 7 GEMMs + squarings
+        out = {"matrices": len(A), "m": 18, "dtype": "f32"}
+        for mode in ("fixed", "mixed"):
+            g = ps.BatchedGraph(A, 18, sigma=sig, mode=mode)
+            t = _time(g.launch, 5, torch)
+            g.close()
+            out[mode] = {"ms": round(t * 1e3, 3), "evals_per_s": round(len(A) / t, 1),
+                         "tflops_credited": round(flops / t / 1e12, 2)}
+        sub = list(range(0, len(A), 8))          # per-matrix loop on every 8th matrix, scaled
+        wsl = [ps.expm_workspace(A[i], 18, 0, sig[i]) for i in sub]
+        outs = [torch.empty_like(A[i]) for i in sub]
 
-    def loop():
-        for k, i in enumerate(sub):
-            ps.ps_expm(A[i], 18, s=0, sigma=sig[i], mode="mixed", out=outs[k], workspace=wsl[k])
-    t = _time(loop, 1, torch) * len(A) / len(sub)
-    out["per_matrix_loop_mixed"] = {"ms": round(t * 1e3, 2), "evals_per_s": round(len(A) / t, 1),
-                                    "note": "loop of ps_expm calls timed on every 8th matrix, scaled"}
-    out["speedup_persistent_vs_loop"] = round(t / (out["mixed"]["ms"] * 1e-3), 2)
-    res["batched_uneven_4096"] = out
-    del A, outs, wsl
+        def loop():
+            for k, i in enumerate(sub):
+                ps.ps_expm(A[i], 18, s=0, sigma=sig[i], mode="mixed", out=outs[k], workspace=wsl[k])
+        t = _time(loop, 1, torch) * len(A) / len(sub)
+        out["per_matrix_loop_mixed"] = {"ms": round(t * 1e3, 2), "evals_per_s": round(len(A) / t, 1),
+                                        "note": "loop of ps_expm calls timed on every 8th matrix, scaled"}
+        out["speedup_persistent_vs_loop"] = round(t / (out["mixed"]["ms"] * 1e-3), 2)
+        res["batched_uneven_4096"] = out
+        del A, outs, wsl
     # ---- Pade pair and cos at n = 2048
-    Aq = torch.tensor(inputs.orthosim_2048(), dtype=torch.float64, device=dev)
-    p, q = ps.coef_pade_exp(13)
-    c = ps.coef_taylor_cos(12)
-    out = {"n": 2048, "dtype": "f64"}
-    for mode in ("fixed", "mixed"):
-        tp = _time(lambda: ps.ps_eval_multi(Aq, [p, q], s=4, mode=mode), 5, torch)
-        tc = _time(lambda: ps.ps_eval_multi(Aq, [c], s=4, square_arg=True, mode=mode), 5, torch)
-        out[mode] = {"pade_pair_ms": round(tp * 1e3, 3), "pade_tflops_credited": round(9 * 2 * 2048 ** 3 / tp / 1e12, 2),
-                     "cos_ms": round(tc * 1e3, 3), "cos_tflops_credited": round(6 * 2 * 2048 ** 3 / tc / 1e12, 2)}
-    res["pade_cos_2048"] = out
-    del Aq
+    if "pade_cos" in which:
+        Aq = torch.tensor(inputs.orthosim_2048(), dtype=torch.float64, device=dev)
+        p, q = ps.coef_pade_exp(13)
+        c = ps.coef_taylor_cos(12)
+        out = {"n": 2048, "dtype": "f64"}
+        for mode in ("fixed", "mixed"):
+            tp = _time(lambda: ps.ps_eval_multi(Aq, [p, q], s=4, mode=mode), 5, torch)
+            tc = _time(lambda: ps.ps_eval_multi(Aq, [c], s=4, square_arg=True, mode=mode), 5, torch)
+            out[mode] = {"pade_pair_ms": round(tp * 1e3, 3), "pade_tflops_credited": round(9 * 2 * 2048 ** 3 / tp / 1e12, 2),
+                         "cos_ms": round(tc * 1e3, 3), "cos_tflops_credited": round(6 * 2 * 2048 ** 3 / tc / 1e12, 2)}
+        res["pade_cos_2048"] = out
+        del Aq
     # ---- adjoint batch
-    An, Gn = inputs.grad_batch_512()
-    At = torch.tensor(An, device=dev)
-    Gt = torch.tensor(Gn, device=dev)
-    sigma = inputs.squarings_for(max(float(x) for x in torch.linalg.matrix_norm(At.double(), ord=1).cpu()))
-    tf = _time(lambda: ps.ps_expm_strided_batched(At, 18, s=5, sigma=sigma, mode="mixed"), 3, torch)
-    tb = _time(lambda: ps.ps_expm_backward(At, Gt, 18, s=5, sigma=sigma), 3, torch)
-    gem_f = 4 + 3 + sigma
-    res["grad_batch_512"] = {"batch": 64, "n": 512, "sigma": sigma, "dtype": "f32",
-                             "forward_ms": round(tf * 1e3, 3), "backward_ms": round(tb * 1e3, 3),
-                             "backward_tflops_credited": round(64 * (gem_f + 2 * gem_f) * 2 * 512 ** 3 / tb / 1e12, 2)}
-    del At, Gt
+    if "grad" in which:
+        An, Gn = inputs.grad_batch_512()
+        At = torch.tensor(An, device=dev)
+        Gt = torch.tensor(Gn, device=dev)
+        sigma = inputs.squarings_for(max(float(x) for x in torch.linalg.matrix_norm(At.double(), ord=1).cpu()))
+        tf = _time(lambda: ps.ps_expm_strided_batched(At, 18, s=5, sigma=sigma, mode="mixed"), 3, torch)
+        tb = _time(lambda: ps.ps_expm_backward(At, Gt, 18, s=5, sigma=sigma), 3, torch)
+        gem_f = 4 + 3 + sigma
+        res["grad_batch_512"] = {"batch": 64, "n": 512, "sigma": sigma, "dtype": "f32",
+                                 "forward_ms": round(tf * 1e3, 3), "backward_ms": round(tb * 1e3, 3),
+                                 "backward_tflops_credited": round(64 * (gem_f + 2 * gem_f) * 2 * 512 ** 3 / tb / 1e12, 2)}
+        del At, Gt
     # ---- automatic scaling (alpha_m bound) on the dense n = 1024 set
-    mats = [torch.tensor(inputs.dense_1024(t), device=dev) for t in inputs.DENSE_NORMS]
-    wsa = [ps.auto_workspace(a, M, S) for a in mats]
-    outs = [torch.empty_like(a) for a in mats]
-    sig = [ps.ps_expm_auto(a, M, s=S, mode="mixed", out=o, workspace=w)[1] for a, o, w in zip(mats, outs, wsa)]
+    if "auto" in which:
+        mats = [torch.tensor(inputs.dense_1024(t), device=dev) for t in inputs.DENSE_NORMS]
+        wsa = [ps.auto_workspace(a, M, S) for a in mats]
+        outs = [torch.empty_like(a) for a in mats]
+        sig = [ps.ps_expm_auto(a, M, s=S, mode="mixed", out=o, workspace=w)[1] for a, o, w in zip(mats, outs, wsa)]
 
-    def auto_step():
-        for a, o, w in zip(mats, outs, wsa):
-            ps.ps_expm_auto(a, M, s=S, mode="mixed", out=o, workspace=w)
-    ta = _time(auto_step, 5, torch)
-    res["expm_auto_dense_1024"] = {"sigma_chosen": sig, "sigma_fixed_rule": [inputs.squarings_for(t) for t in inputs.DENSE_NORMS],
-                                   "ms_per_step": round(ta * 1e3, 3), "evals_per_s": round(len(mats) / ta, 1),
-                                   "note": "mixed tiers; includes the two norm read-backs of each call"}
-    del mats, outs, wsa
+        def auto_step():
+            for a, o, w in zip(mats, outs, wsa):
+                ps.ps_expm_auto(a, M, s=S, mode="mixed", out=o, workspace=w)
+        ta = _time(auto_step, 5, torch)
+        res["expm_auto_dense_1024"] = {"sigma_chosen": sig, "sigma_fixed_rule": [inputs.squarings_for(t) for t in inputs.DENSE_NORMS],
+                                       "ms_per_step": round(ta * 1e3, 3), "evals_per_s": round(len(mats) / ta, 1),
+                                       "note": "mixed tiers; includes the two norm read-backs of each call"}
+        del mats, outs, wsa
     # ---- double-double working precision
-    Ad = inputs.dense_1024(1.0)
-    Td = torch.tensor(np.stack([Ad, np.zeros_like(Ad)]), dtype=torch.float64, device=dev)
-    wsd = ps.dd_workspace(1024, 30, 6, 0)
-    Ed = torch.empty_like(Td)
-    out = {"n": 1024, "m": 30, "s": 6, "sigma": 0, "dtype": "dd"}
-    for mode in ("fixed", "mixed"):
-        _, rep = ps.ps_expm_dd(Td, 30, s=6, mode=mode, out=Ed, workspace=wsd, report=True)
-        t = _time(lambda: ps.ps_expm_dd(Td, 30, s=6, mode=mode, out=Ed, workspace=wsd), 3, torch)
-        out[mode] = {"ms": round(t * 1e3, 3), "tiers": [ps.TIER_NAMES[x] for x in rep["tier"][:rep["first_step"] + 1]]}
-    out["speedup_mixed_vs_fixed"] = round(out["fixed"]["ms"] / out["mixed"]["ms"], 3)
-    res["expm_dd_1024"] = out
+    if "dd" in which:
+        Ad = inputs.dense_1024(1.0)
+        Td = torch.tensor(np.stack([Ad, np.zeros_like(Ad)]), dtype=torch.float64, device=dev)
+        wsd = ps.dd_workspace(1024, 30, 6, 0)
+        Ed = torch.empty_like(Td)
+        out = {"n": 1024, "m": 30, "s": 6, "sigma": 0, "dtype": "dd"}
+        for mode in ("fixed", "mixed"):
+            _, rep = ps.ps_expm_dd(Td, 30, s=6, mode=mode, out=Ed, workspace=wsd, report=True)
+            t = _time(lambda: ps.ps_expm_dd(Td, 30, s=6, mode=mode, out=Ed, workspace=wsd), 3, torch)
+            out[mode] = {"ms": round(t * 1e3, 3), "tiers": [ps.TIER_NAMES[x] for x in rep["tier"][:rep["first_step"] + 1]]}
+        out["speedup_mixed_vs_fixed"] = round(out["fixed"]["ms"] / out["mixed"]["ms"], 3)
+        res["expm_dd_1024"] = out
     return res
 
 

@@ -49,7 +49,7 @@ typedef enum {
   PS_ERR_ARG = -1,         /* invalid size, degree, block size, pointer, ld */
   PS_ERR_ALIAS = -2,       /* output overlaps an input */
   PS_ERR_WORKSPACE = -3,   /* workspace missing, too small or misaligned */
-  PS_ERR_UNSUPPORTED = -5, /* valid request this build does not implement */
+  PS_ERR_UNSUPPORTED = -5, /* valid request the library does not implement */
   PS_ERR_HIP = -6          /* a HIP runtime call failed; see ps_last_error() */
 } ps_status;
 
