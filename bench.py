@@ -39,7 +39,7 @@ S = 6
 PEAK_FP64_MFMA = 78.6   # TFLOP/s, MI355X dense FP64 matrix
 
 
-EXTRAS = ("batched", "pade_cos", "grad", "auto", "dd")
+EXTRAS = ("batched", "pade_cos", "grad", "auto", "vars", "dd")
 
 
 def parse():
@@ -222,6 +222,8 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
     grad      64 FP32 matrices of order 512: forward + hand-written adjoint;
     auto      the dense n = 1024 set with the scaling chosen by the alpha_m bound
               (ps_expm_auto) instead of ceil(log2 ||A||_1);
+    vars      n = 1024, A = -0.5 I + E with ||E||_1 = 0.05, Taylor m = 30, sigma = 0:
+              Algorithm 2's variable-s branch (ps_expm_vars) against s = 6;
     dd        n = 1024, ||A||_1 = 1, Taylor m = 30 (theta_30 = 1.16 at u = 2^-106,
               so no scaling), s = 6, double-double working precision: every
               product in double-double vs the planned tiers below it."""
@@ -295,6 +297,24 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
                                        "ms_per_step": round(ta * 1e3, 3), "evals_per_s": round(len(mats) / ta, 1),
                                        "note": "mixed tiers; includes the two norm read-backs of each call"}
         del mats, outs, wsa
+    # ---- variable block size (Algorithm 2, fix_params = false)
+    if "vars" in which:
+        Av = torch.tensor(inputs.shifted_1024(), device=dev)
+        Ev = torch.empty_like(Av)
+        wsv = ps.vars_workspace(Av, M, 0)
+        wsf = ps.expm_workspace(Av, M, S, 0)
+        _, s_var, rep_v = ps.ps_expm_vars(Av, M, mode="mixed", out=Ev, workspace=wsv, report=True)
+        _, rep_f = ps.ps_expm(Av, M, s=S, mode="mixed", out=Ev, workspace=wsf, report=True)
+        tv = _time(lambda: ps.ps_expm_vars(Av, M, mode="mixed", out=Ev, workspace=wsv), 5, torch)
+        tf = _time(lambda: ps.ps_expm(Av, M, s=S, mode="mixed", out=Ev, workspace=wsf), 5, torch)
+        res["expm_vars_shifted_1024"] = {
+            "n": 1024, "m": M, "sigma": 0,
+            "variable_s": {"s": s_var, "ms": round(tv * 1e3, 3),
+                           "tiers": [ps.TIER_NAMES[x] for x in rep_v["tier"][:rep_v["first_step"] + 1]]},
+            "fixed_s": {"s": S, "ms": round(tf * 1e3, 3),
+                        "tiers": [ps.TIER_NAMES[x] for x in rep_f["tier"][:rep_f["first_step"] + 1]]},
+            "note": "mixed tiers; the variable-s call includes one norm read-back per growth step"}
+        del Av, Ev, wsv, wsf
     # ---- double-double working precision
     if "dd" in which:
         Ad = inputs.dense_1024(1.0)

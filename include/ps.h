@@ -183,6 +183,30 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
                        ps_report* report, int* sigma_out, void* ws, size_t ws_bytes,
                        void* stream);
 
+/* Workspace bytes for ps_expm_vars: the power table X^2 .. X^m (s may grow to
+ * m), the largest block / iterate / plan section over s0 <= s <= m, one
+ * matrix for the running B_0 and the norm scratch. */
+ps_status ps_workspace_size_vars(ps_dtype dtype, int64_t n, int m, int sigma, size_t* bytes);
+
+/* E = p(2^-sigma A)^(2^sigma) with the block size chosen by Algorithm 2's
+ * variable-s branch (fix_params = false, section 3.3): with X = 2^-sigma A and
+ * s0 = ceil(sqrt(m)), if ||X||_1 <= s0 / e the call forms X^2 .. X^s0,
+ * B_0 = sum_{j<s0} c_j X^j and Y = X^s0, then while ||Y||_1 > ||B_0||_1
+ * ||X||_1^s and s < m it adds c_s Y to B_0, raises s by one and forms
+ * Y = X Y, all in the working precision; otherwise s = s0.  The blocks, the
+ * plan (the same rule as ps_expm), the Horner steps and the squarings then
+ * run with the chosen s, reusing the powers.  coef = NULL selects the Taylor
+ * coefficients 1/k! (m <= 170).  The chosen s goes to *s_out (may be NULL).
+ * Norms are 1-norms of the column-major matrix.  The call synchronizes the
+ * stream once per norm read (1 + number of growth steps + 1 when the branch
+ * runs), so it cannot be captured into a graph.  Errors as ps_expm;
+ * PS_ERR_ARG also for non-finite input, PS_ERR_UNSUPPORTED for
+ * opts->tier_override. */
+ps_status ps_expm_vars(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
+                       const double* coef, int m, int sigma,
+                       void* E, int64_t lde, const ps_opts* opts, ps_report* report,
+                       int* s_out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Double-double working precision (u = 2^-106) with the FP64, FP32, BF16 and
  * MX-FP8 tiers below it: the multi-precision setting the paper is written

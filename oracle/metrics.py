@@ -24,6 +24,11 @@ TEST INFRASTRUCTURE ONLY (part of the oracle).
       X0 = 2^-sigma0 A from its powers (repeated multiplication in IEEE
       double), sigma the smallest with 2^-sigma alpha_m(A) <= theta_m; with
       norm_guard also ||2^-sigma A||_1 <= s / e (section 3.2).
+  variable_s(X, coef)  the block size of Algorithm 2's variable-s branch
+      (fix_params = false, section 3.3): s = ceil(sqrt(m)); only when
+      ||X||_1 <= s / e, B_0 = sum_{j<s} c_j X^j and Y = X^s, then while
+      ||Y||_1 > ||B_0||_1 ||X||_1^s and s < m: B_0 += c_s Y, s += 1,
+      Y = X Y (IEEE double, powers by repeated multiplication).
 """
 from __future__ import annotations
 
@@ -135,3 +140,26 @@ def auto_sigma(A, m: int, s: int, u: float, norm_guard: bool = False) -> int:
     if norm_guard:
         sig = max(sig, _smallest_shift(math.e * nA, float(s)))
     return sig
+
+
+def variable_s(X, coef) -> int:
+    X = np.asarray(X, dtype=np.float64)
+    c = [float(v) for v in coef]
+    m = len(c) - 1
+    s = 1
+    while s * s < m:
+        s += 1
+    nX = norm1(X)
+    if not (nX <= s / math.e) or s >= m:
+        return s
+    n = X.shape[0]
+    powers = [np.eye(n), X]
+    for _ in range(2, s + 1):
+        powers.append(powers[-1] @ X)
+    B0 = sum(c[j] * powers[j] for j in range(s))
+    Y = powers[s]
+    while norm1(Y) > norm1(B0) * nX ** s and s < m:
+        B0 = B0 + c[s] * Y
+        s += 1
+        Y = X @ Y
+    return s

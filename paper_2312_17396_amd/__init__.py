@@ -78,6 +78,8 @@ _SIGS = {
     "ps_theta_taylor": ([_i, _i, _dp], _i),
     "ps_workspace_size_auto": ([_i, _i64, _i, _i, _szp], _i),
     "ps_expm_auto": ([_i, _i64, _vp, _i64, _i, _i, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
+    "ps_workspace_size_vars": ([_i, _i64, _i, _i, _szp], _i),
+    "ps_expm_vars": ([_i, _i64, _vp, _i64, _dp, _i, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
     "ps_workspace_size_dd": ([_i64, _i, _i, _i, _szp], _i),
     "ps_expm_dd": ([_i64, _vp, _i64, _dp, _i, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
     "ps_workspace_size_multi": ([_i, _i64, _i, _ip, _i, _i, _szp], _i),
@@ -248,7 +250,7 @@ def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
         ws, wsp, wsb = _workspace(nbytes.value, A.device)
     else:
         ws, wsp, wsb = workspace
-    E = torch.empty_like(A) if out is None else out
+    E = torch.empty_like(A) if out is None else _check_out(out, A)
     o, _k = _opts(mode, tier_mask, delta, tier_override, profile)
     rep = ps_report() if (report or profile) else None
     c = _darr(coef) if coef is not None else None
@@ -279,7 +281,7 @@ def ps_expm_auto(A, m, s=0, norm_guard=False, mode="fixed", tier_mask=0, delta=1
         ws, wsp, wsb = _workspace(nbytes.value, A.device)
     else:
         ws, wsp, wsb = workspace
-    E = torch.empty_like(A) if out is None else out
+    E = torch.empty_like(A) if out is None else _check_out(out, A)
     o, _k = _opts(mode, tier_mask, delta, None, profile)
     rep = ps_report() if (report or profile) else None
     sig = ctypes.c_int()
@@ -287,6 +289,43 @@ def ps_expm_auto(A, m, s=0, norm_guard=False, mode="fixed", tier_mask=0, delta=1
                               ctypes.byref(o), ctypes.byref(rep) if rep is not None else None, ctypes.byref(sig),
                               wsp, wsb, _stream_ptr(A.device)))
     return (E, sig.value, rep.to_dict()) if rep is not None else (E, sig.value)
+
+
+def ps_expm_vars(A, m, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
+                 profile=False, out=None, workspace=None):
+    """E = p(2^-sigma A)^(2^sigma) with the block size s chosen by Algorithm 2's
+    variable-s branch; returns (E, s) or (E, s, report).  Norms are those of
+    the column-major view (the transpose of a row-major tensor)."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if workspace is None:
+        ws, wsp, wsb = vars_workspace(A, m, sigma)
+    else:
+        ws, wsp, wsb = workspace
+    E = torch.empty_like(A) if out is None else _check_out(out, A)
+    o, _k = _opts(mode, tier_mask, delta, None, profile)
+    rep = ps_report() if (report or profile) else None
+    c = _darr(coef) if coef is not None else None
+    s_out = ctypes.c_int()
+    _check(lib().ps_expm_vars(dt, n, A.data_ptr(), n, c, int(m), int(sigma), E.data_ptr(), n, ctypes.byref(o),
+                              ctypes.byref(rep) if rep is not None else None, ctypes.byref(s_out), wsp, wsb,
+                              _stream_ptr(A.device)))
+    return (E, s_out.value, rep.to_dict()) if rep is not None else (E, s_out.value)
+
+
+def vars_workspace(A, m, sigma=0):
+    """Pre-allocate a workspace for repeated ps_expm_vars calls of this shape."""
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_vars(_dtype_code(A), A.shape[0], int(m), int(sigma), ctypes.byref(nbytes)))
+    return _workspace(nbytes.value, A.device)
+
+
+def _check_out(E, A):
+    if E.shape != A.shape or E.dtype != A.dtype or E.device != A.device or not E.is_contiguous():
+        raise PSError(-1, "out must be a contiguous tensor of A's shape, dtype and device")
+    return E
 
 
 def auto_workspace(A, m, s=0):
@@ -313,9 +352,7 @@ def ps_expm_dd(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=1
         ws, wsp, wsb = _workspace(nbytes.value, A.device)
     else:
         ws, wsp, wsb = workspace
-    E = torch.empty_like(A) if out is None else out
-    if E.shape != A.shape or E.dtype != A.dtype or E.device != A.device or not E.is_contiguous():
-        raise PSError(-1, "out must be a contiguous float64 tensor of A's shape on A's device")
+    E = torch.empty_like(A) if out is None else _check_out(out, A)
     o, _k = _opts(mode, tier_mask, delta)
     rep = ps_report() if report else None
     c = None

@@ -452,6 +452,39 @@ int ceil_log2_ratio(double a, double b) {   // smallest k >= 0 with a <= 2^k b
 
 }  // namespace
 
+// Variable block size (Algorithm 2 with fix_params = false): the power slots
+// X^2..X^m come first in every layout with npow = m - 1, so the powers built
+// while s grows stay where the layout of the final s expects them.  After the
+// largest of those layouts: the running B_0 and the norm scratch.
+struct VarsLayout {
+  size_t off_b0, off_wg, bytes;
+};
+static VarsLayout vars_layout(ps_dtype dtype, int64_t n, int m, int s0, int sigma) {
+  const int np = std::max(m - 1, 0);
+  size_t mx = 0;
+  for (int s = s0; s <= std::max(m, s0); ++s) mx = std::max(mx, make_layout(dtype, n, m, s, sigma, 0, np).bytes);
+  VarsLayout V;
+  V.off_b0 = mx;
+  V.off_wg = V.off_b0 + make_layout(dtype, n, m, s0, sigma, 0, np).slot;
+  V.bytes = al256(V.off_wg + 2 * (size_t)norm1_groups(n) * sizeof(double));
+  return V;
+}
+
+// host maxima of the two workgroup arrays written by launch_comb_norm
+static ps_status read_norm_pair(const double* dev, int64_t n, hipStream_t st, double* nb, double* ny) {
+  const size_t g = (size_t)norm1_groups(n);
+  std::vector<double> h(2 * g);
+  PS_HIP(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  PS_HIP(hipStreamSynchronize(st));
+  double v[2] = {0.0, 0.0};
+  for (int q = 0; q < 2; ++q)
+    for (size_t k = 0; k < g; ++k)
+      if (h[q * g + k] > v[q] || h[q * g + k] != h[q * g + k]) v[q] = h[q * g + k];
+  *nb = v[0];
+  *ny = v[1];
+  return PS_OK;
+}
+
 static Layout auto_layout(ps_dtype dtype, int64_t n, int m, int s) {
   const int D = std::max(s, alpha_dstar(m) + 1);
   return make_layout(dtype, n, m, s, 1, 0, D - 1);
@@ -708,6 +741,134 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
   float ms[4] = {0, 0, 0, 0};
   if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
   if (sigma_out) *sigma_out = sigma;
+  if (report)
+    if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
+  return PS_OK;
+}
+
+ps_status ps_workspace_size_vars(ps_dtype dtype, int64_t n, int m, int sigma, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  int s0 = 0;
+  if (ps_status e = check_common(dtype, n, m, &s0, sigma)) return e;
+  *bytes = vars_layout(dtype, n, m, s0, sigma).bytes;
+  return PS_OK;
+}
+
+ps_status ps_expm_vars(ps_dtype dtype, int64_t n, const void* A, int64_t lda, const double* coef, int m, int sigma,
+                       void* E, int64_t lde, const ps_opts* opts, ps_report* report, int* s_out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  int s0 = 0;
+  if (ps_status e = check_common(dtype, n, m, &s0, sigma)) return e;
+  if (!A || !E) return fail(PS_ERR_ARG, "NULL matrix pointer");
+  if (lda < n || lde < n) return fail(PS_ERR_ARG, "leading dimension smaller than n");
+  const int esize = dtype == PS_F64 ? 8 : 4;
+  const size_t spanA = mat_span_bytes(n, lda, esize), spanE = mat_span_bytes(n, lde, esize);
+  if (overlap(A, spanA, E, spanE)) return fail(PS_ERR_ALIAS, "output overlaps the input matrix");
+  Opts o = read_opts(opts, dtype == PS_F64 ? 0 : 1);
+  if (ps_status e = check_opts(o)) return e;
+  if (o.override_tiers) return fail(PS_ERR_UNSUPPORTED, "tier_override is not supported by ps_expm_vars");
+  const VarsLayout V = vars_layout(dtype, n, m, s0, sigma);
+  if (ps_status e = check_ws(ws, ws_bytes, V.bytes)) return e;
+  if (overlap(ws, V.bytes, E, spanE) || overlap(ws, V.bytes, A, spanA))
+    return fail(PS_ERR_ALIAS, "workspace overlaps a matrix argument");
+  std::vector<double> c(m + 1);
+  if (coef) {
+    for (int k = 0; k <= m; ++k) c[k] = coef[k];
+  } else {
+    if (m > 170) return fail(PS_ERR_ARG, "built-in Taylor coefficients need m <= 170");
+    ps_coef_taylor_exp(m, c.data());
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int W = dtype == PS_F64 ? 0 : 1;
+  const int np = std::max(m - 1, 0);
+  const double beta = ldexp(1.0, -sigma);
+  char* wsc = (char*)ws;
+  double* wg = (double*)(wsc + V.off_wg);
+  const MatArg X1{A, lda, 0};
+  Layout L = make_layout(dtype, n, m, s0, sigma, 0, np);
+  auto power = [&](int j) { return j == 1 ? X1 : ws_mat(wsc, L.off_pow + (size_t)(j - 2) * L.slot, n, 0, esize); };
+  // 1. ||X||_1 for X = 2^-sigma A (exact power-of-two scaling of the column sums)
+  double nA = 0.0;
+  PS_HIP(launch_norm1(W, n, X1, wg, st));
+  if (ps_status e = read_norm1(wg, n, st, &nA)) return e;
+  if (!std::isfinite(nA)) return fail(PS_ERR_ARG, "input matrix has non-finite entries");
+  const double nX = ldexp(nA, -sigma);
+  int s = s0;
+  bool built = false;
+  // 2. the variable-s branch runs only for ||X||_1 <= s/e (section 3.3); it
+  //    grows s while ||Y|| > ||B_0|| ||X||^s, adding c_s Y to B_0 each time
+  if (nX <= s0 / M_E && s0 < m) {
+    for (int top = 2; top / 2 < s0; top *= 2) {
+      const int lo = top / 2 + 1, hi = std::min(top, s0);
+      GemmGroup g;
+      memset(&g, 0, sizeof g);
+      for (int j = lo; j <= hi; ++j) {
+        const int a = pow_a(j), b = pow_b(j), k = g.count++;
+        g.A[k] = power(a);
+        g.B[k] = power(b);
+        g.C[k] = power(j);
+        g.alpha[k] = (a == 1 ? beta : 1.0) * (b == 1 ? beta : 1.0);
+      }
+      PS_HIP(launch_gemm_group(W, n, 1, g, st));
+    }
+    built = true;
+    const MatArg B0 = ws_mat(wsc, V.off_b0, n, 0, esize);
+    CombArgs ca;
+    memset(&ca, 0, sizeof ca);
+    for (int j = 1; j < s0; ++j) {
+      ca.M[ca.count] = power(j);
+      ca.c[ca.count++] = j == 1 ? c[1] * beta : c[j];
+    }
+    ca.c_id = c[0];
+    ca.accumulate = 0;
+    ca.B = B0;
+    ca.Y = power(s0);
+    ca.wgB = wg;
+    ca.wgY = wg + norm1_groups(n);
+    PS_HIP(launch_comb_norm(W, n, ca, st));
+    double nB0 = 0.0, nY = 0.0;
+    if (ps_status e = read_norm_pair(wg, n, st, &nB0, &nY)) return e;
+    while (nY > nB0 * std::pow(nX, s) && s < m) {
+      GemmGroup g;   // X_{s+1} = X X_s
+      memset(&g, 0, sizeof g);
+      g.A[0] = X1;
+      g.B[0] = power(s);
+      g.C[0] = power(s + 1);
+      g.alpha[0] = beta;
+      g.count = 1;
+      PS_HIP(launch_gemm_group(W, n, 1, g, st));
+      memset(&ca, 0, sizeof ca);
+      ca.M[0] = power(s);   // B_0 += c_s X^s
+      ca.c[0] = c[s];
+      ca.count = 1;
+      ca.accumulate = 1;
+      ca.B = B0;
+      ca.Y = power(s + 1);
+      ca.wgB = wg;
+      ca.wgY = wg + norm1_groups(n);
+      PS_HIP(launch_comb_norm(W, n, ca, st));
+      if (ps_status e = read_norm_pair(wg, n, st, &nB0, &nY)) return e;
+      ++s;
+    }
+  }
+  // 3. blocks, plan, Horner and squarings with the chosen s
+  L = make_layout(dtype, n, m, s, sigma, 0, np);
+  Job J;
+  J.L = &L;
+  J.batch = 1;
+  J.X1 = X1;
+  J.beta = beta;
+  J.coef = c.data();
+  J.out = MatArg{E, lde, 0};
+  J.ws = wsc;
+  J.ws_stride = L.bytes;
+  J.opts = o;
+  J.write_y = true;
+  J.build_powers = !built;
+  J.skip_square = false;
+  float ms[4] = {0, 0, 0, 0};
+  if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
+  if (s_out) *s_out = s;
   if (report)
     if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
   return PS_OK;

@@ -137,6 +137,21 @@ hipError_t launch_plan(const PlanArgs& a, int batch, hipStream_t st);
 hipError_t launch_norm1(int working, int64_t n, MatArg X, double* wgmax, hipStream_t st);
 inline int64_t norm1_groups(int64_t n) { return (n + 7) / 8; }
 
+// B = (accumulate ? B : 0) + c_id I + sum_k c[k] M[k], and the per-workgroup
+// maxima (norm1_groups(n) of each) of the column abs sums of the new B and of Y
+constexpr int kMaxComb = 16;
+struct CombArgs {
+  MatArg M[kMaxComb];
+  double c[kMaxComb];
+  int count;
+  double c_id;
+  int accumulate;
+  MatArg B, Y;
+  double* wgB;
+  double* wgY;
+};
+hipError_t launch_comb_norm(int working, int64_t n, const CombArgs& a, hipStream_t st);
+
 // One Horner step: P_{i-1} = B_{i-1} + P_i Y (or, with cast_only, P = B_src
 // converted to the format of the consumer step).
 struct HornerArgs {

@@ -196,6 +196,53 @@ hipError_t launch_norm1(int working, int64_t n, MatArg X, double* wgmax, hipStre
 }
 
 // ---------------------------------------------------------------------------
+// k_comb_norm: a linear combination of matrices into B (one wave per column)
+// with the column abs sums of B and Y, maximum per workgroup
+// ---------------------------------------------------------------------------
+template <typename W>
+__global__ __launch_bounds__(NT) void k_comb_norm(int64_t n, CombArgs a) {
+  __shared__ double red[2][NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t col = (int64_t)blockIdx.x * NW + w;
+  double vb = 0.0, vy = 0.0;
+  if (col < n) {
+    W* b = (W*)a.B.p + col * a.B.ld;
+    const W* y = (const W*)a.Y.p + col * a.Y.ld;
+    for (int64_t rw = lane; rw < n; rw += 64) {
+      double v = a.accumulate ? (double)b[rw] : 0.0;
+      for (int k = 0; k < a.count; ++k) v += a.c[k] * (double)((const W*)a.M[k].p)[rw + col * a.M[k].ld];
+      if (rw == col) v += a.c_id;
+      const W out = (W)v;
+      b[rw] = out;
+      vb += fabs((double)out);
+      vy += fabs((double)y[rw]);
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      vb += __shfl_xor(vb, off, 64);
+      vy += __shfl_xor(vy, off, 64);
+    }
+  }
+  if (lane == 0) {
+    red[0][w] = vb;
+    red[1][w] = vy;
+  }
+  __syncthreads();
+  if (t < 2) {
+    double m = red[t][0];
+    for (int k = 1; k < NW; ++k)
+      if (red[t][k] > m || red[t][k] != red[t][k]) m = red[t][k];
+    (t == 0 ? a.wgB : a.wgY)[blockIdx.x] = m;
+  }
+}
+
+hipError_t launch_comb_norm(int working, int64_t n, const CombArgs& a, hipStream_t st) {
+  const dim3 grid((unsigned)norm1_groups(n)), block(NT);
+  if (working == 0) hipLaunchKernelGGL(k_comb_norm<double>, grid, block, 0, st, n, a);
+  else hipLaunchKernelGGL(k_comb_norm<float>, grid, block, 0, st, n, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_plan: one workgroup per matrix
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void k_plan(PlanArgs a) {

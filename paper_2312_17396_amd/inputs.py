@@ -20,6 +20,10 @@ available, see the paper's sections 3.3 and 4):
   grad_batch_512   64 matrices 512x512 with N(0,1)/sqrt(n) entries (float32)
                    and upstream gradients G with N(0,1) entries
   class_b(n)       the paper's class B generator 100*triu(N(0,1), 1)
+  shifted_1024     -t I + E, E a 1024x1024 N(0,1) matrix rescaled to
+                   ||E||_1 = eps (t = 0.5, eps = 0.05): a matrix near a
+                   negative scalar, the kind for which Algorithm 2's
+                   variable-s branch raises s above ceil(sqrt(m))
 """
 from __future__ import annotations
 
@@ -93,3 +97,7 @@ def grad_batch_512(batch: int = 64, n: int = 512):
 
 def class_b(n: int, k: int = 0) -> np.ndarray:
     return 100.0 * np.triu(rng(5, k).standard_normal((n, n)), 1)
+
+
+def shifted_1024(t: float = 0.5, eps: float = 0.05, n: int = 1024) -> np.ndarray:
+    return -t * np.eye(n) + rescaled_normal(n, eps, rng(8))

@@ -416,3 +416,54 @@ def test_auto_sigma_on_the_nonnormal_example():
     # a normal matrix: alpha_m = ||A||_1 for a diagonal one, so sigma = sigma0
     D = np.diag([-9.0, 3.0, 1.0])
     assert metrics.auto_sigma(D, 30, 6, u) == math.ceil(math.log2(9.0 / th))
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2's variable-s branch (fix_params = false, section 3.3)
+# --------------------------------------------------------------------------
+def _jordan_s(t, a, m):
+    """The branch's s for X = [[-t, a], [0, -t]] (t, a > 0) in exact rational
+    arithmetic from the closed forms X^k = (-t)^k I + k (-t)^(k-1) a N:
+    ||X^k||_1 = t^k + k t^(k-1) a, ||X||_1 = t + a, and
+    ||B_0||_1 = |sum_{j<s} c_j (-t)^j| + a |sum_{0<j<s} c_j j (-t)^(j-1)|."""
+    c = [F(1, math.factorial(k)) for k in range(m + 1)]
+    s = 1
+    while s * s < m:
+        s += 1
+    nX = t + a
+    if not (nX <= F(s) / F(math.e)) or s >= m:
+        return s
+
+    def nB0(s):
+        S = sum(c[j] * (-t) ** j for j in range(s))
+        Sp = sum(c[j] * j * (-t) ** (j - 1) for j in range(1, s))
+        return abs(S) + a * abs(Sp)
+    while t ** s + s * t ** (s - 1) * a > nB0(s) * nX ** s and s < m:
+        s += 1
+    return s
+
+
+@pytest.mark.parametrize("t,a", [(F(1, 2), F(1, 32)), (F(1, 4), F(1, 32)), (F(3, 4), F(1, 8)), (F(1), F(1, 4)),
+                                 (F(1, 2), F(1, 4)), (F(1, 4), F(1, 64))])
+def test_variable_s_on_jordan_blocks(t, a):
+    m = 30
+    X = np.array([[-float(t), float(a)], [0.0, -float(t)]])
+    assert metrics.variable_s(X, coeffs.taylor_exp(m)) == _jordan_s(t, a, m)
+
+
+def test_variable_s_special_cases():
+    m = 30
+    c = coeffs.taylor_exp(m)
+    # -tI, 0 < t <= 1: every partial sum of e^-t lies in (0, 1) while
+    # ||X^s|| = ||X||^s, so s grows to m (explicit powers)
+    assert metrics.variable_s(-0.5 * np.eye(5), c) == m
+    # tI, t > 0: ||B_0|| > 1 = ||X^s|| / ||X||^s, so s stays at ceil(sqrt(m))
+    assert metrics.variable_s(0.5 * np.eye(5), c) == 6
+    # nilpotent of order 2: Y = X^s = 0
+    assert metrics.variable_s(np.array([[0.0, 2.0], [0.0, 0.0]]), c) == 6
+    # ||X||_1 > s/e: the branch does not run
+    assert metrics.variable_s(-3.0 * np.eye(5), c) == 6
+    # small degrees: m = 4 grows from 2 to 4; m = 2 and m = 1 start at s = m
+    assert metrics.variable_s(-0.5 * np.eye(3), coeffs.taylor_exp(4)) == 4
+    assert metrics.variable_s(-0.5 * np.eye(3), coeffs.taylor_exp(2)) == 2
+    assert metrics.variable_s(-0.5 * np.eye(3), coeffs.taylor_exp(1)) == 1
