@@ -8,10 +8,11 @@
 // with |lo| <= ulp(hi) / 2.
 //
 // Kernels:
-//   k_gemm_dd     C = alpha A B in double-double (FP64 vector FMAs: the
-//                 product of two entries is exact as hi*hi + fma residual +
-//                 the two cross terms; accumulation by two-sum), alpha a
-//                 power of two.  Power table and squarings.
+//   k_gemm_dd     C = alpha A B in double-double on the FP64 vector units
+//                 (the head hi*hi of each product with its exact FMA
+//                 residual, the two cross terms in the tail, lo*lo dropped;
+//                 compensated summation), alpha a power of two.  Power table
+//                 and squarings.
 //   k_assemble_dd B_0..B_r = sum_j c_{si+j} X^j in double-double with
 //                 double-double coefficients (section 2: the blocks are
 //                 assembled in the working precision), column abs sums of
@@ -69,16 +70,22 @@ __device__ inline D2 d2_mul(D2 x, D2 y) {
   e = fma(x.lo, y.hi, e);
   return fast_two_sum(p, e);
 }
-// acc += x y in the dot-product loop: the exact head of the product, its tail
-// with the cross terms, one two-sum into the accumulator
+// One term of a double-double dot product, in the compensated form of Ogita,
+// Rump and Oishi's Dot2 ("Accurate sum and dot product", 2005): acc.hi is
+// the running sum of the product heads, acc.lo collects (unnormalised) the
+// two-sum errors of those additions and the product tails (FMA residual of
+// hi*hi and the two cross terms).  12 FP64 operations per term; the pair is
+// renormalised once at the end of the dot product (d2_finish).
 __device__ inline void d2_fma_acc(D2& acc, D2 x, D2 y) {
   const double p = x.hi * y.hi;
   double e = fma(x.hi, y.hi, -p);
   e = fma(x.hi, y.lo, e);
   e = fma(x.lo, y.hi, e);
   const D2 s = two_sum(acc.hi, p);
-  acc = fast_two_sum(s.hi, s.lo + (acc.lo + e));
+  acc.hi = s.hi;
+  acc.lo += s.lo + e;
 }
+__device__ inline D2 d2_finish(D2 acc) { return two_sum(acc.hi, acc.lo); }
 
 // ---------------------------------------------------------------------------
 // double-double GEMM tile: 64 x 64 outputs, 512 threads, 4 x 2 outputs per
@@ -124,8 +131,9 @@ __device__ inline void dd_store_b(double* S, int t, const double r[4]) {
   for (int i = 0; i < 4; ++i) S[2 * DD_PLANE + pl * DD_PLANE + (kk + i) * DD_LR + jj] = r[i];
 }
 
-// acc[4][2] += (alpha A)(tile rows) x B(tile cols) over all of K.  alpha is a
-// power of two applied to A exactly.  Ends with a barrier.
+// acc[4][2] = (alpha A)(tile rows) x B(tile cols) over all of K, returned as
+// normalised double-double values.  alpha is a power of two applied to A
+// exactly.  Ends with a barrier.
 __device__ inline void dd_mainloop(const DDMat& A, double alpha, const DDMat& B, int64_t n, int64_t m0, int64_t n0,
                                    char* smem, D2 acc[4][2]) {
   const int t = threadIdx.x;
@@ -167,6 +175,10 @@ __device__ inline void dd_mainloop(const DDMat& A, double alpha, const DDMat& B,
     dd_store_b(nx, t, rb);
     __syncthreads();
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = d2_finish(acc[i][j]);
 }
 
 __global__ __launch_bounds__(NT) void k_gemm_dd(int64_t n, DDMat A, double alpha, DDMat B, double* C, int64_t ldc,
