@@ -37,9 +37,31 @@ N = 1024
 M = 30
 S = 6
 PEAK_FP64_MFMA = 78.6   # TFLOP/s, MI355X dense FP64 matrix
+# dense MFMA peaks per tier (FP64, FP32, BF16, FP8) in flop/s and HBM bytes/s
+TIER_PEAK = {0: 78.6e12, 1: 157.3e12, 2: 2.5e15, 3: 5.0e15}
+HBM_BW = 8.0e12
+TIER_BYTES = {0: 8.0, 1: 4.0, 2: 2.0, 3: 1.0 + 1.0 / 32}   # per element, FP8 with its E8M0 scales
 
 
-EXTRAS = ("batched", "pade_cos", "grad", "auto", "vars", "dd")
+def step_ideal_s(rep, sigma, mixed):
+    """Ideal time of one evaluation at nominal peaks: sum over its steps of
+    max(flops / peak(tier), algorithmic bytes / HBM bandwidth)."""
+    n2, F = float(N) * N, 2.0 * N ** 3
+    gemm64 = max(F / TIER_PEAK[0], 3 * 8 * n2 / HBM_BW)
+    t = (S - 1) * gemm64 + sigma * gemm64                                    # powers, squarings
+    copies = sum(TIER_BYTES[k] for k in (1, 2, 3)) if mixed else 0.0
+    fs = rep["first_step"]
+    t += (S * 8 + (fs + 1) * 8 + copies) * n2 / HBM_BW                           # block assembly
+    tiers = rep["tier"]
+    t += (8 + TIER_BYTES[tiers[fs]]) * n2 / HBM_BW                              # B_first into step format
+    for i in range(fs, 0, -1):
+        ti, to = tiers[i], tiers[i - 1]
+        byts = (2 * TIER_BYTES[ti] + 8 + TIER_BYTES[to]) * n2                   # P_i, Y, B_{i-1}, P_{i-1}
+        t += max(F / TIER_PEAK[ti], byts / HBM_BW)
+    return t
+
+
+EXTRAS = ("latency", "batched", "pade_cos", "grad", "auto", "vars", "dd")
 
 
 def parse():
@@ -135,13 +157,15 @@ def main():
         res[mode] = timed("fixed" if mode == "plain" else "mixed")
 
     # tiers and accuracy (outside the timed region)
-    _, rep = ps.ps_expm(mats[1], M, s=S, sigma=sigmas[1], mode="mixed", report=True)
     plans = []
     errs = []
+    ideal = {"plain": 0.0, "mixed": 0.0}
     for a, sg in zip(mats, sigmas):
         em, rp = ps.ps_expm(a, M, s=S, sigma=sg, mode="mixed", report=True)
-        ef = ps.ps_expm(a, M, s=S, sigma=sg, mode="fixed")
-        plans.append([ps.TIER_NAMES[t] for t in rp["tier"][1:]])
+        ef, rf = ps.ps_expm(a, M, s=S, sigma=sg, mode="fixed", report=True)
+        ideal["mixed"] += step_ideal_s(rp, sg, True)
+        ideal["plain"] += step_ideal_s(rf, sg, False)
+        plans.append([ps.TIER_NAMES[t] for t in rp["tier"][1:rp["first_step"] + 1]])
         d = torch.linalg.matrix_norm(em - ef, ord=1).item() / torch.linalg.matrix_norm(ef, ord=1).item()
         errs.append(d)
 
@@ -182,6 +206,8 @@ def main():
         "tiers": plans,
         "rel_diff_mixed_vs_plain": [float("%.3e" % e) for e in errs],
         "roofline": roofline,
+        "step_roofline": {mode: {"ideal_ms": round(ideal[mode] * 1e3, 4), "measured_ms": round(res[mode] * 1e3, 4),
+                                 "frac": round(ideal[mode] / res[mode], 4)} for mode in res},
     }
     if "plain" in res and "mixed" in res:
         out["plain"] = {"evals_per_s": round(len(mats) / res["plain"], 2),
@@ -214,6 +240,10 @@ def _time(fn, reps, torch):
 
 def extra_workloads(ps, inputs, torch, which=EXTRAS):
     """Secondary workloads of the hot path (each a few seconds):
+    latency   one 64x64 FP64 matrix, ||A||_1 = 1, Taylor m = 16, s = 4, no
+              scaling: microseconds per evaluation, as a stream of ps_expm
+              calls and as one replayed hipGraph (the batched path with one
+              matrix);
     batched   4096 matrices, n uniform in {8..256}, ||A||_1 ~ U[0.05, 4], Taylor
               m = 18, s chosen per matrix, FP32: one persistent launch replayed
               from a hipGraph vs a loop of single-matrix calls;
@@ -230,6 +260,20 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
     import numpy as np
     res = {}
     dev = torch.device("cuda:0")
+    # ---- latency of the small case
+    if "latency" in which:
+        A1 = torch.tensor(inputs.single_64(), device=dev)
+        E1 = torch.empty_like(A1)
+        ws1 = ps.expm_workspace(A1, 16, 4, 0)
+        out = {"n": 64, "m": 16, "s": 4, "sigma": 0, "dtype": "f64"}
+        for mode in ("fixed", "mixed"):
+            tc = _time(lambda: ps.ps_expm(A1, 16, s=4, mode=mode, out=E1, workspace=ws1), 200, torch)
+            g = ps.BatchedGraph([A1], 16, s=[4], sigma=[0], mode=mode)
+            tg = _time(g.launch, 200, torch)
+            g.close()
+            out[mode] = {"us_per_eval_calls": round(tc * 1e6, 2), "us_per_eval_graph": round(tg * 1e6, 2)}
+        res["latency_single_64"] = out
+        del A1, E1, ws1
     # ---- batched
     if "batched" in which:
         mats, ts = inputs.batch_uneven()
