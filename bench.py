@@ -133,15 +133,63 @@ def main():
                 reps.append(r[1])
         return reps
 
-    def timed(mode):
-        for _ in range(args.warmup):
+    streams = [torch.cuda.Stream(device=dev) for _ in mats]   # default priority
+
+    def step_forked(mode):
+        """the four evaluations on four streams (they are independent), joined"""
+        cur = torch.cuda.current_stream(dev)
+        for st in streams:
+            st.wait_stream(cur)
+        for a, o, w, sg, st in zip(mats, outs, wss, sigmas, streams):
+            with torch.cuda.stream(st):
+                ps.ps_expm(a, M, s=S, sigma=sg, mode=mode, out=o, workspace=w)
+        for st in streams:
+            cur.wait_stream(st)
+
+    def capture(mode):
+        """one hipGraph of the forked step; its replays are checked against the
+        eager results (with eager work and synchronisations between them)"""
+        step(mode)
+        torch.cuda.synchronize()
+        ref = [o.clone() for o in outs]
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            step_forked(mode)
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step_forked(mode)
+        for _ in range(2):
+            for o in outs:
+                o.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            if not all(torch.equal(o, r) for o, r in zip(outs, ref)):
+                raise RuntimeError("graph replay differs from the eager evaluation")
             step(mode)
+            torch.cuda.synchronize()
+        return g
+
+    def run_timed(fn):
+        for _ in range(args.warmup):
+            fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            step(mode)
+            fn()
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / args.steps
+
+    eager = {}
+
+    def timed(mode):
+        eager[mode] = run_timed(lambda: step(mode))
+        g = capture(mode)
+        t = run_timed(g.replay)
+        del g
+        return t
 
     if args.calib_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -209,6 +257,11 @@ def main():
         "step_roofline": {mode: {"ideal_ms": round(ideal[mode] * 1e3, 4), "measured_ms": round(res[mode] * 1e3, 4),
                                  "frac": round(ideal[mode] / res[mode], 4)} for mode in res},
     }
+    out["schedule"] = ("one hipGraph per step: the four evaluations forked over four streams "
+                       "(default priority) and joined; replays checked bitwise against eager calls")
+    out["eager_sequential"] = {("plain" if mode == "fixed" else mode): {"ms_per_step": round(t * 1e3, 4),
+                                                                        "evals_per_s": round(len(mats) / t, 2)}
+                               for mode, t in eager.items()}
     if "plain" in res and "mixed" in res:
         out["plain"] = {"evals_per_s": round(len(mats) / res["plain"], 2),
                         "ms_per_step": round(res["plain"] * 1e3, 4),
