@@ -68,6 +68,9 @@ typedef enum { PS_TIER_F64 = 0, PS_TIER_F32 = 1, PS_TIER_BF16 = 2, PS_TIER_FP8 =
 #define PS_MODE_FIXED 0   /* Algorithm 1: every product in the working precision */
 #define PS_MODE_MIXED 1   /* Algorithms 2/3 (fixed s): per-step tiers from the norms */
 
+#define PS_RULE_BLOCKS 0  /* tiers from the assembled blocks' 1-norms (Thm 2.1, eq. (choose-ui)) */
+#define PS_RULE_APRIORI 1 /* tiers from coefficient magnitudes times powers of ||X||_1 */
+
 #define PS_MAX_BLOCKS 64  /* r + 1 <= PS_MAX_BLOCKS */
 
 typedef struct ps_opts {
@@ -80,6 +83,11 @@ typedef struct ps_opts {
   const int* tier_override;  /* optional host array of r+1 tiers (entry 0 ignored),
                                 replaces the plan (testing); NULL = plan */
   int profile;               /* nonzero: time the phases with hipEvents */
+  int rule;                  /* PS_RULE_BLOCKS (0, default): u_i from the 1-norms of
+                                the assembled blocks, ||B_i|| ||Y||^i (eq. (choose-ui));
+                                PS_RULE_APRIORI (1): the denominator bounded a priori by
+                                sum_{k in block i} |c_k| ||X||^k, the numerator the
+                                block norm ||B_0|| (never overestimated) */
 } ps_opts;
 
 typedef struct ps_report {
@@ -91,6 +99,7 @@ typedef struct ps_report {
   double normY;              /* ||X^s||_1 */
   int gemms[4];              /* GEMMs per tier: powers + Horner + squarings */
   float ms_power, ms_assemble, ms_horner, ms_square;  /* profile != 0 only */
+  double normX;              /* ||X||_1, X = 2^-sigma A (the first power) */
 } ps_report;
 
 /* Version of the ABI (major*10000 + minor*100 + patch). */

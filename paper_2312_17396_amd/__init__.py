@@ -34,7 +34,7 @@ class PSError(RuntimeError):
 
 class ps_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tier_mask", ctypes.c_uint), ("delta", ctypes.c_double),
-                ("tier_override", ctypes.POINTER(ctypes.c_int)), ("profile", ctypes.c_int)]
+                ("tier_override", ctypes.POINTER(ctypes.c_int)), ("profile", ctypes.c_int), ("rule", ctypes.c_int)]
 
 
 class ps_report(ctypes.Structure):
@@ -42,13 +42,13 @@ class ps_report(ctypes.Structure):
                 ("tier", ctypes.c_int * MAX_BLOCKS), ("u", ctypes.c_double * MAX_BLOCKS),
                 ("normB", ctypes.c_double * MAX_BLOCKS), ("normY", ctypes.c_double),
                 ("gemms", ctypes.c_int * 4), ("ms_power", ctypes.c_float), ("ms_assemble", ctypes.c_float),
-                ("ms_horner", ctypes.c_float), ("ms_square", ctypes.c_float)]
+                ("ms_horner", ctypes.c_float), ("ms_square", ctypes.c_float), ("normX", ctypes.c_double)]
 
     def to_dict(self):
         r = self.r
         return {"s": self.s, "r": r, "nu": self.nu, "first_step": self.first_step,
                 "tier": [self.tier[i] for i in range(r + 1)], "u": [self.u[i] for i in range(r + 1)],
-                "normB": [self.normB[i] for i in range(r + 1)], "normY": self.normY,
+                "normB": [self.normB[i] for i in range(r + 1)], "normY": self.normY, "normX": self.normX,
                 "gemms": list(self.gemms), "ms": {"power": self.ms_power, "assemble": self.ms_assemble,
                                                   "horner": self.ms_horner, "square": self.ms_square}}
 
@@ -144,9 +144,15 @@ def _darr(vals):
     return (ctypes.c_double * max(len(vals), 1))(*vals)
 
 
-def _opts(mode="fixed", tier_mask=0, delta=10.0, tier_override=None, profile=False):
+RULES = {"blocks": 0, "apriori": 1}
+
+
+def _opts(mode="fixed", tier_mask=0, delta=10.0, tier_override=None, profile=False, rule="blocks"):
     o = ps_opts()
     o.mode = MODE_MIXED if mode in ("mixed", MODE_MIXED) else MODE_FIXED
+    if rule not in RULES:
+        raise PSError(-1, "rule must be one of %s" % sorted(RULES))
+    o.rule = RULES[rule]
     o.tier_mask = int(tier_mask)
     o.delta = float(delta)
     keep = None
@@ -219,7 +225,8 @@ def default_s(m):
 # ---------------------------------------------------------------------------
 # single matrix
 # ---------------------------------------------------------------------------
-def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=None, report=False, profile=False):
+def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=None, report=False, profile=False,
+            rule="blocks"):
     """P = sum_k coef[k] A^k by Paterson--Stockmeyer (mixed mode: per-step tiers)."""
     import torch
     A = _check_square(A)
@@ -230,7 +237,7 @@ def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=N
     _check(lib().ps_workspace_size(dt, n, m, int(s), 0, ctypes.byref(nbytes)))
     ws, wsp, wsb = _workspace(nbytes.value, A.device)
     P = torch.empty_like(A)
-    o, _k = _opts(mode, tier_mask, delta, tier_override, profile)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile, rule=rule)
     rep = ps_report() if (report or profile) else None
     _check(lib().ps_eval(dt, n, A.data_ptr(), n, _darr(coef), m, int(s), P.data_ptr(), n, ctypes.byref(o),
                          ctypes.byref(rep) if rep is not None else None, wsp, wsb, _stream_ptr(A.device)))
@@ -238,7 +245,7 @@ def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=N
 
 
 def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, tier_override=None,
-            report=False, profile=False, out=None, workspace=None):
+            report=False, profile=False, out=None, workspace=None, rule="blocks"):
     """E = p(2^-sigma A)^(2^sigma); coef=None uses the Taylor coefficients 1/k!."""
     import torch
     A = _check_square(A)
@@ -251,7 +258,7 @@ def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
     else:
         ws, wsp, wsb = workspace
     E = torch.empty_like(A) if out is None else _check_out(out, A)
-    o, _k = _opts(mode, tier_mask, delta, tier_override, profile)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile, rule=rule)
     rep = ps_report() if (report or profile) else None
     c = _darr(coef) if coef is not None else None
     _check(lib().ps_expm(dt, n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n, ctypes.byref(o),
@@ -267,7 +274,7 @@ def theta_taylor(m, dtype="f64"):
 
 
 def ps_expm_auto(A, m, s=0, norm_guard=False, mode="fixed", tier_mask=0, delta=10.0, report=False,
-                 profile=False, out=None, workspace=None):
+                 profile=False, out=None, workspace=None, rule="blocks"):
     """E = p_m(2^-sigma A)^(2^sigma) with sigma from the alpha_m bound (Taylor
     coefficients); returns (E, sigma) or (E, sigma, report).  The norms are
     those of the column-major view (the transpose of a row-major tensor)."""
@@ -282,7 +289,7 @@ def ps_expm_auto(A, m, s=0, norm_guard=False, mode="fixed", tier_mask=0, delta=1
     else:
         ws, wsp, wsb = workspace
     E = torch.empty_like(A) if out is None else _check_out(out, A)
-    o, _k = _opts(mode, tier_mask, delta, None, profile)
+    o, _k = _opts(mode, tier_mask, delta, None, profile, rule=rule)
     rep = ps_report() if (report or profile) else None
     sig = ctypes.c_int()
     _check(lib().ps_expm_auto(dt, n, A.data_ptr(), n, int(m), int(s), int(bool(norm_guard)), E.data_ptr(), n,
@@ -292,7 +299,7 @@ def ps_expm_auto(A, m, s=0, norm_guard=False, mode="fixed", tier_mask=0, delta=1
 
 
 def ps_expm_vars(A, m, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
-                 profile=False, out=None, workspace=None):
+                 profile=False, out=None, workspace=None, rule="blocks"):
     """E = p(2^-sigma A)^(2^sigma) with the block size s chosen by Algorithm 2's
     variable-s branch; returns (E, s) or (E, s, report).  Norms are those of
     the column-major view (the transpose of a row-major tensor)."""
@@ -305,7 +312,7 @@ def ps_expm_vars(A, m, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
     else:
         ws, wsp, wsb = workspace
     E = torch.empty_like(A) if out is None else _check_out(out, A)
-    o, _k = _opts(mode, tier_mask, delta, None, profile)
+    o, _k = _opts(mode, tier_mask, delta, None, profile, rule=rule)
     rep = ps_report() if (report or profile) else None
     c = _darr(coef) if coef is not None else None
     s_out = ctypes.c_int()
@@ -381,7 +388,7 @@ def expm_workspace(A, m, s=0, sigma=0):
 
 
 def ps_eval_multi(A, coefs, s=0, square_arg=False, mode="fixed", tier_mask=0, delta=10.0, report=False,
-                  profile=False):
+                  profile=False, rule="blocks"):
     """[p_t(A) for t] (or p_t(A^2) with square_arg) sharing one power table."""
     import torch
     A = _check_square(A)
@@ -397,7 +404,7 @@ def ps_eval_multi(A, coefs, s=0, square_arg=False, mode="fixed", tier_mask=0, de
     cptrs = (_dp * k)(*[ctypes.cast(c, _dp) for c in carr])
     pptrs = (_vp * k)(*[o.data_ptr() for o in outs])
     lds = (ctypes.c_int64 * k)(*([n] * k))
-    o, _k = _opts(mode, tier_mask, delta, None, profile)
+    o, _k = _opts(mode, tier_mask, delta, None, profile, rule=rule)
     reps = (ps_report * k)() if (report or profile) else None
     _check(lib().ps_eval_multi(dt, n, A.data_ptr(), n, k, cptrs, degrees, int(s), int(bool(square_arg)), pptrs, lds,
                                ctypes.byref(o), reps, wsp, wsb, _stream_ptr(A.device)))
@@ -410,7 +417,7 @@ def ps_eval_multi(A, coefs, s=0, square_arg=False, mode="fixed", tier_mask=0, de
 # batches
 # ---------------------------------------------------------------------------
 def ps_expm_strided_batched(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
-                            tier_override=None, profile=False):
+                            tier_override=None, profile=False, rule="blocks"):
     """E[b] = p(2^-sigma A[b])^(2^sigma) for A of shape (batch, n, n)."""
     import torch
     if A.dim() != 3 or A.shape[1] != A.shape[2]:
@@ -422,7 +429,7 @@ def ps_expm_strided_batched(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_ma
     _check(lib().ps_workspace_size_strided(dt, bsz, n, int(m), int(s), int(sigma), ctypes.byref(nbytes)))
     ws, wsp, wsb = _workspace(nbytes.value, A.device)
     E = torch.empty_like(A)
-    o, _k = _opts(mode, tier_mask, delta, tier_override, profile)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile, rule=rule)
     reps = (ps_report * bsz)() if (report or profile) else None
     c = _darr(coef) if coef is not None else None
     _check(lib().ps_expm_strided_batched(dt, bsz, n, A.data_ptr(), n, n * n, c, int(m), int(s), int(sigma),
@@ -454,7 +461,7 @@ def batched_workspace_bytes(mats, m, s=None, dtype=None):
 
 
 def ps_expm_batched(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
-                    outs=None, workspace=None):
+                    outs=None, workspace=None, rule="blocks"):
     """E_b = p(2^-sigma_b A_b)^(2^sigma_b) for a list of square matrices of
     uneven order (1..256), one persistent launch.  s: None/0 (choose per
     matrix), an int, or a list; sigma: int or list."""
@@ -473,7 +480,7 @@ def ps_expm_batched(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask
     aptr = (_vp * k)(*[a.data_ptr() for a in mats])
     eptr = (_vp * k)(*[o.data_ptr() for o in outs])
     lda = (ctypes.c_int64 * k)(*[a.shape[0] for a in mats])
-    o, _k = _opts(mode, tier_mask, delta)
+    o, _k = _opts(mode, tier_mask, delta, rule=rule)
     tiers = (ctypes.c_int32 * (k * MAX_BLOCKS))() if report else None
     c = _darr(coef) if coef is not None else None
     _check(lib().ps_expm_batched(dt, k, n, aptr, lda, c, int(m), sv, sgv, eptr, lda, ctypes.byref(o), tiers,
@@ -492,7 +499,7 @@ class BatchedGraph:
     launch() replays it on the current stream.  The input and output tensors
     are held so their memory stays valid for every replay."""
 
-    def __init__(self, mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0):
+    def __init__(self, mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, rule="blocks"):
         import torch
         self.mats = [_check_square(a) for a in mats]
         k = len(self.mats)
@@ -503,7 +510,7 @@ class BatchedGraph:
         aptr = (_vp * k)(*[a.data_ptr() for a in self.mats])
         eptr = (_vp * k)(*[o.data_ptr() for o in self.outs])
         lda = (ctypes.c_int64 * k)(*[a.shape[0] for a in self.mats])
-        o, _k = _opts(mode, tier_mask, delta)
+        o, _k = _opts(mode, tier_mask, delta, rule=rule)
         c = _darr(coef) if coef is not None else None
         h = ctypes.c_void_p()
         _check(lib().ps_batched_prepare(dt, k, n, aptr, lda, c, int(m), sv, sgv, eptr, lda, ctypes.byref(o),

@@ -91,6 +91,7 @@ struct Opts {
   double delta = 10.0;
   const int* override_tiers = nullptr;
   int profile = 0;
+  int rule = PS_RULE_BLOCKS;
 };
 
 Opts read_opts(const ps_opts* o, int working) {
@@ -101,6 +102,7 @@ Opts read_opts(const ps_opts* o, int working) {
     r.delta = o->delta > 0 ? o->delta : 10.0;
     r.override_tiers = o->tier_override;
     r.profile = o->profile;
+    r.rule = o->rule;
   }
   r.mask |= 1u << working;
   for (int t = 0; t < working; ++t) r.mask &= ~(1u << t);
@@ -142,7 +144,7 @@ Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_a
   L.off_ybf16 = off; off += al256((size_t)L.Mp * L.Kp * 2);
   L.off_yfp8 = off;  off += al256((size_t)L.Mp * L.Kp);
   L.off_yfp8s = off; off += al256((size_t)L.Mp * (L.Kp / 32));
-  L.off_colsum = off; off += al256((size_t)(L.nB + 1) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
+  L.off_colsum = off; off += al256((size_t)(L.nB + 2) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
   L.off_plan = off;  off += al256(sizeof(Plan));
   L.bytes = al256(off);
   return L;
@@ -173,6 +175,7 @@ ps_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
 
 ps_status check_opts(const Opts& o) {
   if (o.mode != PS_MODE_FIXED && o.mode != PS_MODE_MIXED) return fail(PS_ERR_ARG, "opts.mode must be 0 or 1");
+  if (o.rule != PS_RULE_BLOCKS && o.rule != PS_RULE_APRIORI) return fail(PS_ERR_ARG, "opts.rule must be 0 or 1");
   return PS_OK;
 }
 
@@ -293,6 +296,7 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
   pa.mask = J.opts.mask;
   pa.delta = J.opts.delta;
   pa.abs_cm = fabs(cf.c[L.m]);
+  pa.rule = J.opts.rule;
   pa.use_override = J.opts.override_tiers != nullptr;
   if (pa.use_override)
     for (int i = 0; i <= L.r; ++i) pa.override_tier[i] = J.opts.override_tiers[i];
@@ -371,6 +375,7 @@ ps_status fill_report(const Layout& L, const Job& J, int b, ps_report* rep, hipS
     rep->normB[i] = P.normB[i];
   }
   rep->normY = P.normY;
+  rep->normX = P.normX;
   rep->gemms[L.working] += L.npow + L.sigma;
   for (int i = L.first_step; i >= 1; --i) rep->gemms[P.tier[i]] += 1;
   if (ms) {
@@ -929,7 +934,7 @@ static ps_status multi_layouts(ps_dtype dtype, int64_t n, int k, const int* degr
     priv.off_B = o;      o += (size_t)Lt.nB * Lt.slot;
     priv.off_P0 = o;     o += Lt.pslot;
     priv.off_P1 = o;     o += Lt.pslot;
-    priv.off_colsum = o; o += al256((size_t)(Lt.nB + 1) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
+    priv.off_colsum = o; o += al256((size_t)(Lt.nB + 2) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
     priv.off_plan = o;   o += al256(sizeof(Plan));
     // shared offsets from polynomial 0
     priv.off_pow = base.off_pow;

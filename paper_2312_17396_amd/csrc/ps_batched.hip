@@ -74,6 +74,7 @@ struct BatchArgs {
   int* chosen;            // per matrix: chosen block size (for reports)
   int batch;
   int mode;
+  int rule;
   unsigned mask;
   double delta;
   char* ws;
@@ -253,7 +254,7 @@ template <typename W>
 __global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   __shared__ double red[8 * NW];
-  __shared__ double norms[PS_MAX_BLOCKS + 1];
+  __shared__ double norms[PS_MAX_BLOCKS + 2];
   const int b = blockIdx.x;
   const BatchRes& it = a.res[b];
   const Layout& L = it.L;
@@ -266,6 +267,7 @@ __global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
   pa.mask = a.mask;
   pa.delta = a.delta;
   pa.abs_cm = fabs(a.cf.c[L.m]);
+  pa.rule = a.rule;
   pa.use_override = 0;
   pa.ws = it.ws;
   pa.ws_stride = 0;
@@ -465,6 +467,8 @@ ps_status fill_args(ps_dtype dt, const double* coef, int m, const ps_opts* opts,
   ba.mode = opts ? opts->mode : PS_MODE_FIXED;
   if (ba.mode != PS_MODE_FIXED && ba.mode != PS_MODE_MIXED) return bfail(PS_ERR_ARG, "opts.mode must be 0 or 1");
   if (opts && opts->tier_override) return bfail(PS_ERR_UNSUPPORTED, "tier_override is not supported for batches");
+  ba.rule = opts ? opts->rule : PS_RULE_BLOCKS;
+  if (ba.rule != PS_RULE_BLOCKS && ba.rule != PS_RULE_APRIORI) return bfail(PS_ERR_ARG, "opts.rule must be 0 or 1");
   unsigned mask = (opts && opts->tier_mask) ? opts->tier_mask : 0xFu;
   mask |= 1u << W;
   for (int t = 0; t < W; ++t) mask &= ~(1u << t);

@@ -287,6 +287,11 @@ __global__ __launch_bounds__(NT) void k_assemble_dd(AssembleDD a) {
       }
     }
   }
+  if (col == 0 && chunk == 0) {   // |c_k| (hi parts) beside the plan
+    Plan* P = (Plan*)(a.ws + L.off_plan);
+    for (int k = lane; k <= m; k += 64) P->abs_coef[k] = fabs(a.chi[k]);
+  }
+  double xsum = 0.0;   // column abs sum of X_1 (hi parts), first pass over the blocks
   for (int i0 = 0; i0 < nB; i0 += 4) {
     D2 bv[RPL][4];
 #pragma unroll
@@ -299,6 +304,9 @@ __global__ __launch_bounds__(NT) void k_assemble_dd(AssembleDD a) {
     for (int j = 1; j < s; ++j) {
       D2 xj[RPL];
       load_x(j, xj);
+      if (j == 1 && i0 == 0)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) xsum += fabs(xj[q].hi);
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
         const int k = s * (i0 + ii) + j;
@@ -329,8 +337,15 @@ __global__ __launch_bounds__(NT) void k_assemble_dd(AssembleDD a) {
     }
   }
   double v = ysum;
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (lane == 0) colsum[((int64_t)nB * nch + chunk) * n + col] = v;
+  double vx = s == 1 ? ysum : xsum;   // s = 1: X_1 is Y
+  for (int off = 32; off >= 1; off >>= 1) {
+    v += __shfl_xor(v, off, 64);
+    vx += __shfl_xor(vx, off, 64);
+  }
+  if (lane == 0) {
+    colsum[((int64_t)nB * nch + chunk) * n + col] = v;
+    colsum[((int64_t)(nB + 1) * nch + chunk) * n + col] = vx;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -477,7 +492,7 @@ Layout dd_layout(int64_t n, int m, int s, int sigma) {
   D.off_ybf16 = off; off += al256((size_t)D.Mp * D.Kp * 2);
   D.off_yfp8 = off;  off += al256((size_t)D.Mp * D.Kp);
   D.off_yfp8s = off; off += al256((size_t)D.Mp * (D.Kp / 32));
-  D.off_colsum = off; off += al256((size_t)(D.nB + 1) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
+  D.off_colsum = off; off += al256((size_t)(D.nB + 2) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
   D.off_plan = off;  off += al256(sizeof(Plan));
   D.off_coef = off;  off += al256((size_t)2 * (m + 1) * 8);
   D.bytes = al256(off);
@@ -541,6 +556,7 @@ ps_status ps_expm_dd(int64_t n, const double* A, int64_t lda, const double* coef
   const int mode = opts ? opts->mode : PS_MODE_FIXED;
   if (mode != PS_MODE_FIXED && mode != PS_MODE_MIXED) return dfail(PS_ERR_ARG, "opts.mode must be 0 or 1");
   if (opts && opts->tier_override) return dfail(PS_ERR_UNSUPPORTED, "tier_override is not supported by ps_expm_dd");
+  if (opts && opts->rule != PS_RULE_BLOCKS) return dfail(PS_ERR_UNSUPPORTED, "ps_expm_dd plans from the block norms only");
   const unsigned mask = ((opts && opts->tier_mask) ? opts->tier_mask : 0xFu) & 0xFu;
   const double delta = (opts && opts->delta > 0) ? opts->delta : 10.0;
   hipStream_t st = (hipStream_t)stream;
@@ -674,6 +690,7 @@ ps_status ps_expm_dd(int64_t n, const double* A, int64_t lda, const double* coef
       report->normB[i] = pl.normB[i];
     }
     report->normY = pl.normY;
+    report->normX = pl.normX;
   }
   return PS_OK;
 }

@@ -677,6 +677,12 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
       }
     }
   }
+  // |c_k| for the a-priori planning rule (one wave writes them)
+  if (col == 0 && chunk == 0) {
+    Plan* P = (Plan*)(ws + L.off_plan);
+    for (int k = lane; k <= m; k += 64) P->abs_coef[k] = fabs(cf.c[k]);
+  }
+  double xsum = 0.0;   // column abs sum of X_1 (taken in the first pass over the blocks)
   // blocks in chunks of 8 so their running values stay in registers
   for (int i0 = 0; i0 < nB; i0 += 8) {
     W bv[RPL][8];
@@ -691,6 +697,9 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
     for (int j = 1; j < s; ++j) {
       W xj[RPL];
       load_x(j, xj);
+      if (j == 1 && i0 == 0)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) xsum += fabs((double)xj[q]);
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii) {
         const int k = s * (i0 + ii) + j;
@@ -719,14 +728,21 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
     }
   }
   double v = ysum;
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (lane == 0) colsum[((int64_t)nB * nch + chunk) * n + col] = v;
+  double vx = s == 1 ? ysum : xsum;   // s = 1: X_1 is Y
+  for (int off = 32; off >= 1; off >>= 1) {
+    v += __shfl_xor(v, off, 64);
+    vx += __shfl_xor(vx, off, 64);
+  }
+  if (lane == 0) {
+    colsum[((int64_t)nB * nch + chunk) * n + col] = v;
+    colsum[((int64_t)(nB + 1) * nch + chunk) * n + col] = vx;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // per-matrix plan (whole workgroup): norms = max over columns of the summed
 // partial column sums, then the tier rule of ps_planner.h.  Thread 0 writes
-// the Plan; ends with a barrier.  red: NT doubles, norms: PS_MAX_BLOCKS+1
+// the Plan; ends with a barrier.  red: NT doubles, norms: PS_MAX_BLOCKS+2
 // doubles, both in LDS.
 // ---------------------------------------------------------------------------
 // PT: threads of the workgroup (red holds 8 PT / 64 doubles).  The norms do
@@ -741,7 +757,8 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
   // each thread: running max over its columns of every block's column sum
   // (partial sums of the row chunks added in chunk order); the loads of
   // different blocks and chunks are independent, so their latencies overlap
-  for (int i0 = 0; i0 <= a.nB; i0 += 8) {
+  const int rows = a.nB + 1;   // column-sum rows: B_0 .. B_{nB-1}, Y, X
+  for (int i0 = 0; i0 <= rows; i0 += 8) {
     double mx[8];
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) mx[ii] = 0.0;
@@ -755,9 +772,9 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
       for (int64_t ch = 0; ch < nch; ++ch) {
 #pragma unroll
         for (int ii = 0; ii < 8; ++ii) {
-          const int i = min(i0 + ii, a.nB);   // clamped: every load is unconditional
+          const int i = min(i0 + ii, rows);   // clamped: every load is unconditional
           const double v = colsum[((int64_t)i * nch + ch) * n + c];
-          sum[ii] += (i0 + ii <= a.nB) ? v : 0.0;
+          sum[ii] += (i0 + ii <= rows) ? v : 0.0;
         }
       }
 #pragma unroll
@@ -776,7 +793,7 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii) red[ii * PW + w] = mx[ii];
     __syncthreads();
-    if (t < 8 && i0 + t <= a.nB) {
+    if (t < 8 && i0 + t <= rows) {
       double v = red[t * PW];
       for (int k = 1; k < PW; ++k) {
         const double o = red[t * PW + k];
@@ -790,12 +807,16 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
   __shared__ int s_tier[PS_MAX_BLOCKS];
   __shared__ double s_u[PS_MAX_BLOCKS];
   __shared__ int s_nu;
-  __shared__ double s_ny;
+  __shared__ double s_ny, s_nx;
+  __shared__ double s_nb[PS_MAX_BLOCKS];
   if (t == 0) {
-    // norms[nB] holds ||Y||; with s | m, nB = r and slot r then receives
-    // ||B_r|| = |c_m| (B_r = c_m I), so ||Y|| is read out first
+    // norms[nB] holds ||Y|| and norms[nB + 1] ||X||; with s | m, nB = r and
+    // slot r then receives ||B_r|| = |c_m| (B_r = c_m I), so ||Y|| is read
+    // out first
     const double ny = norms[a.nB];
+    const double nx = norms[a.nB + 1];
     s_ny = ny;
+    s_nx = nx;
     if (a.trivial_last) norms[a.r] = a.abs_cm;
     if (a.use_override) {
       for (int i = 0; i <= a.r; ++i) {
@@ -807,6 +828,25 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
     } else if (a.mode == PS_MODE_FIXED) {
       for (int i = 0; i <= a.r; ++i) { s_tier[i] = a.working; s_u[i] = tier_unit_roundoff(a.working); }
       s_nu = a.r + 1;
+    } else if (a.rule == PS_RULE_APRIORI) {
+      // ||B_i|| ||Y||^i bounded by sum_{k in block i} |c_k| ||X||^k, written as
+      // nb_i ||X||^(s i) with nb_i = sum_j |c_{si+j}| ||X||^j; ||B_0|| exact
+      const double* ac = ((const Plan*)(ws + L.off_plan))->abs_coef;
+      const int sb = L.s;
+      s_nb[0] = norms[0];
+      for (int i = 1; i <= a.r; ++i) {
+        double v = 0.0, p = 1.0;
+        for (int k = sb * i; k <= min(sb * i + sb - 1, L.m); ++k) {
+          v += ac[k] * p;
+          p *= nx;
+        }
+        s_nb[i] = v;
+      }
+      double nys = 1.0;
+      for (int j = 0; j < sb; ++j) nys *= nx;
+      int nu;
+      plan_tiers(a.r, s_nb, nys, a.working, a.mask, a.delta, s_tier, s_u, &nu);
+      s_nu = nu;
     } else {
       int nu;
       plan_tiers(a.r, norms, ny, a.working, a.mask, a.delta, s_tier, s_u, &nu);
@@ -822,6 +862,7 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
   }
   if (t == 0) {
     P->normY = s_ny;
+    P->normX = s_nx;
     P->nu = s_nu;
   }
   __syncthreads();

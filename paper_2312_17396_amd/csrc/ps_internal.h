@@ -29,8 +29,10 @@ struct Plan {
   double u[PS_MAX_BLOCKS];
   double normB[PS_MAX_BLOCKS];
   double normY;
+  double normX;                     // ||X||_1 (X = X_1)
   int nu;
   int pad_[3];
+  double abs_coef[kMaxDegree + 1];  // |c_k|, written by the block assembly for the a-priori rule
 };
 
 struct Coefs {
@@ -57,7 +59,7 @@ struct Layout {
   int nB;
   size_t off_P0, off_P1, off_R;
   size_t off_yf32, off_ybf16, off_yfp8, off_yfp8s;
-  size_t off_colsum;   // (nB + 1) * nchunks * n doubles: partial column abs sums of B_i and Y
+  size_t off_colsum;   // (nB + 2) * nchunks * n doubles: partial column abs sums of B_i, Y and X
   size_t off_plan;
   size_t off_coef;     // double-double coefficients (hi[m+1], lo[m+1]); double-double path only
   size_t bytes;        // total per matrix
@@ -121,6 +123,7 @@ hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, i
 // Per-matrix planning kernel.
 struct PlanArgs {
   int r, mode, working, nB, trivial_last;
+  int rule;             // PS_RULE_BLOCKS or PS_RULE_APRIORI
   unsigned mask;
   double delta;
   double abs_cm;        // |c_m| (norm of B_r = c_m I when s divides m)

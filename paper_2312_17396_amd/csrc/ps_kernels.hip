@@ -247,7 +247,7 @@ hipError_t launch_comb_norm(int working, int64_t n, const CombArgs& a, hipStream
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void k_plan(PlanArgs a) {
   __shared__ double red[8 * NW];
-  __shared__ double norms[PS_MAX_BLOCKS + 1];
+  __shared__ double norms[PS_MAX_BLOCKS + 2];
   char* ws = a.ws + (int64_t)blockIdx.x * a.ws_stride;
   plan_matrix<NT>(a, a.L, ws, red, norms);
 }

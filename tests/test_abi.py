@@ -122,3 +122,13 @@ def test_theta_taylor_host_matches_oracle():
             assert abs(a - b) <= 1e-12 * b, (dt, m, a, b)
     with pytest.raises(ps.PSError):
         ps.theta_taylor(171)
+
+
+def test_rule_names_checked_on_the_host():
+    import paper_2312_17396_amd as ps
+    o, _ = ps._opts("mixed", rule="apriori")
+    assert o.rule == 1
+    o, _ = ps._opts("mixed")
+    assert o.rule == 0
+    with pytest.raises(ps.PSError):
+        ps._opts("mixed", rule="nonsense")
