@@ -61,7 +61,7 @@ def step_ideal_s(rep, sigma, mixed):
     return t
 
 
-EXTRAS = ("latency", "batched", "pade_cos", "grad", "auto", "vars", "dd")
+EXTRAS = ("latency", "batched", "pade_cos", "grad", "auto", "select", "vars", "dd")
 
 
 def parse():
@@ -305,6 +305,8 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
     grad      64 FP32 matrices of order 512: forward + hand-written adjoint;
     auto      the dense n = 1024 set with the scaling chosen by the alpha_m bound
               (ps_expm_auto) instead of ceil(log2 ||A||_1);
+    select    the dense n = 1024 set with the Taylor degree (<= 42) and the scaling
+              chosen together by the alpha_m bound (ps_expm_select);
     vars      n = 1024, A = -0.5 I + E with ||E||_1 = 0.05, Taylor m = 30, sigma = 0:
               Algorithm 2's variable-s branch (ps_expm_vars) against s = 6;
     dd        n = 1024, ||A||_1 = 1, Taylor m = 30 (theta_30 = 1.16 at u = 2^-106,
@@ -394,6 +396,22 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
                                        "ms_per_step": round(ta * 1e3, 3), "evals_per_s": round(len(mats) / ta, 1),
                                        "note": "mixed tiers; includes the two norm read-backs of each call"}
         del mats, outs, wsa
+    # ---- joint choice of degree and scaling
+    if "select" in which:
+        mats = [torch.tensor(inputs.dense_1024(t), device=dev) for t in inputs.DENSE_NORMS]
+        wsl = [ps.select_workspace(a, 42) for a in mats]
+        outs = [torch.empty_like(a) for a in mats]
+        chosen = [ps.ps_expm_select(a, 42, mode="mixed", out=o, workspace=w)[1] for a, o, w in zip(mats, outs, wsl)]
+
+        def select_step():
+            for a, o, w in zip(mats, outs, wsl):
+                ps.ps_expm_select(a, 42, mode="mixed", out=o, workspace=w)
+        tsel = _time(select_step, 5, torch)
+        res["expm_select_dense_1024"] = {"m_max": 42, "chosen_m_s_sigma": [list(c) for c in chosen],
+                                         "ms_per_step": round(tsel * 1e3, 3),
+                                         "evals_per_s": round(len(mats) / tsel, 1),
+                                         "note": "mixed tiers, eager sequential calls; two norm read-backs per call"}
+        del mats, outs, wsl
     # ---- variable block size (Algorithm 2, fix_params = false)
     if "vars" in which:
         Av = torch.tensor(inputs.shifted_1024(), device=dev)

@@ -192,6 +192,31 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
                        ps_report* report, int* sigma_out, void* ws, size_t ws_bytes,
                        void* stream);
 
+/* Workspace bytes for ps_expm_select (the power table up to the largest
+ * candidate's max(s, d* + 1), the largest candidate layout, norm scratch). */
+ps_status ps_workspace_size_select(ps_dtype dtype, int64_t n, int m_max, size_t* bytes);
+
+/* E = p_m(2^-sigma A)^(2^sigma), Taylor coefficients, with the degree m and
+ * the scaling sigma chosen together by the alpha_m bound (section 3.2, eq.
+ * (alpha_m-X)): the candidates are the degrees m = q^2 and m = q(q+1) up to
+ * m_max (the PS-optimal degrees: s = ceil(sqrt(m)) gives s - 1 powers and
+ * floor(m/s) - [s | m] Horner products); sigma0 makes ||2^-sigma0 A||_1 at
+ * most the largest candidate's theta; the powers of X0 = 2^-sigma0 A give
+ * alpha_m; for each candidate the least sigma with
+ * 2^-sigma alpha_m(A) <= theta_m (theta_m as in ps_theta_taylor) is taken,
+ * and the candidate with the fewest products plus squarings (the smaller m
+ * on ties) is evaluated on the same powers (exact power-of-two rescaling).
+ * The candidates are examined in increasing m, and the search stops at the
+ * first one whose products alone reach the best total (the PS cost grows
+ * strictly along the list), so powers are formed only as far as
+ * max(s, d* + 1) of the examined candidates.  chosen: host array of 3 ints
+ * receiving m, s, sigma (may be NULL).  1 <= m_max <= 170.  The call
+ * synchronizes the stream once for ||A||_1 and once per extension of the
+ * powers.  Errors: as ps_expm_auto. */
+ps_status ps_expm_select(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m_max,
+                         void* E, int64_t lde, const ps_opts* opts, ps_report* report,
+                         int* chosen, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace bytes for ps_expm_vars: the power table X^2 .. X^m (s may grow to
  * m), the largest block / iterate / plan section over s0 <= s <= m, one
  * matrix for the running B_0 and the norm scratch. */

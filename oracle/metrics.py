@@ -24,6 +24,12 @@ TEST INFRASTRUCTURE ONLY (part of the oracle).
       X0 = 2^-sigma0 A from its powers (repeated multiplication in IEEE
       double), sigma the smallest with 2^-sigma alpha_m(A) <= theta_m; with
       norm_guard also ||2^-sigma A||_1 <= s / e (section 3.2).
+  select_degree(A, m_max, u)  the joint choice of (m, s, sigma) by the
+      alpha_m bound: candidates m = q^2, q(q+1) <= m_max with PS cost
+      (s - 1) + floor(m/s) - [s | m], s = ceil(sqrt(m)); alpha_m(A) from the
+      powers of A (repeated multiplication in IEEE double); for each m the
+      least sigma with 2^-sigma alpha_m(A) <= theta_m; the least cost plus
+      sigma wins, the smaller m on ties (section 3.2).
   variable_s(X, coef)  the block size of Algorithm 2's variable-s branch
       (fix_params = false, section 3.3): s = ceil(sqrt(m)); only when
       ||X||_1 <= s / e, B_0 = sum_{j<s} c_j X^j and Y = X^s, then while
@@ -163,3 +169,47 @@ def variable_s(X, coef) -> int:
         s += 1
         Y = X @ Y
     return s
+
+
+def _ceil_sqrt(m: int) -> int:
+    s = 1
+    while s * s < m:
+        s += 1
+    return s
+
+
+def select_degree(A, m_max: int, u: float):
+    A = np.asarray(A, dtype=np.float64)
+    cands = []
+    q = 1
+    while q * q <= m_max:
+        cands.append(q * q)
+        if q * (q + 1) <= m_max:
+            cands.append(q * (q + 1))
+        q += 1
+    thetas = [theta_taylor(m, u) for m in cands]
+    nA = norm1(A)
+    s0 = _smallest_shift(nA, thetas[-1])
+    X0 = A * math.ldexp(1.0, -s0)
+    dstar = []
+    for m in cands:
+        d = 1
+        while (d + 1) * d <= m + 1:
+            d += 1
+        dstar.append(d)
+    D = max(max(_ceil_sqrt(m), d + 1) for m, d in zip(cands, dstar))
+    norms = {1: norm1(X0)}
+    P = X0
+    for d in range(2, D + 1):
+        P = P @ X0
+        norms[d] = norm1(P)
+    best = None
+    for m, d, th in zip(cands, dstar, thetas):
+        a0 = max(norms[d] ** (1.0 / d), norms[d + 1] ** (1.0 / (d + 1)))
+        sig = _smallest_shift(math.ldexp(a0, s0), th)
+        s = _ceil_sqrt(m)
+        r = m // s
+        cost = (s - 1) + r - (1 if m == s * r else 0) + sig
+        if best is None or cost < best[0]:
+            best = (cost, m, s, sig)
+    return best[1], best[2], best[3]

@@ -78,6 +78,8 @@ _SIGS = {
     "ps_theta_taylor": ([_i, _i, _dp], _i),
     "ps_workspace_size_auto": ([_i, _i64, _i, _i, _szp], _i),
     "ps_expm_auto": ([_i, _i64, _vp, _i64, _i, _i, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
+    "ps_workspace_size_select": ([_i, _i64, _i, _szp], _i),
+    "ps_expm_select": ([_i, _i64, _vp, _i64, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
     "ps_workspace_size_vars": ([_i, _i64, _i, _i, _szp], _i),
     "ps_expm_vars": ([_i, _i64, _vp, _i64, _dp, _i, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
     "ps_workspace_size_dd": ([_i64, _i, _i, _i, _szp], _i),
@@ -320,6 +322,37 @@ def ps_expm_vars(A, m, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
                               ctypes.byref(rep) if rep is not None else None, ctypes.byref(s_out), wsp, wsb,
                               _stream_ptr(A.device)))
     return (E, s_out.value, rep.to_dict()) if rep is not None else (E, s_out.value)
+
+
+def ps_expm_select(A, m_max, mode="fixed", tier_mask=0, delta=10.0, report=False, profile=False, out=None,
+                   workspace=None, rule="blocks"):
+    """exp(A) with the Taylor degree m <= m_max and the scaling sigma chosen
+    together by the alpha_m bound; returns (E, (m, s, sigma)) or
+    (E, (m, s, sigma), report).  Norms are those of the column-major view."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    if workspace is None:
+        ws, wsp, wsb = select_workspace(A, m_max)
+    else:
+        ws, wsp, wsb = workspace
+    E = torch.empty_like(A) if out is None else _check_out(out, A)
+    o, _k = _opts(mode, tier_mask, delta, None, profile, rule=rule)
+    rep = ps_report() if (report or profile) else None
+    ch = (ctypes.c_int * 3)()
+    _check(lib().ps_expm_select(dt, n, A.data_ptr(), n, int(m_max), E.data_ptr(), n, ctypes.byref(o),
+                                ctypes.byref(rep) if rep is not None else None, ch, wsp, wsb,
+                                _stream_ptr(A.device)))
+    chosen = (ch[0], ch[1], ch[2])
+    return (E, chosen, rep.to_dict()) if rep is not None else (E, chosen)
+
+
+def select_workspace(A, m_max):
+    """Pre-allocate a workspace for repeated ps_expm_select calls of this shape."""
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_select(_dtype_code(A), A.shape[0], int(m_max), ctypes.byref(nbytes)))
+    return _workspace(nbytes.value, A.device)
 
 
 def vars_workspace(A, m, sigma=0):

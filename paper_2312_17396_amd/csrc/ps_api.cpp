@@ -490,6 +490,35 @@ static ps_status read_norm_pair(const double* dev, int64_t n, hipStream_t st, do
   return PS_OK;
 }
 
+// Joint choice of the degree and the scaling.  Candidates are the degrees
+// m = q^2 and m = q(q+1) up to m_max, for which PS with s = ceil(sqrt(m))
+// costs s - 1 powers and floor(m/s) - [s | m] Horner products.  One power
+// table X0^2 .. X0^j serves the alpha_m bound of the candidates and the
+// evaluation; the workspace holds it up to D = the largest of s and d* + 1
+// over the candidates.
+struct SelectPlan {
+  std::vector<int> cand;   // candidate degrees, increasing
+  int D = 1;               // highest power formed
+  size_t off_wg = 0, bytes = 0;
+};
+static int ps_cost(int m) {
+  const int s = default_s(m), r = m / s;
+  return (s - 1) + (r - ((r >= 1 && m == s * r) ? 1 : 0));
+}
+static SelectPlan select_plan(ps_dtype dtype, int64_t n, int m_max) {
+  SelectPlan P;
+  for (int q = 1; q * q <= m_max; ++q) {
+    P.cand.push_back(q * q);
+    if (q * (q + 1) <= m_max) P.cand.push_back(q * (q + 1));
+  }
+  for (int m : P.cand) P.D = std::max(P.D, std::max(default_s(m), alpha_dstar(m) + 1));
+  size_t mx = 0;
+  for (int m : P.cand) mx = std::max(mx, make_layout(dtype, n, m, default_s(m), 1, 0, P.D - 1).bytes);
+  P.off_wg = mx;
+  P.bytes = al256(mx + (size_t)P.D * norm1_groups(n) * sizeof(double));
+  return P;
+}
+
 static Layout auto_layout(ps_dtype dtype, int64_t n, int m, int s) {
   const int D = std::max(s, alpha_dstar(m) + 1);
   return make_layout(dtype, n, m, s, 1, 0, D - 1);
@@ -746,6 +775,139 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
   float ms[4] = {0, 0, 0, 0};
   if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
   if (sigma_out) *sigma_out = sigma;
+  if (report)
+    if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
+  return PS_OK;
+}
+
+ps_status ps_workspace_size_select(ps_dtype dtype, int64_t n, int m_max, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  int s = 0;
+  if (ps_status e = check_common(dtype, n, m_max, &s, 1)) return e;
+  if (m_max < 1 || m_max > 170) return fail(PS_ERR_ARG, "m_max = %d out of range [1, 170]", m_max);
+  *bytes = select_plan(dtype, n, m_max).bytes;
+  return PS_OK;
+}
+
+ps_status ps_expm_select(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m_max, void* E, int64_t lde,
+                         const ps_opts* opts, ps_report* report, int* chosen, void* ws, size_t ws_bytes,
+                         void* stream) {
+  int s_chk = 0;
+  if (ps_status e = check_common(dtype, n, m_max, &s_chk, 1)) return e;
+  if (m_max < 1 || m_max > 170) return fail(PS_ERR_ARG, "m_max = %d out of range [1, 170]", m_max);
+  if (!A || !E) return fail(PS_ERR_ARG, "NULL matrix pointer");
+  if (lda < n || lde < n) return fail(PS_ERR_ARG, "leading dimension smaller than n");
+  const int esize = dtype == PS_F64 ? 8 : 4;
+  const size_t spanA = mat_span_bytes(n, lda, esize), spanE = mat_span_bytes(n, lde, esize);
+  if (overlap(A, spanA, E, spanE)) return fail(PS_ERR_ALIAS, "output overlaps the input matrix");
+  Opts o = read_opts(opts, dtype == PS_F64 ? 0 : 1);
+  if (ps_status e = check_opts(o)) return e;
+  if (o.override_tiers) return fail(PS_ERR_UNSUPPORTED, "tier_override is not supported by ps_expm_select");
+  const SelectPlan SP = select_plan(dtype, n, m_max);
+  if (ps_status e = check_ws(ws, ws_bytes, SP.bytes)) return e;
+  if (overlap(ws, SP.bytes, E, spanE) || overlap(ws, SP.bytes, A, spanA))
+    return fail(PS_ERR_ALIAS, "workspace overlaps a matrix argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int W = dtype == PS_F64 ? 0 : 1;
+  const double u = W == 0 ? 0x1p-53 : 0x1p-24;
+  char* wsc = (char*)ws;
+  double* wg = (double*)(wsc + SP.off_wg);
+  const int64_t G = norm1_groups(n);
+  const MatArg X1{A, lda, 0};
+  // the power slots sit at the start of every candidate's layout
+  const Layout L0 = make_layout(dtype, n, SP.cand.back(), default_s(SP.cand.back()), 1, 0, SP.D - 1);
+  auto power = [&](int j) { return j == 1 ? X1 : ws_mat(wsc, L0.off_pow + (size_t)(j - 2) * L0.slot, n, 0, esize); };
+  // 1. ||A||_1; sigma0 from the largest candidate's theta (the smallest scaling)
+  std::vector<double> theta(SP.cand.size());
+  for (size_t k = 0; k < SP.cand.size(); ++k) theta[k] = theta_taylor(SP.cand[k], u);
+  double nA = 0.0;
+  PS_HIP(launch_norm1(W, n, X1, wg, st));
+  if (ps_status e = read_norm1(wg, n, st, &nA)) return e;
+  if (!std::isfinite(nA)) return fail(PS_ERR_ARG, "input matrix has non-finite entries");
+  const int sigma0 = ceil_log2_ratio(nA, theta.back());
+  if (sigma0 > kMaxSigma) return fail(PS_ERR_ARG, "||A||_1 = %g needs more than %d squarings", nA, kMaxSigma);
+  const double beta0 = ldexp(1.0, -sigma0);
+  // 2. candidates in increasing m; PS cost grows strictly along them, so the
+  //    search stops at the first candidate whose products alone reach the
+  //    best total.  Powers X0^j are formed as far as the examined candidates
+  //    need them (X_j = X_ceil(j/2) X_floor(j/2), grouped), with one norm
+  //    read-back per extension.
+  std::vector<double> nrm(SP.D + 2, 0.0);
+  nrm[1] = beta0 * nA;
+  int built = 1;
+  auto build_to = [&](int need) -> ps_status {
+    if (need <= built) return PS_OK;
+    const int first = built + 1;
+    while (built < need) {
+      const int lo = built + 1, hi = std::min(std::min(need, 2 * built), built + kMaxGroup);
+      GemmGroup g;
+      memset(&g, 0, sizeof g);
+      for (int j = lo; j <= hi; ++j) {
+        const int a = pow_a(j), b = pow_b(j), k = g.count++;
+        g.A[k] = power(a);
+        g.B[k] = power(b);
+        g.C[k] = power(j);
+        g.alpha[k] = (a == 1 ? beta0 : 1.0) * (b == 1 ? beta0 : 1.0);
+      }
+      PS_HIP(launch_gemm_group(W, n, 1, g, st));
+      for (int j = lo; j <= hi; ++j) PS_HIP(launch_norm1(W, n, power(j), wg + (size_t)(j - 1) * G, st));
+      built = hi;
+    }
+    std::vector<double> h((size_t)(need - first + 1) * G);
+    PS_HIP(hipMemcpyAsync(h.data(), wg + (size_t)(first - 1) * G, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+    PS_HIP(hipStreamSynchronize(st));
+    for (int d = first; d <= need; ++d)
+      for (int64_t k = 0; k < G; ++k) {
+        const double v = h[(size_t)(d - first) * G + k];
+        if (v > nrm[d] || v != v) nrm[d] = v;
+      }
+    return PS_OK;
+  };
+  // 3. per candidate: alpha_m(A) = 2^sigma0 alpha_m(X0), the least sigma with
+  //    2^-sigma alpha_m(A) <= theta_m, and the products it costs
+  int best = -1, best_cost = 0, best_sigma = 0;
+  for (size_t k = 0; k < SP.cand.size(); ++k) {
+    const int m = SP.cand[k], d = alpha_dstar(m);
+    if (best >= 0 && ps_cost(m) >= best_cost) break;
+    if (ps_status e = build_to(std::max(default_s(m), d + 1))) return e;
+    const double a0 = std::max(std::pow(nrm[d], 1.0 / d), std::pow(nrm[d + 1], 1.0 / (d + 1)));
+    const int sg = ceil_log2_ratio(ldexp(a0, sigma0), theta[k]);
+    if (sg > kMaxSigma) continue;
+    const int cost = ps_cost(m) + sg;
+    if (best < 0 || cost < best_cost) {
+      best = (int)k;
+      best_cost = cost;
+      best_sigma = sg;
+    }
+  }
+  if (best < 0) return fail(PS_ERR_ARG, "no candidate degree meets the bound within %d squarings", kMaxSigma);
+  const int m = SP.cand[best], s = default_s(m), sigma = best_sigma;
+  // 4. evaluation with the chosen (m, s, sigma) on the power table
+  std::vector<double> c(m + 1);
+  ps_coef_taylor_exp(m, c.data());
+  Layout L = make_layout(dtype, n, m, s, sigma, 0, SP.D - 1);
+  Job J;
+  J.L = &L;
+  J.batch = 1;
+  J.X1 = X1;
+  J.beta = ldexp(1.0, -sigma);
+  J.coef = c.data();
+  J.out = MatArg{E, lde, 0};
+  J.ws = wsc;
+  J.ws_stride = L.bytes;
+  J.opts = o;
+  J.write_y = true;
+  J.build_powers = false;
+  J.skip_square = false;
+  J.pow_shift = sigma0 - sigma;   // X^j = 2^(j (sigma0 - sigma)) X0^j, exact (either sign)
+  float ms[4] = {0, 0, 0, 0};
+  if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
+  if (chosen) {
+    chosen[0] = m;
+    chosen[1] = s;
+    chosen[2] = sigma;
+  }
   if (report)
     if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
   return PS_OK;

@@ -94,3 +94,38 @@ def test_auto_rejects_nonfinite(ps):
     A[3, 2] = np.inf
     with pytest.raises(ps.PSError):
         ps.ps_expm_auto(to_dev(A), M, s=S)
+
+
+# --------------------------------------------------------------------------
+# joint choice of the degree and the scaling (ps_expm_select)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["fixed", "mixed"])
+@pytest.mark.parametrize("name,A", _cases(), ids=[c[0] for c in _cases()])
+def test_select_matches_oracle_and_accuracy(ps, name, A, mode):
+    u = 2.0 ** -53
+    m_o, s_o, sig_o = metrics.select_degree(A.T, 42, u)
+    E, (m, s, sig) = ps.ps_expm_select(to_dev(A), 42, mode=mode)
+    assert (m, s, sig) == (m_o, s_o, sig_o), name
+    Eh, El = oracle.expm_dd(A, coeffs.taylor_exp(m), sig)
+    assert metrics.rel_err_1(to_np(E), Eh, El) <= TOL64, (name, m, sig)
+
+
+def test_select_nilpotent_is_exact(ps):
+    A = np.zeros((70, 70))
+    A[np.arange(0, 70, 2), np.arange(1, 70, 2)] = 3.0          # A^2 = 0: e^A = I + A
+    E, ch = ps.ps_expm_select(to_dev(A), 42)
+    assert ch == (1, 1, 0)
+    assert np.array_equal(to_np(E), np.eye(70) + A)
+
+
+def test_select_fp32_and_doubling(ps):
+    import torch
+    A = _dense(96, 20.0, 12).astype(np.float32).astype(np.float64)
+    u = 2.0 ** -24
+    E, ch = ps.ps_expm_select(to_dev(A, torch.float32), 42, mode="mixed")
+    assert ch == metrics.select_degree(A.T, 42, u)
+    Eh, El = oracle.expm_dd(A, coeffs.taylor_exp(ch[0]), ch[2])
+    assert metrics.rel_err_1(to_np(E).astype(np.float64), Eh, El) <= 2.0 ** ch[2] * 8 * 96 * u
+    # every candidate needs scaling here, so doubling A adds one squaring
+    _, ch2 = ps.ps_expm_select(to_dev(2 * A, torch.float32), 42, mode="mixed")
+    assert ch2 == (ch[0], ch[1], ch[2] + 1)

@@ -467,3 +467,63 @@ def test_variable_s_special_cases():
     assert metrics.variable_s(-0.5 * np.eye(3), coeffs.taylor_exp(4)) == 4
     assert metrics.variable_s(-0.5 * np.eye(3), coeffs.taylor_exp(2)) == 2
     assert metrics.variable_s(-0.5 * np.eye(3), coeffs.taylor_exp(1)) == 1
+
+
+# --------------------------------------------------------------------------
+# joint choice of the Taylor degree and the scaling (section 3.2)
+# --------------------------------------------------------------------------
+def _alpha_brute(A, m):
+    """alpha_m from eq. (alpha_m-X) with d* found by enumeration and powers
+    by numpy.linalg.matrix_power"""
+    d = max(k for k in range(1, m + 3) if k * (k - 1) <= m + 1)
+    return max(metrics.norm1(np.linalg.matrix_power(A, d)) ** (1.0 / d),
+               metrics.norm1(np.linalg.matrix_power(A, d + 1)) ** (1.0 / (d + 1)))
+
+
+def _cost_brute(m):
+    s = math.isqrt(m - 1) + 1 if m > 1 else 1          # ceil(sqrt(m))
+    r = m // s
+    return (s - 1) + r - (1 if m == s * r else 0)
+
+
+def test_select_degree_zero_and_nilpotent():
+    u = 2.0 ** -53
+    # alpha_m = 0: no scaling, and the cheapest candidate m = 1 (p_1(X) = I + X,
+    # which is e^A exactly when A^2 = 0)
+    assert metrics.select_degree(np.zeros((4, 4)), 42, u) == (1, 1, 0)
+    assert metrics.select_degree(np.array([[0.0, 5.0], [0.0, 0.0]]), 42, u) == (1, 1, 0)
+
+
+@pytest.mark.parametrize("t,seed", [(0.01, 1), (0.3, 2), (1.0, 3), (8.0, 4), (64.0, 5), (1e3, 6)])
+def test_select_degree_is_the_cheapest_admissible_choice(t, seed):
+    u = 2.0 ** -53
+    G = np.random.default_rng(seed).standard_normal((12, 12))
+    A = G * (t / metrics.norm1(G))
+    m, s, sig = metrics.select_degree(A, 42, u)
+    assert s == (math.isqrt(m - 1) + 1 if m > 1 else 1)
+    # the bound holds at the chosen pair
+    assert math.ldexp(_alpha_brute(A, m), -sig) <= metrics.theta_taylor(m, u) * (1 + 1e-12)
+    # no candidate is cheaper at its own least admissible scaling
+    best = _cost_brute(m) + sig
+    for q in range(1, 7):
+        for mc in (q * q, q * (q + 1)):
+            if mc > 42:
+                continue
+            a = _alpha_brute(A, mc)
+            th = metrics.theta_taylor(mc, u)
+            sc = 0
+            while math.ldexp(a, -sc) > th * (1 + 1e-12):
+                sc += 1
+            assert _cost_brute(mc) + sc >= best, (mc, sc, m, sig)
+            if _cost_brute(mc) + sc == best:
+                assert mc >= m                      # ties go to the smaller degree
+
+
+def test_select_degree_scales_by_one_squaring():
+    # once every candidate needs scaling, doubling A adds exactly one squaring
+    u = 2.0 ** -53
+    G = np.random.default_rng(9).standard_normal((10, 10))
+    A = G * (20.0 / metrics.norm1(G))
+    m, s, sig = metrics.select_degree(A, 42, u)
+    assert sig >= 1
+    assert metrics.select_degree(2 * A, 42, u) == (m, s, sig + 1)
