@@ -323,6 +323,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.outw = final_out ? (square ? (W*)(ws + L.off_R) : (W*)it.E) : (W*)h.pout;
   h.ldo = final_out ? (square ? n : it.lde) : n;
   h.nv = (final_out && !square) ? it.nv : n;
+  h.nvb = it.nv;
   horner_tile<W>(h, (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, smem);
 }
 

@@ -539,6 +539,8 @@ struct HornerTile {
   W* outw;                  // working-precision output (t_out = working tier)
   int64_t ldo;
   int64_t nv;               // rows and columns < nv of outw are written (nv <= n)
+  int64_t nvb;              // order of the matrix inside the padded n: B_{i-1} is read
+                            // for rows and columns < nvb only (zero beyond)
 };
 
 template <typename W>
@@ -575,7 +577,7 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
 #pragma unroll
   for (int q = 0; q < TILE_Q; ++q) {
     const int64_t gc = n0 + (t >> 6) + NW * q;
-    const bool in = gr < n && gc < n;
+    const bool in = gr < h.nvb && gc < h.nvb;
     const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
     bq[q] = in ? x : W(0);
   }
@@ -634,23 +636,30 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
   const int64_t r_begin = chunk * kRowChunk;
   const int64_t r_end = min<int64_t>(n, r_begin + kRowChunk);
   const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
+  // valid: rows of this chunk (the Y copies cover the padded order n);
+  // inner: rows and column inside the matrix's own order nv.  Outside it the
+  // powers are zero, so nothing there is loaded, and the blocks are neither
+  // formed nor stored there (their readers mask at nv).
+  const bool colv = col < a.nv;
   int64_t rw[RPL];
-  bool valid[RPL];
+  bool valid[RPL], inner[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     rw[q] = r_begin + lane + 64 * q;
     valid[q] = rw[q] < r_end;
+    inner[q] = colv && rw[q] < r_end && rw[q] < a.nv;
   }
   // this lane's elements of column `col` of X_j; the loads are unconditional
-  // (rows past the end read row r_begin) so that all of them are in flight
-  // together
+  // (rows outside read row r_begin of a column inside) so that all of them are
+  // in flight together
+  const int64_t cl = colv ? col : 0;
   auto load_x = [&](int j, W out[RPL]) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-      const int64_t rr = valid[q] ? rw[q] : r_begin;
-      const W x = (j == 1) ? (W)(x1s * (double)X1[rr + col * a.X1.ld])
-                           : (W)ldexp((double)pw[(int64_t)(j - 2) * se + rr + col * n], j * a.pow_shift);
-      out[q] = valid[q] ? x : W(0);
+      const int64_t rr = inner[q] ? rw[q] : r_begin;
+      const W x = (j == 1) ? (W)(x1s * (double)X1[rr + cl * a.X1.ld])
+                           : (W)ldexp((double)pw[(int64_t)(j - 2) * se + rr + cl * n], j * a.pow_shift);
+      out[q] = inner[q] ? x : W(0);
     }
   };
   W y[RPL];
@@ -694,7 +703,7 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
       for (int q = 0; q < RPL; ++q) bv[q][ii] = (rw[q] == col && col < a.nv) ? c0 : W(0);
     }
 #pragma unroll 2
-    for (int j = 1; j < s; ++j) {
+    for (int j = 1; j < (colv ? s : 1); ++j) {
       W xj[RPL];
       load_x(j, xj);
       if (j == 1 && i0 == 0)
@@ -717,7 +726,7 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
       double v = 0.0;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
-        if (!valid[q]) continue;
+        if (!inner[q]) continue;
         v += fabs((double)bv[q][ii]);
         W outv = bv[q][ii];
         if (a.trivial_last && i == r - 1) outv += (W)cf.c[m] * y[q];   // step r: c_m I * Y

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.outw = a.final_out ? ((W*)a.out.p + b * a.out.stride) : (W*)(ws + a.off_pout);
   h.ldo = a.final_out ? a.out.ld : a.n;
   h.nv = a.n;
+  h.nvb = a.n;
   horner_tile<W>(h, (int64_t)tm * kTileM, (int64_t)tn * kTileN, smem);
 }
 
