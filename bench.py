@@ -45,10 +45,12 @@ TIER_BYTES = {0: 8.0, 1: 4.0, 2: 2.0, 3: 1.0 + 1.0 / 32}   # per element, FP8 wi
 
 def step_ideal_s(rep, sigma, mixed):
     """Ideal time of one evaluation at nominal peaks: sum over its steps of
-    max(flops / peak(tier), algorithmic bytes / HBM bandwidth)."""
+    max(flops / peak(tier), algorithmic bytes / HBM bandwidth); and the
+    MFMA-only part, sum of flops / peak(tier)."""
     n2, F = float(N) * N, 2.0 * N ** 3
     gemm64 = max(F / TIER_PEAK[0], 3 * 8 * n2 / HBM_BW)
     t = (S - 1) * gemm64 + sigma * gemm64                                    # powers, squarings
+    mf = (S - 1 + sigma) * F / TIER_PEAK[0]
     copies = sum(TIER_BYTES[k] for k in (1, 2, 3)) if mixed else 0.0
     fs = rep["first_step"]
     t += (S * 8 + (fs + 1) * 8 + copies) * n2 / HBM_BW                           # block assembly
@@ -58,7 +60,8 @@ def step_ideal_s(rep, sigma, mixed):
         ti, to = tiers[i], tiers[i - 1]
         byts = (2 * TIER_BYTES[ti] + 8 + TIER_BYTES[to]) * n2                   # P_i, Y, B_{i-1}, P_{i-1}
         t += max(F / TIER_PEAK[ti], byts / HBM_BW)
-    return t
+        mf += F / TIER_PEAK[ti]
+    return t, mf
 
 
 EXTRAS = ("latency", "batched", "pade_cos", "grad", "auto", "select", "vars", "dd")
@@ -172,24 +175,42 @@ def main():
             torch.cuda.synchronize()
         return g
 
-    def run_timed(fn):
+    def run_timed(fn, per_step=None):
+        """wall-clock mean over K steps; per_step (a list) also receives each
+        step's duration from a pair of events on the current stream"""
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)] if per_step is not None else None
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for k in range(args.steps):
+            if evs:
+                evs[k][0].record()
             fn()
+            if evs:
+                evs[k][1].record()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / args.steps
+        t = (time.perf_counter() - t0) / args.steps
+        if evs:
+            per_step.extend(a.elapsed_time(b) for a, b in evs)
+        return t
 
     eager = {}
+    step_ms = {}
 
     def timed(mode):
         eager[mode] = run_timed(lambda: step(mode))
         g = capture(mode)
-        t = run_timed(g.replay)
+        step_ms[mode] = []
+        t = run_timed(g.replay, step_ms[mode])
         del g
         return t
+
+    def stats(v):
+        v = sorted(v)
+        q = lambda f: v[min(len(v) - 1, int(round(f * (len(v) - 1))))]
+        return {"median": round(q(0.5), 4), "p10": round(q(0.1), 4), "p90": round(q(0.9), 4)}
 
     if args.calib_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -208,11 +229,14 @@ def main():
     plans = []
     errs = []
     ideal = {"plain": 0.0, "mixed": 0.0}
+    mfma_only = {"plain": 0.0, "mixed": 0.0}
     for a, sg in zip(mats, sigmas):
         em, rp = ps.ps_expm(a, M, s=S, sigma=sg, mode="mixed", report=True)
         ef, rf = ps.ps_expm(a, M, s=S, sigma=sg, mode="fixed", report=True)
-        ideal["mixed"] += step_ideal_s(rp, sg, True)
-        ideal["plain"] += step_ideal_s(rf, sg, False)
+        for mode, rr, mixed in (("mixed", rp, True), ("plain", rf, False)):
+            ti, tm = step_ideal_s(rr, sg, mixed)
+            ideal[mode] += ti
+            mfma_only[mode] += tm
         plans.append([ps.TIER_NAMES[t] for t in rp["tier"][1:rp["first_step"] + 1]])
         d = torch.linalg.matrix_norm(em - ef, ord=1).item() / torch.linalg.matrix_norm(ef, ord=1).item()
         errs.append(d)
@@ -255,7 +279,9 @@ def main():
         "rel_diff_mixed_vs_plain": [float("%.3e" % e) for e in errs],
         "roofline": roofline,
         "step_roofline": {mode: {"ideal_ms": round(ideal[mode] * 1e3, 4), "measured_ms": round(res[mode] * 1e3, 4),
-                                 "frac": round(ideal[mode] / res[mode], 4)} for mode in res},
+                                 "frac": round(ideal[mode] / res[mode], 4),
+                                 "mfma_only_frac": round(mfma_only[mode] / res[mode], 4)} for mode in res},
+        "step_ms_events": {("plain" if k == "fixed" else k): stats(v) for k, v in step_ms.items()},
     }
     out["schedule"] = ("one hipGraph per step: the four evaluations forked over four streams "
                        "(default priority) and joined; replays checked bitwise against eager calls")
@@ -278,6 +304,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(mats, outs_mixed=[ps.ps_expm(a, M, s=S, sigma=sg, mode="mixed")
                                                              for a, sg in zip(mats, sigmas)],
                                            norms=norms, sigmas=sigmas)
+        worst = max(out["cpu_baseline"]["gpu_mixed_rel_err_vs_dd_oracle_sampled_cols"])
+        out["accuracy_gate"] = {"tol": 1e-13, "max_rel_err_vs_dd_oracle": worst, "ok": worst <= 1e-13,
+                                "note": "mixed results, sampled columns, 1-norm relative error"}
     print(json.dumps(out))
 
 
@@ -471,9 +500,17 @@ def cpu_baseline(mats, outs_mixed, norms, sigmas):
         got = e.cpu().numpy()[:, cols]
         d = (got - wh) - wl
         errs.append(float(np.max(np.sum(np.abs(d), 0)) / np.max(np.sum(np.abs(wh), 0))))
+    # one core: the sigma = 0 matrix alone
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.expm_ps_f64(A_np[1], c, S, sigmas[1])
+    d1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return {"value": round(len(A_np) / dt, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": "one evaluation of each of the 4 dense n=1024 matrices by the oracle's FP64 "
                       "Algorithm 1 + squarings (%.1f s)" % dt,
+            "single_core": {"value": round(1.0 / d1, 4), "unit": "evals/s",
+                            "sample": "the ||A||_1 = 1 matrix (sigma = 0) once on one thread (%.1f s)" % d1},
             "gpu_mixed_rel_err_vs_dd_oracle_sampled_cols": [float("%.3e" % e) for e in errs]}
 
 
