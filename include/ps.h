@@ -304,10 +304,13 @@ ps_status ps_expm_strided_batched(ps_dtype dtype, int batch, int64_t n,
  * lda[b], and its result goes to E[b] (lde[b]).  Per-matrix block size s[b]
  * (0 = chosen per matrix from {floor(sqrt m), ceil(sqrt m)} by the lower
  * modelled cost) and scaling sigma[b].  Host arrays of `batch` entries.
- * Every matrix is planned on the device (mixed mode) without a host round
- * trip, so the whole call can be captured in a hipGraph.
- * tiers_out: NULL or host array of batch*PS_MAX_BLOCKS ints receiving each
- * matrix's tier vector (synchronises the stream).
+ * Every matrix's block size and plan are chosen on the device (mixed mode),
+ * with no host round trip between the phases.  The call uploads its work
+ * descriptors into the workspace first and synchronises the stream once for
+ * that, so it cannot itself be captured; ps_batched_prepare below does the
+ * upload once and captures the launch sequence, whose replays need no host
+ * work.  tiers_out: NULL or host array of batch*PS_MAX_BLOCKS ints receiving
+ * each matrix's tier vector (synchronises the stream again).
  * ------------------------------------------------------------------------- */
 ps_status ps_workspace_size_batched(ps_dtype dtype, int batch, const int32_t* n, int m,
                                     const int32_t* s, size_t* bytes);
