@@ -50,7 +50,10 @@ static_assert(kTileM == 64 && (kTileN == 64 || kTileN == 32), "tile shape");
 static_assert(RUNA % 2 == 0 && RUNB % 2 == 0 && TPA * RUNA == kTileM && TPB * RUNB == kTileN, "slab split");
 
 // Wave layout of an output tile: wave w owns rows [32 (w & 1), +32) and
-// columns [16 (w >> 1), +16) as two 16x16 MFMA blocks stacked in M.
+// columns [16 (w >> 1), +16) as two 16x16 MFMA blocks interleaved in M:
+// block bi holds the rows wr + 2 r + bi (r = 0..15), so the two A values a
+// lane feeds to the pair of MFMAs of one k-step are adjacent in LDS and come
+// in one 2-element read.
 __device__ inline int wave_row0() { return ((threadIdx.x >> 6) & 1) * 32; }
 __device__ inline int wave_col0() { return (threadIdx.x >> 7) * 16; }
 
@@ -167,14 +170,15 @@ __device__ inline void store_b(T* Bs, int t, const T r[RUNB]) {
 template <typename T>
 __device__ __forceinline__ void mma_slab(const T* as, const T* bs, int wr, int wc, int g, int c,
                                 typename MF<T>::V acc[2 * KCH]) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int ks = 0; ks < BKL / 4; ++ks) {
     const int k = ks * 4 + g;
     const int ch = (ks % KCH) * 2;
-    const T a0 = as[k * LROWA + wr + c], a1 = as[k * LROWA + wr + 16 + c];
+    const v2 a01 = *(const v2*)(as + k * LROWA + wr + 2 * c);   // rows wr + 2c (block 0), wr + 2c + 1 (block 1)
     const T b0 = bs[k * LROWB + wc + c];
-    acc[ch] = MF<T>::mma(a0, b0, acc[ch]);
-    acc[ch + 1] = MF<T>::mma(a1, b0, acc[ch + 1]);
+    acc[ch] = MF<T>::mma(a01[0], b0, acc[ch]);
+    acc[ch + 1] = MF<T>::mma(a01[1], b0, acc[ch + 1]);
   }
 }
 
@@ -261,7 +265,7 @@ __device__ __forceinline__ void frag_to_cs(const typename MF<T>::V acc[2], W* Cs
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = wr + 16 * bi + MF<T>::row(v, g);
+      const int row = wr + 2 * MF<T>::row(v, g) + bi;
       const int col = wc + c;
       Cs[col * CSTR + row] = (W)((double)acc[bi][v] * scale);
     }
