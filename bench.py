@@ -79,6 +79,9 @@ def parse():
                     help="skip the secondary workloads (batched, Pade/cos, adjoint)")
     ap.add_argument("--extra", default=",".join(EXTRAS),
                     help="comma-separated subset of the secondary workloads: " + ",".join(EXTRAS))
+    ap.add_argument("--schedule", choices=["graph", "sequential"], default="graph",
+                    help="graph: the step's four evaluations forked over four streams in one replayed hipGraph; "
+                         "sequential: eager calls on one stream (kernels never overlap; used for kernel traces)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run three 256 MiB device-to-device copies (known traffic, for counter scaling)")
     return ap.parse_args()
@@ -200,9 +203,12 @@ def main():
     step_ms = {}
 
     def timed(mode):
+        step_ms[mode] = []
+        if args.schedule == "sequential":
+            eager[mode] = run_timed(lambda: step(mode), step_ms[mode])
+            return eager[mode]
         eager[mode] = run_timed(lambda: step(mode))
         g = capture(mode)
-        step_ms[mode] = []
         t = run_timed(g.replay, step_ms[mode])
         del g
         return t
@@ -284,7 +290,8 @@ def main():
         "step_ms_events": {("plain" if k == "fixed" else k): stats(v) for k, v in step_ms.items()},
     }
     out["schedule"] = ("one hipGraph per step: the four evaluations forked over four streams "
-                       "(default priority) and joined; replays checked bitwise against eager calls")
+                       "(default priority) and joined; replays checked bitwise against eager calls"
+                       if args.schedule == "graph" else "eager sequential calls on one stream")
     out["eager_sequential"] = {("plain" if mode == "fixed" else mode): {"ms_per_step": round(t * 1e3, 4),
                                                                         "evals_per_s": round(len(mats) / t, 2)}
                                for mode, t in eager.items()}
