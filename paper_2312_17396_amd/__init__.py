@@ -153,7 +153,7 @@ def _opts(mode="fixed", tier_mask=0, delta=10.0, tier_override=None, profile=Fal
     o = ps_opts()
     o.mode = MODE_MIXED if mode in ("mixed", MODE_MIXED) else MODE_FIXED
     if rule not in RULES:
-        raise PSError(-1, "rule must be one of %s" % sorted(RULES))
+        raise PSError("rule must be one of %s" % sorted(RULES))
     o.rule = RULES[rule]
     o.tier_mask = int(tier_mask)
     o.delta = float(delta)
@@ -364,7 +364,7 @@ def vars_workspace(A, m, sigma=0):
 
 def _check_out(E, A):
     if E.shape != A.shape or E.dtype != A.dtype or E.device != A.device or not E.is_contiguous():
-        raise PSError(-1, "out must be a contiguous tensor of A's shape, dtype and device")
+        raise PSError("out must be a contiguous tensor of A's shape, dtype and device")
     return E
 
 
@@ -383,7 +383,7 @@ def ps_expm_dd(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=1
     sequences.  Returns the (2, n, n) result (and the report)."""
     import torch
     if A.dim() != 3 or A.shape[0] != 2 or A.shape[1] != A.shape[2] or A.dtype != torch.float64:
-        raise PSError(-1, "A must be a float64 tensor of shape (2, n, n)")
+        raise PSError("A must be a float64 tensor of shape (2, n, n)")
     A = A.contiguous()
     n = A.shape[1]
     if workspace is None:
