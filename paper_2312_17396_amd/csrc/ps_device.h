@@ -32,15 +32,9 @@ constexpr int LROWB = kTileN + 16;    //   k and k+1 in one half-wave pass; 640 
                                       //   two rows land on disjoint banks
 constexpr int KCH = PS_KCHAINS;       // independent accumulator chains per MFMA block (k-step parity)
 constexpr int CSTR = kTileM + 1;      // epilogue tile column stride (elements)
-// B slab in LDS: k-contiguous per column (j-major), row stride LKB elements.
-// 34 doubles (272 B) or 36 floats (144 B): the 16-byte stores of a wave and the
-// 8- or 16-byte fragment reads of 32 lanes then fall on distinct banks.
-template <typename T>
-constexpr int lkb() { return sizeof(T) == 8 ? BKL + 2 : BKL + 4; }
 constexpr int SLABA = BKL * LROWA;    // elements of the A slab of one stage
 constexpr int SLABB = BKL * LROWB;    // elements of the B slab of one stage
 constexpr int STAGE = SLABA + SLABB;
-static_assert(kTileN * lkb<double>() <= SLABB && kTileN * lkb<float>() <= SLABB, "B slab fits its stage share");
 // LDS of one tile workgroup with working type W: two FP64/FP32 slab stages
 // (80 KiB for FP64, 40 KiB for FP32, so up to four FP32 workgroups share a
 // compute unit); the low-precision stages and the epilogue tile fit in it
@@ -162,45 +156,29 @@ __device__ inline void load_b(const T* __restrict__ B, int64_t ldb, int64_t n, i
 }
 template <typename T, bool TB>
 __device__ inline void store_b(T* Bs, int t, const T r[RUNB]) {
-  constexpr int LK = lkb<T>();
-  if (!TB) {   // a run of RUNB consecutive k of one column: 16-byte stores
-    typedef T v4 __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int V = 16 / sizeof(T);
+  if (!TB) {
     const int jj = t % kTileN, kk = (t / kTileN) * RUNB;
 #pragma unroll
-    for (int i = 0; i < RUNB; i += V) {
-      v4 x;
-#pragma unroll
-      for (int e = 0; e < V; ++e) x[e] = r[i + e];
-      *(v4*)(Bs + jj * LK + kk + i) = x;
-    }
+    for (int i = 0; i < RUNB; ++i) Bs[(kk + i) * LROWB + jj] = r[i];
   } else {
     const int kk = t / TPB, jj = (t % TPB) * RUNB;
 #pragma unroll
-    for (int i = 0; i < RUNB; ++i) Bs[(jj + i) * LK + kk] = r[i];
+    for (int i = 0; i < RUNB; ++i) Bs[kk * LROWB + jj + i] = r[i];
   }
 }
 
 template <typename T>
 __device__ __forceinline__ void mma_slab(const T* as, const T* bs, int wr, int wc, int g, int c,
                                 typename MF<T>::V acc[2 * KCH]) {
-  // K is visited in pairs: in MFMA steps 2p and 2p + 1 lane group g feeds
-  // k = 8p + 2g and 8p + 2g + 1 (every k of the slab exactly once), so its two
-  // B values are adjacent in the k-contiguous B slab and come in one read.
   typedef T v2 __attribute__((ext_vector_type(2)));
-  constexpr int LK = lkb<T>();
 #pragma unroll
-  for (int p = 0; p < BKL / 8; ++p) {
-    const int k0 = 8 * p + 2 * g;
-    const v2 b01 = *(const v2*)(bs + (wc + c) * LK + k0);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int ks = 2 * p + h;
-      const int ch = (ks % KCH) * 2;
-      const v2 a01 = *(const v2*)(as + (k0 + h) * LROWA + wr + 2 * c);   // rows wr + 2c, wr + 2c + 1
-      acc[ch] = MF<T>::mma(a01[0], b01[h], acc[ch]);
-      acc[ch + 1] = MF<T>::mma(a01[1], b01[h], acc[ch + 1]);
-    }
+  for (int ks = 0; ks < BKL / 4; ++ks) {
+    const int k = ks * 4 + g;
+    const int ch = (ks % KCH) * 2;
+    const v2 a01 = *(const v2*)(as + k * LROWA + wr + 2 * c);   // rows wr + 2c (block 0), wr + 2c + 1 (block 1)
+    const T b0 = bs[k * LROWB + wc + c];
+    acc[ch] = MF<T>::mma(a01[0], b0, acc[ch]);
+    acc[ch + 1] = MF<T>::mma(a01[1], b0, acc[ch + 1]);
   }
 }
 
