@@ -64,7 +64,7 @@ def step_ideal_s(rep, sigma, mixed):
     return t, mf
 
 
-EXTRAS = ("latency", "batched", "pade_cos", "grad", "auto", "select", "vars", "dd")
+EXTRAS = ("latency", "sizes", "batched", "pade_cos", "grad", "auto", "select", "vars", "dd")
 
 
 def parse():
@@ -333,6 +333,9 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
               scaling: microseconds per evaluation, as a stream of ps_expm
               calls and as one replayed hipGraph (the batched path with one
               matrix);
+    sizes     one N(0,1) matrix with ||A||_1 = 1 (m = 30, s = 6, no scaling) at
+              n = 512, 2048, 4096: mixed vs plain ms per evaluation and the FP64
+              GEMM tile kernel's TFLOP/s (library profile mode, hipEvents);
     batched   4096 matrices, n uniform in {8..256}, ||A||_1 ~ U[0.05, 4], Taylor
               m = 18, s chosen per matrix, FP32: one persistent launch replayed
               from a hipGraph vs a loop of single-matrix calls;
@@ -365,6 +368,28 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
             out[mode] = {"us_per_eval_calls": round(tc * 1e6, 2), "us_per_eval_graph": round(tg * 1e6, 2)}
         res["latency_single_64"] = out
         del A1, E1, ws1
+    # ---- other orders
+    if "sizes" in which:
+        out = {}
+        for n in (512, 2048, 4096):
+            An = torch.tensor(inputs.dense_1024(1.0, n=n), device=dev)
+            En = torch.empty_like(An)
+            wsn = ps.expm_workspace(An, M, S, 0)
+            row = {}
+            for mode in ("fixed", "mixed"):
+                tt = _time(lambda: ps.ps_expm(An, M, s=S, mode=mode, out=En, workspace=wsn), 5, torch)
+                row["plain" if mode == "fixed" else mode] = {"ms": round(tt * 1e3, 3)}
+            gm = 0.0
+            for _ in range(3):
+                _, rp = ps.ps_expm(An, M, s=S, mode="mixed", out=En, workspace=wsn, profile=True)
+                gm += rp["ms"]["power"] / 3
+            tf = (S - 1) * 2.0 * n ** 3 / (gm * 1e-3) / 1e12
+            row["speedup_mixed_vs_plain"] = round(row["plain"]["ms"] / row["mixed"]["ms"], 3)
+            row["gemm_f64_tflops"] = round(tf, 2)
+            row["gemm_f64_frac"] = round(tf / PEAK_FP64_MFMA, 4)
+            out["n%d" % n] = row
+            del An, En, wsn
+        res["sizes_taylor_exp"] = out
     # ---- batched
     if "batched" in which:
         mats, ts = inputs.batch_uneven()
