@@ -553,38 +553,49 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
   const int64_t n = h.n, Kp = h.Kp;
   const int t_in = h.t_in, t_out = h.t_out;
   W* Cs = (W*)smem;
+  const int t = threadIdx.x;
+  const int row = t & 63;
+  const int64_t gr = m0 + row;
+  // this thread's elements of B_{i-1}, all loads in flight together: issued
+  // before the main loop for the low-precision products (short loops with
+  // free registers), after it for the FP64 / FP32 ones
+  W bq[TILE_Q];
+  auto load_b = [&]() {
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) {
+      const int64_t gc = n0 + (t >> 6) + NW * q;
+      const bool in = gr < h.nvb && gc < h.nvb;
+      const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
+      bq[q] = in ? x : W(0);
+    }
+  };
   if (t_in == WT) {
     typename MF<W>::V acc[2];
     mainloop_lds<W, false, false>((const W*)h.pin, n, h.ysrc, h.ldy, n, m0, n0, smem, acc);
     frag_to_cs<W, W>(acc, Cs, h.yscale);
+    load_b();
   } else if (t_in == 1) {   // FP32 product below an FP64 working precision
     typename MF<float>::V acc[2];
     mainloop_lds<float, false, false>((const float*)h.pin, n, h.yf32, n, n, m0, n0, smem, acc);
     frag_to_cs<float, W>(acc, Cs, 1.0);
+    load_b();
   } else if (t_in == 2) {
+    load_b();
     f4v acc[2];
     mainloop_lowp<false>((const uint8_t*)h.pin, nullptr, (const uint8_t*)h.ybf16, nullptr, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else if (t_in == 3) {
+    load_b();
     f4v acc[2];
     const uint8_t* p8 = (const uint8_t*)h.pin;
     mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
+  } else {
+    load_b();   // cast only
   }
   __syncthreads();
 
   // pass 1 (column-major, coalesced): add B_{i-1} in the precision of t_out
-  const int t = threadIdx.x;
-  const int row = t & 63;
-  const int64_t gr = m0 + row;
-  W bq[TILE_Q];   // all loads of B_{i-1} issued before any store
-#pragma unroll
-  for (int q = 0; q < TILE_Q; ++q) {
-    const int64_t gc = n0 + (t >> 6) + NW * q;
-    const bool in = gr < h.nvb && gc < h.nvb;
-    const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
-    bq[q] = in ? x : W(0);
-  }
 #pragma unroll
   for (int q = 0; q < TILE_Q; ++q) {
     const int col = (t >> 6) + NW * q;
