@@ -224,7 +224,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ---- blocks, norms, low-precision copies of Y: one wave per column
 template <typename W>
-__global__ __launch_bounds__(NT) void k_bassemble(BatchArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bassemble(BatchArgs a) {
   const int task = a.col_tasks[blockIdx.x];
   const int b = task >> 8, grp = task & 255;
   const BatchRes& it = a.res[b];
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(NT) void k_bassemble(BatchArgs a) {
   aa.ws_stride = 0;
   aa.L = L;
   aa.tier_mask = a.mode == PS_MODE_MIXED ? a.mask : 0u;
-  assemble_column<W>(aa, a.cf, aa.ws, (const W*)it.X1, col, 0);
+  assemble_column<W, false>(aa, a.cf, aa.ws, (const W*)it.X1, col, 0);
 }
 
 // ---- precision plan: one workgroup per matrix

@@ -624,7 +624,11 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
 // last step (B_r = c_m I), partial column abs sums of B_i and Y, and the
 // low-precision copies of Y.  No workgroup barrier inside.
 // ---------------------------------------------------------------------------
-template <typename W>
+// GATHER: for block sizes up to 8, load every power of the column before the
+// first use (one memory round trip per wave; the grid kernel over large
+// matrices).  Otherwise the powers are read one after another (the batched
+// kernel, whose many short waves run faster with the smaller code).
+template <typename W, bool GATHER>
 __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coefs& cf, char* ws, const W* X1, int64_t col,
                                        int64_t chunk) {
   const Layout& L = a.L;
@@ -664,91 +668,156 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
     valid[q] = rw[q] < r_end;
     inner[q] = colv && rw[q] < r_end && rw[q] < a.nv;
   }
-  // this lane's elements of column `col` of X_j; the loads are unconditional
-  // (rows outside read row r_begin of a column inside) so that all of them are
-  // in flight together
+  // this lane's elements of column `col` of X_j, in two phases so that the
+  // loads of several powers can all be in flight before the first use:
+  // load_raw issues the loads (lanes past the end read row r_begin of a
+  // column inside; 64-row groups that hold no row of the matrix are skipped
+  // by a wave-uniform test), finish_x scales and masks the values.
   const int64_t cl = colv ? col : 0;
-  auto load_x = [&](int j, W out[RPL]) {
+  const int rlim = __builtin_amdgcn_readfirstlane((int)(colv ? min<int64_t>(r_end, a.nv) : r_begin));
+  auto load_raw = [&](int j, W out[RPL]) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
-      const int64_t rr = inner[q] ? rw[q] : r_begin;
-      const W x = (j == 1) ? (W)(x1s * (double)X1[rr + cl * a.X1.ld])
-                           : (W)ldexp((double)pw[(int64_t)(j - 2) * se + rr + cl * n], j * a.pow_shift);
-      out[q] = inner[q] ? x : W(0);
-    }
-  };
-  W y[RPL];
-  load_x(s, y);
-  // Y statistics and low-precision copies
-  double ysum = 0.0;
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    ysum += fabs((double)y[q]);
-    if (valid[q] && want32) yf32[rw[q] + col * n] = (float)y[q];
-    if (valid[q] && want16) ybf[col * Kp + rw[q]] = bf16_bits_rne((float)y[q]);
-    if (want8) {
-      // E8M0 block = 32 consecutive rows = one half-wave
-      float av = fabsf((float)y[q]);
-#pragma unroll
-      for (int off = 16; off >= 1; off >>= 1) av = fmaxf(av, __shfl_xor(av, off, 64));
-      const int sbyte = e8m0_for(av);
-      if (valid[q]) {
-        float qv = ldexpf((float)y[q], -(sbyte - 127));
-        qv = fminf(fmaxf(qv, -448.0f), 448.0f);
-        const int wv = __builtin_amdgcn_cvt_pk_fp8_f32(qv, 0.0f, 0, false);
-        y8[col * Kp + rw[q]] = (uint8_t)(wv & 0xff);
-        if ((rw[q] & 31) == 0) y8s[col * Ks + rw[q] / 32] = (uint8_t)sbyte;
+      out[q] = W(0);
+      if (!GATHER || r_begin + 64 * q < rlim) {
+        const int64_t rr = inner[q] ? rw[q] : r_begin;
+        out[q] = (j == 1) ? X1[rr + cl * a.X1.ld] : pw[(int64_t)(j - 2) * se + rr + cl * n];
       }
     }
-  }
+  };
+  auto finish_x = [&](int j, W v[RPL]) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const W x = (j == 1) ? (W)(x1s * (double)v[q]) : (W)ldexp((double)v[q], j * a.pow_shift);
+      v[q] = inner[q] ? x : W(0);
+    }
+  };
+  auto load_x = [&](int j, W out[RPL]) {
+    load_raw(j, out);
+    finish_x(j, out);
+  };
+  // Y statistics and low-precision copies
+  double ysum = 0.0;
+  auto y_copies = [&](const W y[RPL]) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      ysum += fabs((double)y[q]);
+      if (valid[q] && want32) yf32[rw[q] + col * n] = (float)y[q];
+      if (valid[q] && want16) ybf[col * Kp + rw[q]] = bf16_bits_rne((float)y[q]);
+      if (want8) {
+        // E8M0 block = 32 consecutive rows = one half-wave
+        float av = fabsf((float)y[q]);
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) av = fmaxf(av, __shfl_xor(av, off, 64));
+        const int sbyte = e8m0_for(av);
+        if (valid[q]) {
+          float qv = ldexpf((float)y[q], -(sbyte - 127));
+          qv = fminf(fmaxf(qv, -448.0f), 448.0f);
+          const int wv = __builtin_amdgcn_cvt_pk_fp8_f32(qv, 0.0f, 0, false);
+          y8[col * Kp + rw[q]] = (uint8_t)(wv & 0xff);
+          if ((rw[q] & 31) == 0) y8s[col * Ks + rw[q] / 32] = (uint8_t)sbyte;
+        }
+      }
+    }
+  };
   // |c_k| for the a-priori planning rule (one wave writes them)
   if (col == 0 && chunk == 0) {
     Plan* P = (Plan*)(ws + L.off_plan);
     for (int k = lane; k <= m; k += 64) P->abs_coef[k] = fabs(cf.c[k]);
   }
-  double xsum = 0.0;   // column abs sum of X_1 (taken in the first pass over the blocks)
-  // blocks in chunks of 8 so their running values stay in registers
-  for (int i0 = 0; i0 < nB; i0 += 8) {
-    W bv[RPL][8];
+  // block i's values of this lane's rows, stored with the trivial last step
+  // folded in; its partial column abs sum
+  auto store_block = [&](int i, const W bv[RPL], const W y[RPL]) {
+    double v = 0.0;
 #pragma unroll
-    for (int ii = 0; ii < 8; ++ii) {
-      const int i = i0 + ii;
-      const W c0 = (i < nB && s * i <= m) ? (W)cf.c[s * i] : W(0);
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) bv[q][ii] = (rw[q] == col && col < a.nv) ? c0 : W(0);
+    for (int q = 0; q < RPL; ++q) {
+      if (!inner[q]) continue;
+      v += fabs((double)bv[q]);
+      W outv = bv[q];
+      if (a.trivial_last && i == r - 1) outv += (W)cf.c[m] * y[q];   // step r: c_m I * Y
+      Bm[(int64_t)i * se + rw[q] + col * n] = outv;
     }
-#pragma unroll 2
-    for (int j = 1; j < (colv ? s : 1); ++j) {
-      W xj[RPL];
-      load_x(j, xj);
-      if (j == 1 && i0 == 0)
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) colsum[((int64_t)i * nch + chunk) * n + col] = v;
+  };
+  // identity term of block i on this lane's rows
+  auto block_init = [&](int i, W bv[RPL]) {
+    const W c0 = (i < nB && s * i <= m) ? (W)cf.c[s * i] : W(0);
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) xsum += fabs((double)xj[q]);
+    for (int q = 0; q < RPL; ++q) bv[q] = (rw[q] == col && col < a.nv) ? c0 : W(0);
+  };
+  double xsum = 0.0;   // column abs sum of X_1
+  W y[RPL];
+  constexpr int PG = 8;   // block sizes up to PG: every power of the column loaded at once
+  if (GATHER && s <= PG) {
+    W x[PG][RPL];
 #pragma unroll
-      for (int ii = 0; ii < 8; ++ii) {
-        const int k = s * (i0 + ii) + j;
-        if (i0 + ii < nB && k <= m) {
+    for (int jj = 0; jj < PG; ++jj) {
+      if (jj < s) {
+        load_raw(jj + 1, x[jj]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) x[jj][q] = W(0);
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < PG; ++jj) finish_x(jj + 1, x[jj]);   // zero stays zero for jj >= s
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) y[q] = x[0][q];
+#pragma unroll
+    for (int jj = 1; jj < PG; ++jj)
+      if (jj + 1 == s)
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) y[q] = x[jj][q];
+    y_copies(y);
+    if (s > 1)
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) xsum += fabs((double)x[0][q]);
+    for (int i = 0; i < nB; ++i) {
+      W bv[RPL];
+      block_init(i, bv);
+      // B_i = c_{si} I + sum_{j=1}^{s-1} c_{si+j} X_j, terms in increasing j
+#pragma unroll
+      for (int j = 1; j < PG; ++j) {
+        const int k = s * i + j;
+        if (j < s && k <= m) {
           const W ck = (W)cf.c[k];
 #pragma unroll
-          for (int q = 0; q < RPL; ++q) bv[q][ii] += ck * xj[q];
+          for (int q = 0; q < RPL; ++q) bv[q] += ck * x[j - 1][q];
         }
       }
+      store_block(i, bv, y);
     }
+  } else {
+    load_x(s, y);
+    y_copies(y);
+    // blocks in chunks of BC so their running values stay in registers; the
+    // powers X_1..X_{s-1} are read once per chunk, terms in increasing j
+    constexpr int BC = sizeof(W) == 8 ? 4 : 8;
+    for (int i0 = 0; i0 < nB; i0 += BC) {
+      W bv[BC][RPL];
 #pragma unroll
-    for (int ii = 0; ii < 8; ++ii) {
-      const int i = i0 + ii;
-      if (i >= nB) continue;
-      double v = 0.0;
+      for (int ii = 0; ii < BC; ++ii) block_init(i0 + ii, bv[ii]);
+#pragma unroll 2
+      for (int j = 1; j < (colv ? s : 1); ++j) {
+        W xj[RPL];
+        load_x(j, xj);
+        if (j == 1 && i0 == 0)
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        if (!inner[q]) continue;
-        v += fabs((double)bv[q][ii]);
-        W outv = bv[q][ii];
-        if (a.trivial_last && i == r - 1) outv += (W)cf.c[m] * y[q];   // step r: c_m I * Y
-        Bm[(int64_t)i * se + rw[q] + col * n] = outv;
+          for (int q = 0; q < RPL; ++q) xsum += fabs((double)xj[q]);
+#pragma unroll
+        for (int ii = 0; ii < BC; ++ii) {
+          const int k = s * (i0 + ii) + j;
+          if (i0 + ii < nB && k <= m) {
+            const W ck = (W)cf.c[k];
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) bv[ii][q] += ck * xj[q];
+          }
+        }
       }
-      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-      if (lane == 0) colsum[((int64_t)i * nch + chunk) * n + col] = v;
+#pragma unroll
+      for (int ii = 0; ii < BC; ++ii)
+        if (i0 + ii < nB) store_block(i0 + ii, bv[ii], y);
     }
   }
   double v = ysum;

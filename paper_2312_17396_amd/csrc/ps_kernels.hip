@@ -8,8 +8,10 @@
 //   k_gemm      C = alpha op(A) op(B) (+C): power table X_{j+1} = X_j X
 //               (Algorithm 1), squarings R <- R^2 (eq. (scal-idea)) and the
 //               adjoint products.  FP64 or FP32 MFMA 16x16x4, 64x64 output tile
-//               per 256-thread workgroup (2x2 waves of 32x32), K staged through
-//               LDS in double-buffered slabs of 16.
+//               per 512-thread workgroup (8 waves of 32x16, each two 16x16
+//               MFMA blocks), K staged through two LDS stages in slabs of 32.
+//   k_gemm_group several independent products of one order in one launch
+//               (the levels of the power table).
 //   k_horner    one Horner step P_{i-1} = B_{i-1} + P_i Y.  The product runs in
 //               the step's tier (FP64 / FP32 MFMA 16x16x4, BF16 MFMA 16x16x32,
 //               FP8 E4M3 MFMA 16x16x128 with E8M0 scales per 32 K-elements);
@@ -140,14 +142,14 @@ hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_
 // k_assemble: one wave per (column, row chunk)
 // ---------------------------------------------------------------------------
 template <typename W>
-__global__ __launch_bounds__(NT) void k_assemble(AssembleArgs a, Coefs cf) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_assemble(AssembleArgs a, Coefs cf) {
   const int w = threadIdx.x >> 6;
   const int64_t col = (int64_t)blockIdx.x * NW + w;
   if (col >= a.n) return;  // no block-wide synchronisation below
   const int64_t b = blockIdx.z;
   char* ws = a.ws + b * a.ws_stride;
   const W* X1 = (const W*)a.X1.p + b * a.X1.stride;
-  assemble_column<W>(a, cf, ws, X1, col, blockIdx.y);
+  assemble_column<W, true>(a, cf, ws, X1, col, blockIdx.y);
 }
 
 hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, int batch, hipStream_t st) {
