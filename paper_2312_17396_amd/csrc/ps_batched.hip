@@ -324,7 +324,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.ldo = final_out ? (square ? n : it.lde) : n;
   h.nv = (final_out && !square) ? it.nv : n;
   h.nvb = it.nv;
-  horner_tile<W>(h, (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, smem);
+  horner_tile<W, false>(h, (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, smem);
 }
 
 // ---- squaring q (1..sigma): R_q = R_{q-1}^2, R_0 in L.off_R, ping-pong with P0

@@ -295,11 +295,6 @@ __device__ inline uint16_t bf16_bits_rne(float x) {
   return (uint16_t)(u >> 16);
 }
 
-// Register pipeline over K slabs for the low-precision main loops: the loads
-// of PF slabs are in flight while one slab is multiplied, so a wave waits for
-// memory about once per PF slabs instead of once per slab.  The ring slots
-// are expanded by template recursion, so every slot index is a compile-time
-// constant and the ring lives in VGPRs.
 // ---- BF16 / FP8 main loop.  The operands are packed K-contiguous: row r of
 // P_i (and column j of Y) is a run of Kp elements, FP8 rows followed by E8M0
 // scales (one byte per 32 elements).  A slab is 128 bytes of K per row (FP8:
@@ -332,29 +327,44 @@ __device__ inline uint4 lp_mask(uint4 v, int64_t k, int64_t n) {
   return u.q;
 }
 
+// the slab-i loads of thread t (raw: K past n not yet masked)
 template <bool FP8>
-__device__ __forceinline__ void lp_load(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
-                               const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t rsb,
-                               int64_t Ks, int64_t n, int64_t m0, int64_t n0, int64_t i, int t, LpRegs& r) {
-  constexpr int EB = FP8 ? 1 : 2;
+__device__ __forceinline__ void lp_load_raw(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+                                   const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t rsb,
+                                   int64_t Ks, int64_t m0, int64_t n0, int64_t i, int t, LpRegs& r) {
   const int row = t >> 3, ch = t & 7;
   const int64_t kbyte = 128 * i + 16 * ch;
   r.a = *(const uint4*)(A + (m0 + row) * rsb + kbyte);
   r.b = *(const uint4*)(B + (n0 + row) * rsb + kbyte);
-  const int64_t k = kbyte / EB;
+  // one word = the 4 E8M0 scales of this slab for one row of A (t < 64) or
+  // one column of B
+  if (FP8 && t < 128)
+    r.s = (t < 64) ? *(const uint32_t*)(As + (m0 + t) * Ks + 4 * i)
+                   : *(const uint32_t*)(Bs + (n0 + t - 64) * Ks + 4 * i);
+}
+// zero the elements >= n of slab i; scale blocks wholly past n get the
+// neutral scale 2^0
+template <bool FP8>
+__device__ __forceinline__ void lp_fix(int64_t n, int64_t i, int t, LpRegs& r) {
+  constexpr int EB = FP8 ? 1 : 2;
+  const int ch = t & 7;
+  const int64_t k = (128 * i + 16 * ch) / EB;
   if (k + 16 / EB > n) {
     r.a = lp_mask<EB>(r.a, k, n);
     r.b = lp_mask<EB>(r.b, k, n);
   }
   if (FP8 && t < 128) {
-    // one word = the 4 E8M0 scales of this slab for one row of A (t < 64) or
-    // one column of B; blocks wholly past n get the neutral scale 2^0
-    r.s = (t < 64) ? *(const uint32_t*)(As + (m0 + t) * Ks + 4 * i)
-                   : *(const uint32_t*)(Bs + (n0 + t - 64) * Ks + 4 * i);
 #pragma unroll
     for (int bk = 0; bk < 4; ++bk)
       if ((4 * i + bk) * 32 >= n) r.s = (r.s & ~(0xffu << (8 * bk))) | (127u << (8 * bk));
   }
+}
+template <bool FP8>
+__device__ __forceinline__ void lp_load(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+                               const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t rsb,
+                               int64_t Ks, int64_t n, int64_t m0, int64_t n0, int64_t i, int t, LpRegs& r) {
+  lp_load_raw<FP8>(A, As, B, Bs, rsb, Ks, m0, n0, i, t, r);
+  lp_fix<FP8>(n, i, t, r);
 }
 
 template <bool FP8>
@@ -429,6 +439,38 @@ __device__ __forceinline__ void mainloop_lowp(const uint8_t* __restrict__ A, con
     step(kt, r0, r1);
     step(kt + 1, r1, r0);
   }
+}
+
+// FP8 with at most LP_ALL slabs (n <= 1024): the loads of every slab are
+// issued first, so the workgroup waits for memory once; the slabs then pass
+// through the two LDS stages (one barrier per slab: the barrier of slab k+1
+// follows every wave's reads of slab k, so slab k+2 may overwrite its stage).
+constexpr int LP_ALL = 8;
+__device__ __forceinline__ void mainloop_fp8_all(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+                                                 const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs,
+                                                 int64_t Kp, int64_t n, int64_t m0, int64_t n0, char* smem,
+                                                 f4v acc[2]) {
+  const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
+  const int wr = wave_row0(), wc = wave_col0();
+  const int64_t Ks = Kp / 32;
+  const int ns = (int)((n + 127) / 128);
+  acc[0] = f4v{0, 0, 0, 0};
+  acc[1] = f4v{0, 0, 0, 0};
+  LpRegs r[LP_ALL];
+#pragma unroll
+  for (int i = 0; i < LP_ALL; ++i)
+    if (i < ns) lp_load_raw<true>(A, As, B, Bs, Kp, Ks, m0, n0, i, t, r[i]);
+#pragma unroll
+  for (int i = 0; i < LP_ALL; ++i) {
+    if (i < ns) {
+      char* st = smem + (i & 1) * LP_STAGE;
+      lp_fix<true>(n, i, t, r[i]);
+      lp_store<true>(st, t, r[i]);
+      __syncthreads();
+      lp_mma<true>(st, wr, wc, g, c, acc);
+    }
+  }
+  __syncthreads();   // the epilogue reuses the stages
 }
 
 // E4M3 quantisation of 32 floats with a shared power-of-two scale (E8M0).
@@ -547,7 +589,9 @@ struct HornerTile {
                             // for rows and columns < nvb only (zero beyond)
 };
 
-template <typename W>
+// FP8ALL: FP8 products of order n <= 1024 load all their K slabs at once
+// (mainloop_fp8_all); off for the batched kernel, whose orders stay <= 256
+template <typename W, bool FP8ALL>
 __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, int64_t n0, char* smem) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;   // working tier
   const int64_t n = h.n, Kp = h.Kp;
@@ -585,10 +629,16 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
     mainloop_lowp<false>((const uint8_t*)h.pin, nullptr, (const uint8_t*)h.ybf16, nullptr, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else if (t_in == 3) {
-    load_b();
     f4v acc[2];
     const uint8_t* p8 = (const uint8_t*)h.pin;
-    mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
+    if (FP8ALL && n <= LP_ALL * 128) {
+      // every slab's registers are taken by the main loop: B_{i-1} after it
+      mainloop_fp8_all(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
+      load_b();
+    } else {
+      load_b();
+      mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
+    }
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else {
     load_b();   // cast only

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.ldo = a.final_out ? a.out.ld : a.n;
   h.nv = a.n;
   h.nvb = a.n;
-  horner_tile<W>(h, (int64_t)tm * kTileM, (int64_t)tn * kTileN, smem);
+  horner_tile<W, true>(h, (int64_t)tm * kTileM, (int64_t)tn * kTileN, smem);
 }
 
 hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_t st) {

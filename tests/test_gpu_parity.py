@@ -92,6 +92,10 @@ def test_rotation_generator(ps):
     (130, 13, 4, 0, 1.0), (200, 18, 5, 1, 2.0), (257, 30, 6, 0, 0.1), (96, 12, 1, 0, 0.3), (65, 9, 9, 0, 0.8),
     # block sizes whose power table has levels of 4, 6 and 8 products per launch
     (40, 100, 16, 0, 2.0), (24, 170, 14, 1, 3.0),
+    # the block assembly's two forms: all powers of a column loaded at once
+    # (s <= 8) or one after another (s > 8), each over two row chunks of
+    # 256 with a ragged second one; and s = 2
+    (300, 64, 8, 0, 2.0), (290, 81, 9, 1, 1.5), (50, 4, 2, 0, 1.0),
 ])
 @pytest.mark.parametrize("mode", ["fixed", "mixed"])
 def test_fp64_vs_oracle_small(ps, n, m, s, sigma, t, mode):
