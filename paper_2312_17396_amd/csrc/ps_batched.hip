@@ -224,7 +224,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 // ---- blocks, norms, low-precision copies of Y: one wave per column
 template <typename W>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bassemble(BatchArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(W) == 4 ? 6 : 4))) void k_bassemble(BatchArgs a) {
   const int task = a.col_tasks[blockIdx.x];
   const int b = task >> 8, grp = task & 255;
   const BatchRes& it = a.res[b];

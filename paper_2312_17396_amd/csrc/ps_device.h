@@ -841,9 +841,10 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
   } else {
     load_x(s, y);
     y_copies(y);
-    // blocks in chunks of BC so their running values stay in registers; the
-    // powers X_1..X_{s-1} are read once per chunk, terms in increasing j
-    constexpr int BC = sizeof(W) == 8 ? 4 : 8;
+    // blocks in chunks of BC so their running values stay in registers (few
+    // enough for six waves per SIMD in the batched kernel); the powers
+    // X_1..X_{s-1} are read once per chunk, terms in increasing j
+    constexpr int BC = 4;
     for (int i0 = 0; i0 < nB; i0 += BC) {
       W bv[BC][RPL];
 #pragma unroll
