@@ -237,7 +237,35 @@ def test_fp64_ps_close_to_dd():
     assert 0 < e < n * 4 * U
 
 
+def test_fp64_scaling_and_squaring_on_a_diagonal():
+    # the double route of eq. (scal-idea): on a diagonal matrix every entry is
+    # the scalar r(d) = p(2^-sigma d)^(2^sigma), and the Taylor polynomial of
+    # degree 30 is e^x to double precision for |x| <= 1
+    d = np.array([0.5, -1.0, 3.0, 7.5, -6.0])
+    c = coeffs.taylor_exp(30)
+    for sigma in (2, 3):
+        E = oracle.expm_ps_f64(np.diag(d), c, 6, sigma)
+        assert np.array_equal(E - np.diag(np.diag(E)), np.zeros_like(E))
+        assert np.allclose(np.diag(E), np.exp(d), rtol=1e-13, atol=0), sigma
+
+
 # ---------------------------------------------- P7: Pade coefficients
+def test_pade_defining_property_and_small_cases():
+    # section 4.1: p_km / q_km is the [k/m] Pade approximant of e^x, so
+    # q(x) e^x - p(x) = O(x^(k+m+1)) with a non-zero coefficient at k+m+1
+    for k, m in [(0, 1), (1, 0), (2, 1), (1, 2), (3, 5), (6, 2), (13, 13)]:
+        p, q = coeffs.pade_exp_exact(k, m)
+        assert len(p) == k + 1 and len(q) == m + 1 and p[0] == 1 and q[0] == 1
+        ex = [F(1, math.factorial(j)) for j in range(k + m + 2)]
+        prod = [sum(q[i] * ex[d - i] for i in range(min(d, m) + 1)) for d in range(k + m + 2)]
+        for d in range(k + m + 1):
+            assert prod[d] == (p[d] if d <= k else 0), (k, m, d)
+        assert prod[k + m + 1] != 0
+    # textbook forms: [2/1] = (1 + 2x/3 + x^2/6) / (1 - x/3), [1/2] = (1 + x/3) / (1 - 2x/3 + x^2/6)
+    assert coeffs.pade_exp_exact(2, 1) == ([1, F(2, 3), F(1, 6)], [1, F(-1, 3)])
+    assert coeffs.pade_exp_exact(1, 2) == ([1, F(1, 3)], [1, F(-2, 3), F(1, 6)])
+
+
 def test_pade13_blocks_match_paper():
     p, q = coeffs.pade_exp_exact(13, 13)
     rows = [ln.split() for ln in open(os.path.join(GOLD, "pade13_blocks.txt")) if ln.strip() and ln[0] != "#"]
@@ -317,6 +345,37 @@ def test_planner_hand_cases():
     # monotone: a large late block pulls earlier u_i down
     u, nu, t = oplan.plan([1.0, 1e-12, 1e-3], 1e-1)
     assert u[1] <= u[2]
+
+
+def test_planner_exact_values():
+    # eq. (choose-ui) with powers of two, so every u_i is exact:
+    # ||B|| = (4, 2^-10, 2^-20), ||Y|| = 2^-3: the denominators are 2^-13 and
+    # 2^-26, u_1 = 4u 2^13 and u_2 = 4u 2^26 (u = 2^-53)
+    u, nu, t = oplan.plan([4.0, 2.0 ** -10, 2.0 ** -20], 2.0 ** -3)
+    assert u == [2.0 ** -53, 2.0 ** -38, 2.0 ** -25] and nu == 1 and t == [0, 0, 0]
+    # nu and delta (section 3.2): u_1 = 4u < 10u keeps step 1 in the working
+    # precision; u_2 = 2^30 u = 2^-23 >= 2^-24 moves step 2 to FP32
+    u, nu, t = oplan.plan([1.0, 2.0 ** -2, 2.0 ** -30], 1.0)
+    assert nu == 2 and u == [2.0 ** -53, 2.0 ** -53, 2.0 ** -23] and t == [0, 0, 1]
+    # with delta = 1 the same u_1 = 4u starts the lower tiers at step 1
+    u, nu, t = oplan.plan([1.0, 2.0 ** -2, 2.0 ** -30], 1.0, delta=1.0)
+    assert nu == 1 and t == [0, 0, 1]
+
+
+def test_block_bounds_partition_the_coefficients():
+    # eq. (ps): B_i takes c_{si}..c_{si+s-1} for i < r and c_{sr}..c_m last
+    assert oplan.block_bounds(4, 10) == (2, [[0, 1, 2, 3], [4, 5, 6, 7], [8, 9, 10]])
+    assert oplan.block_bounds(3, 9) == (3, [[0, 1, 2], [3, 4, 5], [6, 7, 8], [9]])
+    for s, m in [(1, 5), (5, 5), (6, 30), (7, 40), (16, 255)]:
+        r, ranges = oplan.block_bounds(s, m)
+        assert r == m // s and sum(ranges, []) == list(range(m + 1))
+
+
+def test_norm1_is_the_largest_column_sum():
+    # section 3.3 measures errors in the 1-norm: maximum absolute column sum
+    assert metrics.norm1([[1.0, -2.0], [3.0, 4.0]]) == 6.0
+    assert metrics.norm1(np.array([[1.0, 5.0, 0.0], [-2.0, 0.0, 0.0]])) == 5.0
+    assert metrics.norm1(np.zeros((0, 0))) == 0.0
 
 
 def test_apriori_norms_bound_block_norms():
@@ -402,6 +461,31 @@ def test_theta_taylor_closed_forms_and_bounds(u):
     assert all(a < b for a, b in zip(ths, ths[1:]))
 
 
+def test_alpha_m_closed_forms():
+    # eq. (alpha_m-X): alpha_m(X) = max(||X^d||^(1/d), ||X^(d+1)||^(1/(d+1))) with
+    # d the largest integer such that d (d - 1) <= m + 1
+    for m in (12, 30, 42):
+        d = 1
+        while (d + 1) * d <= m + 1:
+            d += 1
+        for t in (0.5, 2.0, 3.0):
+            assert metrics.alpha_m(t * np.eye(3), m) == pytest.approx(t, rel=1e-15)
+        # Jordan block [[a, b], [0, a]]: ||X^k||_1 = a^k + k a^(k-1) b
+        a, b = 0.75, 0.5
+        ex = max((a ** d + d * a ** (d - 1) * b) ** (1.0 / d),
+                 (a ** (d + 1) + (d + 1) * a ** d * b) ** (1.0 / (d + 1)))
+        assert metrics.alpha_m(np.array([[a, b], [0.0, a]]), m) == pytest.approx(ex, rel=1e-14)
+        # nilpotent of index 2
+        assert metrics.alpha_m(np.array([[0.0, 5.0], [0.0, 0.0]]), m) == 0.0
+
+
+def test_smallest_shift_is_inclusive():
+    # sigma is the least k >= 0 with a <= 2^k b (the scaled norm may reach theta)
+    assert metrics._smallest_shift(4.0, 1.0) == 2
+    assert metrics._smallest_shift(4.0 + 2.0 ** -50, 1.0) == 3
+    assert metrics._smallest_shift(1.0, 1.0) == 0 and metrics._smallest_shift(0.25, 1.0) == 0
+
+
 def test_auto_sigma_on_the_nonnormal_example():
     # A = [[-0.1, 1e6], [0, -0.1]] (eq. (nonnormal-mat-A)): ||A||_1 ~ 1e6 asks for
     # 19 halvings, while alpha_m(A) = 2 alpha_m(A/2) ~ 1.3 (pinned above) is
@@ -444,7 +528,10 @@ def _jordan_s(t, a, m):
 
 
 @pytest.mark.parametrize("t,a", [(F(1, 2), F(1, 32)), (F(1, 4), F(1, 32)), (F(3, 4), F(1, 8)), (F(1), F(1, 4)),
-                                 (F(1, 2), F(1, 4)), (F(1, 4), F(1, 64))])
+                                 (F(1, 2), F(1, 4)), (F(1, 4), F(1, 64)),
+                                 # growth that stops part-way (s = 20 and s = 7), where the
+                                 # norm of the growing B_0 decides the stop
+                                 (F(17, 16), F(1, 8)), (F(9, 8), F(3, 8))])
 def test_variable_s_on_jordan_blocks(t, a):
     m = 30
     X = np.array([[-float(t), float(a)], [0.0, -float(t)]])
