@@ -437,10 +437,19 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
         sigma = inputs.squarings_for(max(float(x) for x in torch.linalg.matrix_norm(At.double(), ord=1).cpu()))
         tf = _time(lambda: ps.ps_expm_strided_batched(At, 18, s=5, sigma=sigma, mode="mixed"), 3, torch)
         tb = _time(lambda: ps.ps_expm_backward(At, Gt, 18, s=5, sigma=sigma), 3, torch)
+        tbm = _time(lambda: ps.ps_expm_backward(At, Gt, 18, s=5, sigma=sigma, mode="mixed"), 3, torch)
+        rep = ps.ps_expm_strided_batched(At[:1], 18, s=5, sigma=sigma, mode="mixed", report=True)[1][0]
         gem_f = 4 + 3 + sigma
+        fl = 64 * (gem_f + 2 * gem_f) * 2 * 512 ** 3   # the backward's forward recomputation + reverse pass
         res["grad_batch_512"] = {"batch": 64, "n": 512, "sigma": sigma, "dtype": "f32",
-                                 "forward_ms": round(tf * 1e3, 3), "backward_ms": round(tb * 1e3, 3),
-                                 "backward_tflops_credited": round(64 * (gem_f + 2 * gem_f) * 2 * 512 ** 3 / tb / 1e12, 2)}
+                                 "forward_ms": round(tf * 1e3, 3),
+                                 "backward_ms": round(tb * 1e3, 3),
+                                 "backward_tflops_credited": round(fl / tb / 1e12, 2),
+                                 "backward_mixed_ms": round(tbm * 1e3, 3),
+                                 "backward_mixed_tflops_credited": round(fl / tbm / 1e12, 2),
+                                 "tiers_matrix_0": [ps.TIER_NAMES[t] for t in rep["tier"][1:rep["first_step"] + 1]],
+                                 "note": "forward: mixed tiers; backward: working precision, and with the reverse "
+                                         "Horner products in the forward plan's tiers (backward_mixed)"}
         del At, Gt
     # ---- automatic scaling (alpha_m bound) on the dense n = 1024 set
     if "auto" in which:

@@ -339,8 +339,16 @@ ps_status ps_batched_destroy(ps_batched_handle h);
 /* ---------------------------------------------------------------------------
  * Adjoint.  gradA = d<G, r(A)>/dA for r(A) = p(2^-sigma A)^(2^sigma), i.e. the
  * Frechet derivative L_r(A^T, G), by reverse-mode differentiation of the
- * squarings, the Horner recurrence, the block assembly and the power table
- * (each reverse Horner step reuses the forward step's tier).
+ * squarings, the Horner recurrence, the block assembly and the power table.
+ * opts NULL or mode PS_MODE_FIXED: every product in the working precision.
+ * mode PS_MODE_MIXED: the forward pass also makes the plan of Theorem 2.1 /
+ * eq. (choose-ui) from its block norms (tier_mask, delta, rule and
+ * tier_override as for ps_expm, so the same tiers as the mixed forward
+ * evaluation), and both products of reverse Horner step i
+ * (Pbar_i = Pbar_{i-1} Y^T, Ybar += P_i^T Pbar_{i-1}) run in forward step
+ * i's tier; the stored iterates, the power chain, the block scatter and the
+ * squarings stay in the working precision.  The plan is made and read on
+ * the device: the call does not synchronise.
  * recompute = 1 keeps only A and recomputes the power table and Horner
  * iterates (smaller workspace); 0 stores them from the forward pass.
  * Strided-batched over `batch` matrices of order n like

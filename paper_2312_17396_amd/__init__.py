@@ -569,9 +569,11 @@ class BatchedGraph:
 # ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
-def ps_expm_backward(A, G, m, s=0, sigma=0, coef=None, recompute=False):
+def ps_expm_backward(A, G, m, s=0, sigma=0, coef=None, recompute=False, mode="fixed", tier_mask=0, delta=10.0,
+                     tier_override=None, rule="blocks"):
     """gradA = d<G, r(A)>/dA for r(A) = p(2^-sigma A)^(2^sigma) (the Frechet
-    derivative L_r(A^T, G)); A and G of shape (n, n) or (batch, n, n)."""
+    derivative L_r(A^T, G)); A and G of shape (n, n) or (batch, n, n).
+    mode="mixed": the reverse Horner products run in the forward plan's tiers."""
     import torch
     squeeze = A.dim() == 2
     A3 = (A.unsqueeze(0) if squeeze else A).contiguous()
@@ -586,9 +588,11 @@ def ps_expm_backward(A, G, m, s=0, sigma=0, coef=None, recompute=False):
     ws, wsp, wsb = _workspace(nbytes.value, A3.device)
     gA = torch.empty_like(A3)
     c = _darr(coef) if coef is not None else None
+    o, keep = _opts(mode, tier_mask, delta, tier_override, rule=rule)
     _check(lib().ps_expm_backward(dt, bsz, n, A3.data_ptr(), n, n * n, G3.data_ptr(), n, n * n, c, int(m), int(s),
-                                  int(sigma), gA.data_ptr(), n, n * n, int(bool(recompute)), None, wsp, wsb,
-                                  _stream_ptr(A3.device)))
+                                  int(sigma), gA.data_ptr(), n, n * n, int(bool(recompute)), ctypes.byref(o), wsp,
+                                  wsb, _stream_ptr(A3.device)))
+    del keep
     return gA[0] if squeeze else gA
 
 
@@ -602,7 +606,7 @@ def _autograd_cls():
         @staticmethod
         def forward(ctx, A, m, s, sigma, coef, mode, recompute):
             ctx.save_for_backward(A)
-            ctx.cfg = (m, s, sigma, coef, recompute)
+            ctx.cfg = (m, s, sigma, coef, recompute, mode)
             if A.dim() == 3:
                 return ps_expm_strided_batched(A, m, s=s, sigma=sigma, coef=coef, mode=mode)
             return ps_expm(A, m, s=s, sigma=sigma, coef=coef, mode=mode)
@@ -610,8 +614,8 @@ def _autograd_cls():
         @staticmethod
         def backward(ctx, gE):
             (A,) = ctx.saved_tensors
-            m, s, sigma, coef, recompute = ctx.cfg
-            gA = ps_expm_backward(A, gE, m, s=s, sigma=sigma, coef=coef, recompute=recompute)
+            m, s, sigma, coef, recompute, mode = ctx.cfg
+            gA = ps_expm_backward(A, gE, m, s=s, sigma=sigma, coef=coef, recompute=recompute, mode=mode)
             return gA, None, None, None, None, None, None
 
     return ExpmPS

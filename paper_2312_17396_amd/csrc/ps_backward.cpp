@@ -17,6 +17,12 @@
 // forward count.  recompute = 0 stores the Horner iterates P_1..P_{first-1};
 // recompute = 1 keeps two buffers and re-runs the Horner recurrence from the
 // top whenever an iterate is needed.
+// In mixed mode the forward pass also runs the planning kernel on its block
+// norms (the same plan as the mixed forward evaluation), and the two products
+// of reverse Horner step i, Pbar_i = Pbar_{i-1} Y^T and Ybar += P_i^T Pbar_{i-1},
+// run in the tier of forward step i (k_tpack + k_tgemm read it on the
+// device).  The stored iterates, the power chain, the block scatter and the
+// squarings stay in the working precision.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -42,6 +48,7 @@ struct BLayout {
   size_t off_G[2];  // adjoint ping-pong
   size_t off_Xbar;  // Xbar_1..Xbar_s
   size_t off_GX;
+  size_t off_Q[2];  // operand copies of a tiered reverse product
   size_t bytes;
 };
 
@@ -58,6 +65,7 @@ BLayout make_blayout(ps_dtype dt, int64_t n, int m, int s, int sigma, int recomp
   B.off_G[1] = off; off += slot;
   B.off_Xbar = off; off += (size_t)s * slot;
   B.off_GX = off;   off += slot;
+  for (int q = 0; q < 2; ++q) { B.off_Q[q] = off; off += B.F.pslot; }
   B.bytes = al256b(off);
   return B;
 }
@@ -118,7 +126,9 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
   if (batch > 1 && (strideA < (n - 1) * lda + n || strideG < (n - 1) * ldg + n || strideGA < (n - 1) * ldga + n))
     return bad(PS_ERR_ARG, "batch stride smaller than one matrix");
   if (opts && opts->mode != PS_MODE_FIXED && opts->mode != PS_MODE_MIXED) return bad(PS_ERR_ARG, "opts.mode");
+  if (opts && opts->rule != PS_RULE_BLOCKS && opts->rule != PS_RULE_APRIORI) return bad(PS_ERR_ARG, "opts.rule");
   const int W = dtype == PS_F64 ? 0 : 1;
+  const bool mixed = opts && opts->mode == PS_MODE_MIXED;
   const int es = W == 0 ? 8 : 4;
   auto span_of = [&](const void* p, int64_t ld, int64_t stride) {
     return std::make_pair((const char*)p, (size_t)(((int64_t)(batch - 1) * stride + (n - 1) * ld + n) * es));
@@ -187,6 +197,30 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
     aa.L = L;
     aa.tier_mask = 0;
     BK_HIP(launch_assemble(W, aa, cf, batch, st));
+  }
+  if (mixed) {
+    // the forward plan from the block norms (tiers of the reverse Horner products)
+    PlanArgs pa;
+    memset(&pa, 0, sizeof pa);
+    pa.r = r;
+    pa.mode = PS_MODE_MIXED;
+    pa.working = W;
+    pa.nB = L.nB;
+    pa.trivial_last = L.trivial_last;
+    pa.rule = opts->rule;
+    unsigned mask = opts->tier_mask ? opts->tier_mask : 0xFu;
+    mask |= 1u << W;
+    for (int t = 0; t < W; ++t) mask &= ~(1u << t);
+    pa.mask = mask;
+    pa.delta = opts->delta > 0 ? opts->delta : 10.0;
+    pa.abs_cm = fabs(c[m]);
+    pa.use_override = opts->tier_override != nullptr;
+    if (pa.use_override)
+      for (int i = 0; i <= r; ++i) pa.override_tier[i] = opts->tier_override[i];
+    pa.ws = base;
+    pa.ws_stride = wss;
+    pa.L = L;
+    BK_HIP(launch_plan(pa, batch, st));
   }
   // Horner iterate P_i (i >= 1): B_{i0} for i = i0, stored slot otherwise
   auto Pst = [&](int i) { return slot(B.off_Pst + (size_t)(i - 1) * L.slot); };
@@ -271,6 +305,44 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
     if (any) BK_HIP(launch_scatter(W, sa, batch, st));
     return PS_OK;
   };
+  // C = alpha op(A) op(B) (+ C) in the tier of forward Horner step i
+  auto tiered = [&](int i, MatArg A_, int tA, MatArg B_, int tB, MatArg C_, double alpha, int acc) -> ps_status {
+    TPackArgs pk;
+    memset(&pk, 0, sizeof pk);
+    pk.n = n;
+    pk.step = i;
+    pk.ws = base;
+    pk.ws_stride = wss;
+    pk.L = L;
+    pk.role = 0;
+    pk.src = A_;
+    pk.trans = tA;
+    pk.off_dst = B.off_Q[0];
+    BK_HIP(launch_tpack(W, pk, batch, st));
+    pk.role = 1;
+    pk.src = B_;
+    pk.trans = tB;
+    pk.off_dst = B.off_Q[1];
+    BK_HIP(launch_tpack(W, pk, batch, st));
+    TGemmArgs tg;
+    memset(&tg, 0, sizeof tg);
+    tg.n = n;
+    tg.step = i;
+    tg.A = A_;
+    tg.B = B_;
+    tg.C = C_;
+    tg.transA = tA;
+    tg.transB = tB;
+    tg.alpha = alpha;
+    tg.accumulate = acc;
+    tg.off_pa = B.off_Q[0];
+    tg.off_pb = B.off_Q[1];
+    tg.ws = base;
+    tg.ws_stride = wss;
+    tg.L = L;
+    BK_HIP(launch_tgemm(W, tg, batch, st));
+    return PS_OK;
+  };
   for (int i = 1; i <= i0; ++i) {
     // Gb[cur] = Pbar_{i-1} = Bbar_{i-1}
     if (ps_status e = scatter_block(i - 1, Gb[cur])) return e;
@@ -278,9 +350,14 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
     if (ps_status e = iterate(i, &Pi)) return e;
     // Ybar += P_i^T Pbar_{i-1} (times yalpha when Y = beta A: the chain rule
     // through Y = beta A is applied at the end with Xbar_1)
-    BK_HIP(launch_gemm(W, n, batch, Pi, 1, Gb[cur], 0, Xbar(s), 1.0, 1, st));
     // Pbar_i = Pbar_{i-1} Y^T
-    BK_HIP(launch_gemm(W, n, batch, Gb[cur], 0, Ym, 1, Gb[cur ^ 1], yalpha, 0, st));
+    if (mixed) {
+      if (ps_status e = tiered(i, Pi, 1, Gb[cur], 0, Xbar(s), 1.0, 1)) return e;
+      if (ps_status e = tiered(i, Gb[cur], 0, Ym, 1, Gb[cur ^ 1], yalpha, 0)) return e;
+    } else {
+      BK_HIP(launch_gemm(W, n, batch, Pi, 1, Gb[cur], 0, Xbar(s), 1.0, 1, st));
+      BK_HIP(launch_gemm(W, n, batch, Gb[cur], 0, Ym, 1, Gb[cur ^ 1], yalpha, 0, st));
+    }
     cur ^= 1;
   }
   if (ps_status e = scatter_block(i0, Gb[cur])) return e;

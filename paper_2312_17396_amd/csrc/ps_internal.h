@@ -194,6 +194,46 @@ struct ScatterArgs {
 };
 hipError_t launch_scatter(int working, const ScatterArgs& a, int batch, hipStream_t st);
 
+// Adjoint products in the forward plan's tiers.  The tier of Horner step
+// `step` is read on the device from each matrix's Plan (L.off_plan in the
+// matrix's workspace region); when it is the working precision nothing is
+// packed and the product runs on the working-precision operands.
+// k_tpack writes op(src) in the step's operand format into the workspace
+// (L.pslot bytes at off_dst): role 0 (left operand) the rows of op(src),
+// role 1 (right operand) the columns of op(src), K-contiguous for BF16 and
+// FP8 (FP8 with E8M0 scales per 32 K elements); op(src) column-major for an
+// FP32 product under an FP64 working precision.
+struct TPackArgs {
+  int64_t n;
+  int step;
+  int role;
+  MatArg src;            // working precision
+  int trans;             // op(src) = src^T
+  size_t off_dst;
+  char* ws;
+  size_t ws_stride;
+  Layout L;
+};
+hipError_t launch_tpack(int working, const TPackArgs& a, int batch, hipStream_t st);
+
+// C = alpha op(A) op(B) (+ C if accumulate), the product in step's tier:
+// the working-precision operands A, B when the tier is the working
+// precision, otherwise the packed copies at off_pa (role 0 of op(A)) and
+// off_pb (role 1 of op(B)).  Supported: (transA, transB) = (0, 1) or (1, 0).
+struct TGemmArgs {
+  int64_t n;
+  int step;
+  MatArg A, B, C;
+  int transA, transB;
+  double alpha;
+  int accumulate;
+  size_t off_pa, off_pb;
+  char* ws;
+  size_t ws_stride;
+  Layout L;
+};
+hipError_t launch_tgemm(int working, const TGemmArgs& a, int batch, hipStream_t st);
+
 // dst = alpha * (x + y) elementwise (n x n, batch).
 hipError_t launch_axpby(int working, int64_t n, int batch, MatArg x, MatArg y, MatArg dst, double alpha,
                         hipStream_t st);

@@ -139,6 +139,125 @@ hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_
 }
 
 // ---------------------------------------------------------------------------
+// k_tpack / k_tgemm: the adjoint's Horner products in the tier that the
+// forward plan gave the step (read from each matrix's Plan on the device)
+// ---------------------------------------------------------------------------
+template <typename W>
+__global__ __launch_bounds__(NT) void k_tpack(TPackArgs a) {
+  constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
+  __shared__ __attribute__((aligned(16))) W Cs[kTileN * CSTR];
+  const int64_t b = blockIdx.z;
+  char* ws = a.ws + b * a.ws_stride;
+  const int tier = ((const Plan*)(ws + a.L.off_plan))->tier[a.step];
+  if (tier == WT) return;   // uniform over the grid's matrix: nothing to pack
+  const int64_t n = a.n;
+  const int ntm = (int)((n + kTileM - 1) / kTileM);
+  const int64_t m0 = (int64_t)(blockIdx.x % ntm) * kTileM, n0 = (int64_t)(blockIdx.x / ntm) * kTileN;
+  const W* src = (const W*)a.src.p + b * a.src.stride;
+  const int64_t ld = a.src.ld;
+  // tile of Z = op(src) (FP32 copy, or a left operand) or Z = op(src)^T (the
+  // right operand of a BF16 / FP8 product, whose columns become rows);
+  // tz: Z is src transposed.  The lanes run along src's contiguous index.
+  const bool tz = (tier == 1 || a.role == 0) ? a.trans != 0 : a.trans == 0;
+  const int t = threadIdx.x, lane = t & 63;
+#pragma unroll
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int o = (t >> 6) + NW * q;
+    const int r = tz ? o : lane, c = tz ? lane : o;   // Z(r, c) of the tile
+    const int64_t zr = m0 + r, zc = n0 + c;
+    const bool in = zr < n && zc < n;
+    const W v = src[in ? (tz ? zc + zr * ld : zr + zc * ld) : 0];
+    Cs[c * CSTR + r] = in ? v : W(0);
+  }
+  __syncthreads();
+  char* dst = ws + a.off_dst;
+  if (tier == 1) {   // FP32 product under an FP64 working precision: Z column-major, ld n
+    float* d = (float*)dst;
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) {
+      const int col = (t >> 6) + NW * q;
+      if (m0 + lane < n && n0 + col < n) d[(m0 + lane) + (n0 + col) * n] = (float)Cs[col * CSTR + lane];
+    }
+  } else {
+    pack_tile_lowp<W>(Cs, tier, dst, a.L.Mp, a.L.Kp, m0, n0);
+  }
+}
+
+template <typename W, bool TA, bool TB>
+__global__ __launch_bounds__(NT) void k_tgemm(TGemmArgs a) {
+  constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
+  const int64_t b = blockIdx.z;
+  char* ws = a.ws + b * a.ws_stride;
+  const int tier = ((const Plan*)(ws + a.L.off_plan))->tier[a.step];
+  const int64_t n = a.n;
+  const int ntm = (int)((n + kTileM - 1) / kTileM), ntn = (int)((n + kTileN - 1) / kTileN);
+  int tm, tn;
+  tile_of_block(ntm, ntn, tm, tn);
+  const int64_t m0 = (int64_t)tm * kTileM, n0 = (int64_t)tn * kTileN;
+  W* C = (W*)a.C.p + b * a.C.stride;
+  if (tier == WT) {
+    gemm_tile<W, TA, TB>((const W*)a.A.p + b * a.A.stride, a.A.ld, (const W*)a.B.p + b * a.B.stride, a.B.ld, C,
+                         a.C.ld, n, n, m0, n0, a.alpha, a.accumulate, smem);
+    return;
+  }
+  const char* pa = ws + a.off_pa;
+  const char* pb = ws + a.off_pb;
+  W* Cs = (W*)smem;
+  if (tier == 1) {
+    typename MF<float>::V acc[2];
+    mainloop_lds<float, false, false>((const float*)pa, n, (const float*)pb, n, n, m0, n0, smem, acc);
+    frag_to_cs<float, W>(acc, Cs, 1.0);
+  } else {
+    f4v acc[2];
+    const int64_t Mp = a.L.Mp, Kp = a.L.Kp;
+    const uint8_t* qa = (const uint8_t*)pa;
+    const uint8_t* qb = (const uint8_t*)pb;
+    if (tier == 3) mainloop_lowp<true>(qa, qa + Mp * Kp, qb, qb + Mp * Kp, Kp, n, m0, n0, smem, acc);
+    else mainloop_lowp<false>(qa, nullptr, qb, nullptr, Kp, n, m0, n0, smem, acc);
+    frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int row = t & 63;
+  const int64_t gr = m0 + row;
+#pragma unroll 4
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int col = (t >> 6) + NW * q;
+    const int64_t gc = n0 + col;
+    if (gr < n && gc < n) {
+      const W v = (W)(a.alpha * (double)Cs[col * CSTR + row]);
+      W* dst = C + gr + gc * a.C.ld;
+      if (a.accumulate) *dst = *dst + v;
+      else *dst = v;
+    }
+  }
+}
+
+hipError_t launch_tpack(int working, const TPackArgs& a, int batch, hipStream_t st) {
+  const int nt = (int)((a.n + kTileM - 1) / kTileM);
+  dim3 grid(nt * nt, 1, batch), block(NT);
+  if (working == 0) hipLaunchKernelGGL(k_tpack<double>, grid, block, 0, st, a);
+  else hipLaunchKernelGGL(k_tpack<float>, grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tgemm(int working, const TGemmArgs& a, int batch, hipStream_t st) {
+  const int ntm = (int)((a.n + kTileM - 1) / kTileM), ntn = (int)((a.n + kTileN - 1) / kTileN);
+  dim3 grid(ntm * ntn, 1, batch), block(NT);
+  if (!a.transA && a.transB) {
+    if (working == 0) hipLaunchKernelGGL((k_tgemm<double, false, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_tgemm<float, false, true>), grid, block, 0, st, a);
+  } else if (a.transA && !a.transB) {
+    if (working == 0) hipLaunchKernelGGL((k_tgemm<double, true, false>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_tgemm<float, true, false>), grid, block, 0, st, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_assemble: one wave per (column, row chunk)
 // ---------------------------------------------------------------------------
 template <typename W>

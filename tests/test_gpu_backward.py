@@ -85,8 +85,80 @@ def test_autograd_function(ps):
     assert torch.autograd.gradcheck(f, (A,), eps=1e-6, atol=1e-8, rtol=1e-6)
     G = torch.randn(n, n, dtype=torch.float64, device="cuda:0")
     (ps.expm(A, 10, s=3, sigma=1, mode="mixed") * G).sum().backward()
-    want = ps.ps_expm_backward(A.detach(), G, 10, s=3, sigma=1)
+    want = ps.ps_expm_backward(A.detach(), G, 10, s=3, sigma=1, mode="mixed")
     assert torch.equal(A.grad, want)
+
+
+# ---------------------------------------------------------------- mixed tiers
+def _tiers(ps, A, m, s, sigma, **kw):
+    """The forward plan's tiers of Horner steps 1..first_step."""
+    _, rep = ps.ps_expm(to_dev(A), m, s=s, sigma=sigma, mode="mixed", report=True, **kw)
+    return rep["tier"][1:rep["first_step"] + 1]
+
+
+@pytest.mark.parametrize("n,m,s,sigma,t", [
+    (17, 18, 5, 2, 3.0), (64, 30, 6, 0, 0.25), (100, 30, 6, 3, 6.0), (130, 16, 4, 0, 0.5), (70, 40, 7, 1, 1.0),
+])
+def test_gradient_mixed_fp64_vs_oracle(ps, n, m, s, sigma, t):
+    """Reverse Horner step i in forward step i's tier: the gradient stays
+    within the FP64 target's tolerance of the block-triangular oracle."""
+    A = _rand(n, t, 40 + n)
+    G = np.random.default_rng(50 + n).standard_normal((n, n))
+    c = coeffs.taylor_exp(m)
+    gh, gl = oracle.expm_grad_dd(A, G, c, sigma)
+    tiers = _tiers(ps, A, m, s, sigma)
+    fixed = to_np(ps.ps_expm_backward(to_dev(A), to_dev(G), m, s=s, sigma=sigma))
+    out = []
+    for rec in (False, True):
+        gA = to_np(ps.ps_expm_backward(to_dev(A), to_dev(G), m, s=s, sigma=sigma, recompute=rec, mode="mixed"))
+        err = metrics.rel_err_1(gA, gh, gl)
+        print("n=%d tiers %s mixed grad rel err %.3e (fixed %.3e)" % (n, tiers, err, metrics.rel_err_1(fixed, gh, gl)))
+        assert err <= 1e-12, (rec, tiers, err)
+        out.append(gA)
+    assert np.array_equal(out[0], out[1])
+    # the tiered products ran: any lower tier changes the bits
+    if any(tt != 0 for tt in tiers):
+        assert not np.array_equal(out[0], fixed)
+
+
+def test_gradient_mixed_uses_low_tiers(ps):
+    """A small ||X||: the plan takes later steps down to BF16/FP8."""
+    n, m, s, sigma = 96, 30, 6, 0
+    A = _rand(n, 0.1, 3)
+    assert max(_tiers(ps, A, m, s, sigma)) >= 2
+
+
+def test_gradient_mixed_with_only_the_working_tier_is_the_fixed_gradient(ps):
+    n, m, s, sigma = 80, 18, 5, 1
+    A = _rand(n, 2.0, 11)
+    G = np.random.default_rng(12).standard_normal((n, n))
+    a = to_np(ps.ps_expm_backward(to_dev(A), to_dev(G), m, s=s, sigma=sigma))
+    b = to_np(ps.ps_expm_backward(to_dev(A), to_dev(G), m, s=s, sigma=sigma, mode="mixed", tier_mask=1))
+    assert np.array_equal(a, b)
+
+
+def test_gradient_forced_tiers(ps):
+    """Every reverse Horner product forced into one tier (the forward plan
+    overridden) on p(x) = sum_{k<=16} x^k with ||A||_1 = 1, where every block
+    weighs about the same, so a wrong product would show at O(1): the error
+    grows with the tier's unit roundoff and stays within a few of them."""
+    n, m, s, sigma = 72, 16, 4, 0
+    A = _rand(n, 1.0, 21)
+    G = np.random.default_rng(22).standard_normal((n, n))
+    c = [1.0] * (m + 1)
+    gh, gl = oracle.expm_grad_dd(A, G, c, sigma)
+    e64 = metrics.rel_err_1(to_np(ps.ps_expm_backward(to_dev(A), to_dev(G), m, s=s, sigma=sigma, coef=c)), gh, gl)
+    errs = [e64]
+    for tier, u in ((1, 2.0 ** -24), (2, 2.0 ** -8), (3, 2.0 ** -4)):
+        ov = [0] + [tier] * (m // s)
+        gA = to_np(ps.ps_expm_backward(to_dev(A), to_dev(G), m, s=s, sigma=sigma, coef=c, mode="mixed",
+                                       tier_override=ov))
+        err = metrics.rel_err_1(gA, gh, gl)
+        print("forced tier %d: grad rel err %.3e (%.3g u), FP64 %.3e" % (tier, err, err / u, e64))
+        assert err <= 4 * u, (tier, err)
+        errs.append(err)
+    # each lower tier moves the result further from the oracle
+    assert 10 * errs[0] < errs[1] < errs[2] < errs[3], errs
 
 
 def test_grad_batch_512_fp32(ps):
@@ -102,17 +174,22 @@ def test_grad_batch_512_fp32(ps):
     At = torch.tensor(A, device="cuda:0")
     Gt = torch.tensor(G, device="cuda:0")
     gA = to_np(ps.ps_expm_backward(At, Gt, 18, s=5, sigma=sigma))
-    assert np.all(np.isfinite(gA))
+    gM = to_np(ps.ps_expm_backward(At, Gt, 18, s=5, sigma=sigma, mode="mixed"))
+    assert np.all(np.isfinite(gA)) and np.all(np.isfinite(gM))
     c32 = [float(np.float32(x)) for x in coeffs.taylor_exp(18)]
     for b in (0, 37):
         Ab = A[b].astype(np.float64)
         Gb = G[b].astype(np.float64)
         cols = sample_cols(512, 3, seed=b)
         gh, gl = oracle.expm_grad_dd(Ab, Gb, c32, sigma, cols=cols)
-        D = (gA[b][:, cols] - gh) - gl
-        err = float(np.max(np.sum(np.abs(D), 0)) / np.max(np.sum(np.abs(gh), 0)))
-        print("b=%d sigma=%d grad rel err %.3e" % (b, sigma, err))
-        assert err <= 2 ** sigma * 512 * U32 / 8, err
+        errs = []
+        for g in (gA, gM):
+            D = (g[b][:, cols] - gh) - gl
+            errs.append(float(np.max(np.sum(np.abs(D), 0)) / np.max(np.sum(np.abs(gh), 0))))
+        print("b=%d sigma=%d grad rel err fixed %.3e mixed %.3e" % (b, sigma, errs[0], errs[1]))
+        assert errs[0] <= 2 ** sigma * 512 * U32 / 8, errs
+        # equal accuracy with the tiers in both passes
+        assert errs[1] <= max(2 ** sigma * 512 * U32 / 8, 2 * errs[0]), errs
     g = np.random.default_rng(1)
     E = g.standard_normal((512, 512))
     E /= metrics.norm1(E)
