@@ -15,8 +15,9 @@ Also reported:
               two n^3 products) and of the squarings (k_gemm): algorithmic
               2 n^3 flops per product over the average time per product, from
               hipEvent pairs around the power-table and squaring phases
-              (library profile mode, same stream), for the same K steps run
-              again after the timed region
+              (library profile mode, same stream), for K steps of the plain
+              evaluation run after the timed region (all its power products
+              are FP64; the mixed one may form Y = X^s by an FP32 product)
   cpu_baseline  the CPU oracle's plain FP64 Algorithm 1 + squarings
               (OpenMP, all host cores) on one evaluation of each matrix, plus
               the GPU result's error against the dd oracle on sampled columns
@@ -49,8 +50,14 @@ def step_ideal_s(rep, sigma, mixed):
     MFMA-only part, sum of flops / peak(tier)."""
     n2, F = float(N) * N, 2.0 * N ** 3
     gemm64 = max(F / TIER_PEAK[0], 3 * 8 * n2 / HBM_BW)
-    t = (S - 1) * gemm64 + sigma * gemm64                                    # powers, squarings
-    mf = (S - 1 + sigma) * F / TIER_PEAK[0]
+    # power products per tier from the report (mixed mode may form Y = X^s by
+    # an FP32 product, and again in FP64 when the plan keeps a product there)
+    steps = [rep["tier"][i] for i in range(1, rep["first_step"] + 1)]
+    pow64 = rep["gemms"][0] - sigma - sum(1 for t in steps if t == 0)
+    pow32 = rep["gemms"][1] - sum(1 for t in steps if t == 1)
+    gemm32 = max(F / TIER_PEAK[1], (2 * 8 + 4) * n2 / HBM_BW)
+    t = pow64 * gemm64 + pow32 * gemm32 + sigma * gemm64                     # powers, squarings
+    mf = (pow64 + sigma) * F / TIER_PEAK[0] + pow32 * F / TIER_PEAK[1]
     copies = sum(TIER_BYTES[k] for k in (1, 2, 3)) if mixed else 0.0
     fs = rep["first_step"]
     t += (S * 8 + (fs + 1) * 8 + copies) * n2 / HBM_BW                           # block assembly
@@ -247,8 +254,10 @@ def main():
         d = torch.linalg.matrix_norm(em - ef, ord=1).item() / torch.linalg.matrix_norm(ef, ord=1).item()
         errs.append(d)
 
-    # roofline of the dominant kernel: FP64 GEMM (power table + squarings)
-    prof_mode = "mixed" if "mixed" in res else "fixed"
+    # roofline of the dominant kernel: FP64 GEMM (power table + squarings),
+    # timed on the plain evaluation, whose power products are all FP64 (the
+    # mixed one forms Y = X^s by an FP32 product when its plan allows)
+    prof_mode = "fixed"
     gemm_ms, gemm_n = 0.0, 0
     for _ in range(args.steps):
         for r, sg in zip(step(prof_mode, profile=True), sigmas):

@@ -194,7 +194,19 @@ struct Job {
   bool build_powers;     // run the power table (first polynomial only)
   bool skip_square;      // squarings handled by the caller
   int pow_shift = 0;     // power slots hold 2^(-j pow_shift) X_j (prebuilt, exact rescaling)
+  bool y_low = false;    // one polynomial: Y may be formed in FP32 (eq. (cond-Y))
 };
+
+// Y = X_s formed by an FP32 product under an FP64 working precision.  By
+// eq. (cond-Y) Y needs the accuracy u_nu of the first lower-precision Horner
+// step; when the plan keeps every Horner product below FP64, FP32 gives it.
+// The plan is only known on the device, so the cast launch forms Y in FP64
+// too whenever the plan keeps a product in FP64 (and the report counts it).
+bool y_in_fp32(const Job& J) {
+  const Layout& L = *J.L;
+  return J.y_low && J.build_powers && J.write_y && L.working == 0 && L.s >= 2 && !L.square_arg &&
+         J.pow_shift == 0 && (J.opts.mode == PS_MODE_MIXED || J.opts.override_tiers) && ((J.opts.mask >> 1) & 1u);
+}
 
 MatArg ws_mat(char* ws, size_t off, int64_t n, size_t stride_bytes, int esize) {
   MatArg a;
@@ -239,12 +251,14 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
   if (ps_status e = tm.init(phase_ms != nullptr, st)) return e;
   if (ps_status e = tm.mark()) return e;
   // 1. power table
+  auto power = [&](int j) {
+    return j == 1 ? J.X1 : ws_mat(J.ws, L.off_pow + (size_t)(j - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
+  };
+  auto power_alpha = [&](int j) { return (pow_a(j) == 1 ? J.beta : 1.0) * (pow_b(j) == 1 ? J.beta : 1.0); };
+  const bool yl = y_in_fp32(J);
   if (J.build_powers && L.s >= 2) {
     // X_j = X_a X_b (a = ceil(j/2), b = floor(j/2)), one grouped launch per
     // level (j in (2^(l-1), 2^l]); X_1 = beta X1 enters through alpha
-    auto power = [&](int j) {
-      return j == 1 ? J.X1 : ws_mat(J.ws, L.off_pow + (size_t)(j - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
-    };
     for (int top = 2; top / 2 < L.s; top *= 2) {
       const int lo = top / 2 + 1, hi = std::min(top, L.s);   // level: j in (top/2, top]
       for (int j0 = lo; j0 <= hi; j0 += kMaxGroup) {
@@ -255,7 +269,11 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
           g.A[k] = power(a);
           g.B[k] = power(b);
           g.C[k] = power(j);
-          g.alpha[k] = (a == 1 ? J.beta : 1.0) * (b == 1 ? J.beta : 1.0);
+          g.alpha[k] = power_alpha(j);
+          if (yl && j == L.s) {   // Y in FP32, into the slot of its FP32 copy
+            g.f32[k] = 1;
+            g.C[k] = ws_mat(J.ws, L.off_yf32, n, wss, 4);
+          }
         }
         PS_HIP(launch_gemm_group(W, n, J.batch, g, st));
       }
@@ -283,6 +301,7 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
   aa.ws_stride = wss;
   aa.L = L;
   aa.tier_mask = (J.opts.mode == PS_MODE_MIXED || J.opts.override_tiers) && J.write_y ? J.opts.mask : 0u;
+  aa.y_f32 = yl ? 1 : 0;
   PS_HIP(launch_assemble(W, aa, cf, J.batch, st));
   if (ps_status e = tm.mark()) return e;
   // 3. plan
@@ -328,7 +347,16 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
   ha.final_out = (i0 == 0);
   ha.off_bsrc = L.off_B + (size_t)i0 * L.slot;
   ha.off_pout = L.off_P0;
+  if (yl) {
+    ha.y_cond = 1;
+    ha.ya = power(pow_a(L.s));
+    ha.yb = power(pow_b(L.s));
+    ha.yc = power(L.s);
+    ha.y_alpha = power_alpha(L.s);
+    ha.y_cm = cf.c[L.m];   // as the assembly's fold
+  }
   PS_HIP(launch_horner(W, ha, J.batch, st));
+  ha.y_cond = 0;
   ha.cast_only = 0;
   for (int i = i0; i >= 1; --i) {
     const int k = i0 - i;
@@ -378,6 +406,12 @@ ps_status fill_report(const Layout& L, const Job& J, int b, ps_report* rep, hipS
   rep->normX = P.normX;
   rep->gemms[L.working] += L.npow + L.sigma;
   for (int i = L.first_step; i >= 1; --i) rep->gemms[P.tier[i]] += 1;
+  if (y_in_fp32(J)) {   // Y by an FP32 product, again in FP64 if a Horner product is
+    bool fp64_step = false;
+    for (int i = 1; i <= L.r; ++i) fp64_step = fp64_step || P.tier[i] == L.working;
+    rep->gemms[1] += 1;
+    if (!fp64_step) rep->gemms[L.working] -= 1;
+  }
   if (ms) {
     rep->ms_power = ms[0];
     rep->ms_assemble = ms[1];
@@ -667,6 +701,7 @@ static ps_status expm_impl(ps_dtype dtype, int batch, int64_t n, const void* A, 
   J.write_y = true;
   J.build_powers = true;
   J.skip_square = false;
+  J.y_low = true;
   hipStream_t st = (hipStream_t)stream;
   float ms[4] = {0, 0, 0, 0};
   if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;

@@ -196,6 +196,7 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
     aa.ws_stride = wss;
     aa.L = L;
     aa.tier_mask = 0;
+    aa.y_f32 = 0;
     BK_HIP(launch_assemble(W, aa, cf, batch, st));
   }
   if (mixed) {

@@ -187,8 +187,10 @@ __device__ __forceinline__ void mma_slab(const T* as, const T* bs, int wr, int w
 // loads of slab kt+2 are issued before the MFMAs of slab kt, and slab kt+1
 // (loaded one iteration earlier) is stored to the other stage after them.
 // The loop multiplies K slabs [sb, se) (se > sb).
-template <typename T, bool TA, bool TB, bool FULL>
-__device__ __forceinline__ void mainloop_lds_impl(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+// TL: the element type of A and B in memory (T, or FP64 operands of an FP32
+// product, rounded to FP32 as they are stored to LDS).
+template <typename T, bool TA, bool TB, bool FULL, typename TL = T>
+__device__ __forceinline__ void mainloop_lds_impl(const TL* __restrict__ A, int64_t lda, const TL* __restrict__ B, int64_t ldb,
                                     int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2],
                                     int64_t sb, int64_t se) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
@@ -204,24 +206,32 @@ __device__ __forceinline__ void mainloop_lds_impl(const T* __restrict__ A, int64
   // is fetched again and stored into the idle stage): a branch around them
   // would make the memory-counter wait before each store cover the newer
   // loads as well, which cancels the prefetch.
-  T ra0[RUNA], rb0[RUNB], ra1[RUNA], rb1[RUNB];
+  TL ra0[RUNA], rb0[RUNB], ra1[RUNA], rb1[RUNB];
+  // LDS stores of a register set, rounded to T when the operands are wider
+  auto put = [&](T* st, const TL* ra, const TL* rb) {
+    T ca[RUNA], cb[RUNB];
+#pragma unroll
+    for (int i = 0; i < RUNA; ++i) ca[i] = (T)ra[i];
+#pragma unroll
+    for (int i = 0; i < RUNB; ++i) cb[i] = (T)rb[i];
+    store_a<T, TA>(st, t, ca);
+    store_b<T, TB>(st + SLABA, t, cb);
+  };
   const int64_t k0 = sb * BKL, k1 = (sb + min<int64_t>(1, nk - 1)) * BKL;
-  load_a<T, TA, FULL>(A, lda, n, m0, k0, t, ra0);
-  load_b<T, TB, FULL>(B, ldb, n, n0, k0, t, rb0);
-  load_a<T, TA, FULL>(A, lda, n, m0, k1, t, ra1);
-  load_b<T, TB, FULL>(B, ldb, n, n0, k1, t, rb1);
-  store_a<T, TA>(S, t, ra0);
-  store_b<T, TB>(S + SLABA, t, rb0);
+  load_a<TL, TA, FULL>(A, lda, n, m0, k0, t, ra0);
+  load_b<TL, TB, FULL>(B, ldb, n, n0, k0, t, rb0);
+  load_a<TL, TA, FULL>(A, lda, n, m0, k1, t, ra1);
+  load_b<TL, TB, FULL>(B, ldb, n, n0, k1, t, rb1);
+  put(S, ra0, rb0);
   __syncthreads();
-  auto step = [&](int64_t kt, T* rna, T* rnb, const T* rfa, const T* rfb) {
+  auto step = [&](int64_t kt, TL* rna, TL* rnb, const TL* rfa, const TL* rfb) {
     // rna/rnb: free set (receives slab kt+2); rfa/rfb: slab kt+1, in flight
     const int cur = (int)(kt & 1);
     const int64_t kn = (sb + min<int64_t>(kt + 2, nk - 1)) * BKL;
-    load_a<T, TA, FULL>(A, lda, n, m0, kn, t, rna);
-    load_b<T, TB, FULL>(B, ldb, n, n0, kn, t, rnb);
+    load_a<TL, TA, FULL>(A, lda, n, m0, kn, t, rna);
+    load_b<TL, TB, FULL>(B, ldb, n, n0, kn, t, rnb);
     if (kt < nk) mma_slab<T>(S + cur * STAGE, S + cur * STAGE + SLABA, wr, wc, g, c, chains);
-    store_a<T, TA>(S + (cur ^ 1) * STAGE, t, rfa);
-    store_b<T, TB>(S + (cur ^ 1) * STAGE + SLABA, t, rfb);
+    put(S + (cur ^ 1) * STAGE, rfa, rfb);
     __syncthreads();
   };
   for (int64_t kt = 0; kt < nk; kt += 2) {
@@ -248,13 +258,15 @@ __device__ inline bool full_tiles(const T* A, int64_t lda, const T* B, int64_t l
   constexpr int64_t V = 16 / sizeof(T);
   return (n % 64) == 0 && (lda % V) == 0 && (ldb % V) == 0 && ((((uintptr_t)A) | ((uintptr_t)B)) & 15) == 0;
 }
-template <typename T, bool TA, bool TB>
-__device__ __forceinline__ void mainloop_lds(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
+template <typename T, bool TA, bool TB, typename TL = T>
+__device__ __forceinline__ void mainloop_lds(const TL* __restrict__ A, int64_t lda, const TL* __restrict__ B, int64_t ldb,
                                     int64_t n, int64_t m0, int64_t n0, char* smem, typename MF<T>::V acc[2]) {
   const int64_t nk = (n + BKL - 1) / BKL;
-  if (full_tiles(A, lda, B, ldb, n)) mainloop_lds_impl<T, TA, TB, true>(A, lda, B, ldb, n, m0, n0, smem, acc, 0, nk);
-  else mainloop_lds_impl<T, TA, TB, false>(A, lda, B, ldb, n, m0, n0, smem, acc, 0, nk);
+  if (full_tiles(A, lda, B, ldb, n)) mainloop_lds_impl<T, TA, TB, true, TL>(A, lda, B, ldb, n, m0, n0, smem, acc, 0, nk);
+  else mainloop_lds_impl<T, TA, TB, false, TL>(A, lda, B, ldb, n, m0, n0, smem, acc, 0, nk);
 }
+
+
 
 // accumulator fragments -> LDS tile Cs[col * CSTR + row] (type W)
 template <typename T, typename W>
@@ -525,6 +537,29 @@ __device__ __forceinline__ void gemm_tile(const T* __restrict__ Ap, int64_t lda,
   __syncthreads();
 }
 
+// C (FP32, ld ldc) = alpha A B for FP64 operands, the product in FP32: the
+// operands are rounded to FP32 on their way into LDS.  One 64 x 64 tile.
+__device__ __forceinline__ void gemm_tile_f32_of_f64(const double* __restrict__ Ap, int64_t lda,
+                                                     const double* __restrict__ Bp, int64_t ldb, float* Cp,
+                                                     int64_t ldc, int64_t n, int64_t m0, int64_t n0, double alpha,
+                                                     char* smem) {
+  typename MF<float>::V acc[2];
+  mainloop_lds<float, false, false, double>(Ap, lda, Bp, ldb, n, m0, n0, smem, acc);
+  float* Cs = (float*)smem;
+  frag_to_cs<float, float>(acc, Cs, 1.0);
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int row = t & 63;
+  const int64_t gr = m0 + row;
+#pragma unroll 4
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int col = (t >> 6) + NW * q;
+    const int64_t gc = n0 + col;
+    if (gr < n && gc < n) Cp[gr + gc * ldc] = (float)(alpha * (double)Cs[col * CSTR + row]);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // one output tile of a Horner step P_{i-1} = B_{i-1} + P_i Y (t_in < 0: cast of
 // B_src into the format t_out).  The product runs in tier t_in; the epilogue
@@ -587,6 +622,12 @@ struct HornerTile {
   int64_t nv;               // rows and columns < nv of outw are written (nv <= n)
   int64_t nvb;              // order of the matrix inside the padded n: B_{i-1} is read
                             // for rows and columns < nvb only (zero beyond)
+  // fyc != 0 (a cast of the block that holds the folded last step c_m Y,
+  // where the fold used Y in FP32 but the plan keeps a product in FP64):
+  // B_{i-1} + fyc (fy64 - fy32) restores the fold with Y in FP64
+  const W* fy64;
+  const float* fy32;
+  double fyc;
 };
 
 // FP8ALL: FP8 products of order n <= 1024 load all their K slabs at once
@@ -642,6 +683,14 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else {
     load_b();   // cast only
+    if (h.fyc != 0.0) {
+#pragma unroll
+      for (int q = 0; q < TILE_Q; ++q) {
+        const int64_t gc = n0 + (t >> 6) + NW * q;
+        if (gr < h.nvb && gc < h.nvb)
+          bq[q] += (W)(h.fyc * ((double)h.fy64[gr + gc * n] - (double)h.fy32[gr + gc * n]));
+      }
+    }
   }
   __syncthreads();
 
@@ -690,7 +739,7 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
   double* colsum = (double*)(ws + L.off_colsum);
   const int s = a.s, r = a.r, m = a.m, nB = a.nB;
   const double x1s = a.x1_scale;
-  const bool want32 = std::is_same<W, double>::value && ((a.tier_mask >> 1) & 1u);
+  const bool want32 = std::is_same<W, double>::value && ((a.tier_mask >> 1) & 1u) && !a.y_f32;
   const bool want16 = (a.tier_mask >> 2) & 1u;
   const bool want8 = (a.tier_mask >> 3) & 1u;
   const int64_t Kp = L.Kp, Ks = Kp / 32;
@@ -725,13 +774,15 @@ __device__ __forceinline__ void assemble_column(const AssembleArgs& a, const Coe
   // by a wave-uniform test), finish_x scales and masks the values.
   const int64_t cl = colv ? col : 0;
   const int rlim = __builtin_amdgcn_readfirstlane((int)(colv ? min<int64_t>(r_end, a.nv) : r_begin));
+  const bool yf = a.y_f32 != 0;   // Y = X_s in the FP32 copy's slot
   auto load_raw = [&](int j, W out[RPL]) {
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       out[q] = W(0);
       if (!GATHER || r_begin + 64 * q < rlim) {
         const int64_t rr = inner[q] ? rw[q] : r_begin;
-        out[q] = (j == 1) ? X1[rr + cl * a.X1.ld] : pw[(int64_t)(j - 2) * se + rr + cl * n];
+        out[q] = (j == 1) ? X1[rr + cl * a.X1.ld]
+                          : (yf && j == s) ? (W)yf32[rr + cl * n] : pw[(int64_t)(j - 2) * se + rr + cl * n];
       }
     }
   };

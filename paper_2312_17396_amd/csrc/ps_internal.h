@@ -95,6 +95,7 @@ constexpr int kMaxGroup = 8;
 struct GemmGroup {
   MatArg A[kMaxGroup], B[kMaxGroup], C[kMaxGroup];
   double alpha[kMaxGroup];
+  int f32[kMaxGroup];   // FP64 working precision only: product k in FP32, its C an FP32 matrix
   int count;
 };
 hipError_t launch_gemm_group(int working, int64_t n, int batch, const GemmGroup& g, hipStream_t st);
@@ -117,6 +118,7 @@ struct AssembleArgs {
   size_t ws_stride;     // bytes per matrix
   Layout L;
   unsigned tier_mask;   // which low-precision copies of Y to produce
+  int y_f32;            // Y was formed in FP32 into the FP32 copy's slot: read it there
 };
 hipError_t launch_assemble(int working, const AssembleArgs& a, const Coefs& c, int batch, hipStream_t st);
 
@@ -170,6 +172,14 @@ struct HornerArgs {
   char* ws;
   size_t ws_stride;
   Layout L;
+  // cast launch only, Y formed in FP32: when the plan keeps a Horner product
+  // (or the folded last step) in the working precision, the launch first
+  // forms Y = y_alpha Ya Yb in the working precision into Yc (the power slot
+  // of X_s)
+  int y_cond;
+  MatArg ya, yb, yc;
+  double y_alpha;
+  double y_cm;           // c_m (working precision) when s divides m: the fold c_m Y is redone with that Y
 };
 hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_t st);
 

@@ -58,6 +58,12 @@ __global__ __launch_bounds__(NT) void k_gemm_group(int64_t n, GemmGroup g) {
   const int k = blockIdx.y;
   const int64_t b = blockIdx.z;
   const MatArg A = g.A[k], B = g.B[k], C = g.C[k];
+  if (std::is_same<T, double>::value && g.f32[k]) {   // uniform per workgroup (product k)
+    gemm_tile_f32_of_f64((const double*)A.p + b * A.stride, A.ld, (const double*)B.p + b * B.stride, B.ld,
+                         (float*)C.p + b * C.stride, C.ld, n, (int64_t)tm * kTileM, (int64_t)tn * kTileN,
+                         g.alpha[k], smem);
+    return;
+  }
   gemm_tile<T, false, false>((const T*)A.p + b * A.stride, A.ld, (const T*)B.p + b * B.stride, B.ld,
                              (T*)C.p + b * C.stride, C.ld, n, n, (int64_t)tm * kTileM, (int64_t)tn * kTileN,
                              g.alpha[k], 0, smem);
@@ -107,7 +113,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const int64_t b = blockIdx.z;
   char* ws = a.ws + b * a.ws_stride;
   const Plan* plan = (const Plan*)(ws + L.off_plan);
+  bool y64 = false;
+  if (a.y_cond) {
+    // Y was formed in FP32; a Horner product in the working precision (the
+    // folded step r included) needs it in the working precision as well
+    for (int i = 1; i <= L.r; ++i) y64 = y64 || plan->tier[i] == WT;
+    if (y64)
+      gemm_tile<W, false, false>((const W*)a.ya.p + b * a.ya.stride, a.ya.ld, (const W*)a.yb.p + b * a.yb.stride,
+                                 a.yb.ld, (W*)a.yc.p + b * a.yc.stride, a.yc.ld, a.n, a.n, (int64_t)tm * kTileM,
+                                 (int64_t)tn * kTileN, a.y_alpha, 0, smem);
+  }
   HornerTile<W> h;
+  h.fy64 = (const W*)a.yc.p + b * a.yc.stride;
+  h.fy32 = (const float*)(ws + L.off_yf32);
+  h.fyc = (y64 && L.trivial_last) ? a.y_cm : 0.0;   // the assembly folded c_m Y with Y in FP32
   h.n = a.n;
   h.Mp = L.Mp;
   h.Kp = L.Kp;

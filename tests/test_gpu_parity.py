@@ -130,15 +130,18 @@ def test_norms_match_oracle(ps):
     n, m, s = 160, 18, 5
     A = _rand(n, 1.0, 77)
     c = coeffs.taylor_exp(m)
-    _, rep = ps.ps_expm(to_dev(A), m, s=s, sigma=0, mode="mixed", report=True)
     r, ranges = oplan.block_bounds(s, m)
     # direct check on B_i via explicit powers in dd
     Xp = [oracle.poly_dd(A, [0.0] * j + [1.0]) for j in range(s + 1)]
-    for i in range(r + 1):
-        B = sum(c[k] * (Xp[k - s * i][0] + Xp[k - s * i][1]) for k in ranges[i]).T
-        assert abs(metrics.norm1(B) - rep["normB"][i]) <= 1e-14 * metrics.norm1(B) + 1e-300
     Y = Xp[s][0].T
-    assert abs(metrics.norm1(Y) - rep["normY"]) <= 1e-14 * metrics.norm1(Y)
+    for mode, ytol in (("fixed", 1e-14), ("mixed", 2.0 ** -24 * 16)):
+        # mixed: Y = X^s is formed by an FP32 product (eq. (cond-Y)), so its
+        # norm is good to FP32 accuracy; the blocks stay in FP64
+        _, rep = ps.ps_expm(to_dev(A), m, s=s, sigma=0, mode=mode, report=True)
+        for i in range(r + 1):
+            B = sum(c[k] * (Xp[k - s * i][0] + Xp[k - s * i][1]) for k in ranges[i]).T
+            assert abs(metrics.norm1(B) - rep["normB"][i]) <= 1e-14 * metrics.norm1(B) + 1e-300, (mode, i)
+        assert abs(metrics.norm1(Y) - rep["normY"]) <= ytol * metrics.norm1(Y), mode
 
 
 # ------------------------------------------------------------ per-tier GEMM paths
@@ -196,6 +199,42 @@ def test_forced_tier_chains_within_bound(ps, pattern):
         bound += (2 * uin[t] + n * (U64 if t == 0 else U32)) * tail
     bound = 4 * bound / metrics.norm1(Ph) + 1e-13
     assert err <= bound, (err, bound)
+
+
+def test_y_formed_in_fp32_when_the_plan_allows(ps):
+    """Eq. (cond-Y): Y = X^s needs the accuracy of the first lower-precision
+    Horner step.  In mixed mode with FP32 allowed the power table forms Y by
+    an FP32 product; the cast launch forms it in FP64 as well when the plan
+    keeps a Horner product (or the folded step r) in FP64.  The report counts
+    the products by tier."""
+    n, m, s = 256, 30, 6          # r = 5, s | m: step 5 folded into B_4
+    c = coeffs.taylor_exp(m)
+    A = _rand(n, 0.5, 31)
+    Eh, El = oracle.expm_dd(A, c, 0)
+
+    def run(**kw):
+        E, rep = ps.ps_expm(to_dev(A), m, s=s, sigma=0, mode="mixed", report=True, **kw)
+        steps = rep["tier"][1:rep["first_step"] + 1]
+        return to_np(E), rep, steps
+
+    # every step below FP64: Y only in FP32
+    E, rep, steps = run()
+    assert all(t != 0 for t in rep["tier"][1:])
+    assert rep["gemms"][0] == (s - 2) and rep["gemms"][1] == 1 + steps.count(1), (rep["gemms"], steps)
+    assert metrics.rel_err_1(E, Eh, El) <= TOL64
+    # FP32 not allowed: Y in FP64 only
+    E2, rep2, steps2 = run(tier_mask=0b1101)
+    assert rep2["gemms"][0] == (s - 1) + steps2.count(0) and rep2["gemms"][1] == 0, (rep2["gemms"], steps2)
+    assert metrics.rel_err_1(E2, Eh, El) <= TOL64
+    # a Horner step kept in FP64: Y in FP32 and again in FP64, and the fold
+    # c_m Y of step 5 redone with the FP64 Y
+    ov = [0, 0, 3, 3, 3, 3]
+    E3, rep3, _ = run(tier_override=ov)
+    assert rep3["gemms"][0] == (s - 1) + 1 and rep3["gemms"][1] == 1, rep3["gemms"]
+    E4, rep4, _ = run(tier_override=ov, tier_mask=0b1101)
+    assert rep4["gemms"][1] == 0
+    assert metrics.rel_err_1(E3, E4, None) <= 1e-15
+    assert metrics.rel_err_1(E3, Eh, El) <= TOL64
 
 
 # ------------------------------------------------------------ dense n = 1024
