@@ -66,7 +66,12 @@ typedef enum {
 typedef enum { PS_TIER_F64 = 0, PS_TIER_F32 = 1, PS_TIER_BF16 = 2, PS_TIER_FP8 = 3 } ps_tier;
 
 #define PS_MODE_FIXED 0   /* Algorithm 1: every product in the working precision */
-#define PS_MODE_MIXED 1   /* Algorithms 2/3 (fixed s): per-step tiers from the norms */
+#define PS_MODE_MIXED 1   /* Algorithms 2/3 (fixed s): per-step tiers from the norms.
+                             With an FP64 working precision and FP32 allowed, ps_eval /
+                             ps_expm / the batched entry points also form Y = X^s by an
+                             FP32 product (eq. (cond-Y): Y needs the accuracy of the
+                             first lower-precision step) and again in FP64 when the
+                             plan keeps a Horner product in FP64. */
 
 #define PS_RULE_BLOCKS 0  /* tiers from the assembled blocks' 1-norms (Thm 2.1, eq. (choose-ui)) */
 #define PS_RULE_APRIORI 1 /* tiers from coefficient magnitudes times powers of ||X||_1 */
@@ -96,8 +101,9 @@ typedef struct ps_report {
   int tier[PS_MAX_BLOCKS];   /* tier[i]: precision of the product P_i * Y (i = 1..r) */
   double u[PS_MAX_BLOCKS];   /* u_i from eq. (choose-ui) (u_0 = working) */
   double normB[PS_MAX_BLOCKS]; /* ||B_i||_1 of the assembled blocks */
-  double normY;              /* ||X^s||_1 */
-  int gemms[4];              /* GEMMs per tier: powers + Horner + squarings */
+  double normY;              /* ||X^s||_1 (of the FP32-formed Y where mixed mode forms it so) */
+  int gemms[4];              /* GEMMs per tier: powers (Y's product under its tier, counted
+                                twice when it is also formed in FP64) + Horner + squarings */
   float ms_power, ms_assemble, ms_horner, ms_square;  /* profile != 0 only */
   double normX;              /* ||X||_1, X = 2^-sigma A (the first power) */
 } ps_report;
