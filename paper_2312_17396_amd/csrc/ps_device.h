@@ -46,7 +46,7 @@ constexpr int TPA = kTileM / RUNA;           // threads per k-row of a normal A 
 constexpr int TPB = kTileN / RUNB;           // threads per k-row of a transposed B slab
 constexpr int TILE_Q = kTileM * kTileN / NT; // tile elements per thread in the epilogue passes (8)
 
-static_assert(kTileM == 64 && (kTileN == 64 || kTileN == 32), "tile shape");
+static_assert(kTileM == 64 && kTileN == 64, "tile shape");
 static_assert(RUNA % 2 == 0 && RUNB % 2 == 0 && TPA * RUNA == kTileM && TPB * RUNB == kTileN, "slab split");
 
 // Wave layout of an output tile: wave w owns rows [32 (w & 1), +32) and

@@ -12,11 +12,8 @@ namespace psk {
 
 constexpr int kMaxSigma = 500;  // largest number of squarings
 constexpr int kMaxDegree = 255;  // coefficients travel by value in kernel arguments
-#ifndef PS_TILE_N
-#define PS_TILE_N 64
-#endif
 constexpr int kTileM = 64;       // output tile rows of every GEMM kernel
-constexpr int kTileN = PS_TILE_N;  // output tile columns (64 or 32)
+constexpr int kTileN = 64;       // output tile columns
 constexpr int kTile = kTileM;    // row padding unit of the packed layouts
 constexpr int kKPad = 128;       // K padding of the packed low-precision layouts
 constexpr int kRowChunk = 256;   // rows per wave in the column passes
