@@ -78,7 +78,7 @@ int default_s_b(int m) {
   return s;
 }
 
-char err_buf[512];
+thread_local char err_buf[512];   // message of the failing HIP call (per thread, like ps_last_error)
 
 ps_status bad(ps_status st, const char* msg) { return ps_set_error(st, msg); }
 
