@@ -194,18 +194,17 @@ struct Job {
   bool build_powers;     // run the power table (first polynomial only)
   bool skip_square;      // squarings handled by the caller
   int pow_shift = 0;     // power slots hold 2^(-j pow_shift) X_j (prebuilt, exact rescaling)
-  bool y_low = false;    // one polynomial: Y may be formed in FP32 (eq. (cond-Y))
+  bool y32 = false;      // Y = X_s lives in the slot of its FP32 copy (y32_allowed)
 };
 
 // Y = X_s formed by an FP32 product under an FP64 working precision.  By
 // eq. (cond-Y) Y needs the accuracy u_nu of the first lower-precision Horner
 // step; when the plan keeps every Horner product below FP64, FP32 gives it.
-// The plan is only known on the device, so the cast launch forms Y in FP64
-// too whenever the plan keeps a product in FP64 (and the report counts it).
-bool y_in_fp32(const Job& J) {
-  const Layout& L = *J.L;
-  return J.y_low && J.build_powers && J.write_y && L.working == 0 && L.s >= 2 && !L.square_arg &&
-         J.pow_shift == 0 && (J.opts.mode == PS_MODE_MIXED || J.opts.override_tiers) && ((J.opts.mask >> 1) & 1u);
+// The plan is only known on the device, so each polynomial's cast launch
+// forms Y in FP64 too whenever its plan keeps a product in FP64 (and the
+// report counts it).  Decided by the caller for all jobs sharing the powers.
+bool y32_allowed(const Layout& L, const Opts& o) {
+  return L.working == 0 && L.s >= 2 && (o.mode == PS_MODE_MIXED || o.override_tiers) && ((o.mask >> 1) & 1u);
 }
 
 MatArg ws_mat(char* ws, size_t off, int64_t n, size_t stride_bytes, int esize) {
@@ -255,7 +254,7 @@ ps_status run_job(const Job& J, hipStream_t st, float* phase_ms /*4 or null*/) {
     return j == 1 ? J.X1 : ws_mat(J.ws, L.off_pow + (size_t)(j - 2 + (L.square_arg ? 1 : 0)) * L.slot, n, wss, L.esize);
   };
   auto power_alpha = [&](int j) { return (pow_a(j) == 1 ? J.beta : 1.0) * (pow_b(j) == 1 ? J.beta : 1.0); };
-  const bool yl = y_in_fp32(J);
+  const bool yl = J.y32;
   if (J.build_powers && L.s >= 2) {
     // X_j = X_a X_b (a = ceil(j/2), b = floor(j/2)), one grouped launch per
     // level (j in (2^(l-1), 2^l]); X_1 = beta X1 enters through alpha
@@ -406,7 +405,7 @@ ps_status fill_report(const Layout& L, const Job& J, int b, ps_report* rep, hipS
   rep->normX = P.normX;
   rep->gemms[L.working] += L.npow + L.sigma;
   for (int i = L.first_step; i >= 1; --i) rep->gemms[P.tier[i]] += 1;
-  if (y_in_fp32(J)) {   // Y by an FP32 product, again in FP64 if a Horner product is
+  if (J.y32) {   // Y by an FP32 product, again in FP64 if a Horner product is
     bool fp64_step = false;
     for (int i = 1; i <= L.r; ++i) fp64_step = fp64_step || P.tier[i] == L.working;
     rep->gemms[1] += 1;
@@ -701,7 +700,7 @@ static ps_status expm_impl(ps_dtype dtype, int batch, int64_t n, const void* A, 
   J.write_y = true;
   J.build_powers = true;
   J.skip_square = false;
-  J.y_low = true;
+  J.y32 = y32_allowed(L, o);
   hipStream_t st = (hipStream_t)stream;
   float ms[4] = {0, 0, 0, 0};
   if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
@@ -1202,7 +1201,7 @@ ps_status ps_eval_multi(ps_dtype dtype, int64_t n, const void* A, int64_t lda, i
     J.opts = o;
     J.write_y = (t == 0);
     J.build_powers = (t == 0);
-    J.skip_square = true;
+    J.skip_square = true;   // Y stays in FP64: each chain's plan could call for it
     float ms[4] = {0, 0, 0, 0};
     if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
     if (reports)
