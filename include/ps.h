@@ -67,8 +67,8 @@ typedef enum { PS_TIER_F64 = 0, PS_TIER_F32 = 1, PS_TIER_BF16 = 2, PS_TIER_FP8 =
 
 #define PS_MODE_FIXED 0   /* Algorithm 1: every product in the working precision */
 #define PS_MODE_MIXED 1   /* Algorithms 2/3 (fixed s): per-step tiers from the norms.
-                             With an FP64 working precision and FP32 allowed, ps_eval,
-                             ps_expm and the batched entry points form Y = X^s by an
+                             With an FP64 working precision, FP32 allowed and n > 512,
+                             ps_eval, ps_expm and ps_expm_strided_batched form Y = X^s by an
                              FP32 product (eq. (cond-Y): Y needs the accuracy of the
                              first lower-precision step) and again in FP64 when the
                              plan keeps a Horner product in FP64. */

@@ -202,9 +202,12 @@ struct Job {
 // step; when the plan keeps every Horner product below FP64, FP32 gives it.
 // The plan is only known on the device, so each polynomial's cast launch
 // forms Y in FP64 too whenever its plan keeps a product in FP64 (and the
-// report counts it).  Decided by the caller for all jobs sharing the powers.
+// report counts it).  Only for n > 512: below that an n^3 product is bound
+// by latency, so FP32 saves nothing and a second product in FP64 would add
+// its latency.  Decided by the caller for all jobs sharing the powers.
 bool y32_allowed(const Layout& L, const Opts& o) {
-  return L.working == 0 && L.s >= 2 && (o.mode == PS_MODE_MIXED || o.override_tiers) && ((o.mask >> 1) & 1u);
+  return L.working == 0 && L.n > 512 && L.s >= 2 && (o.mode == PS_MODE_MIXED || o.override_tiers) &&
+         ((o.mask >> 1) & 1u);
 }
 
 MatArg ws_mat(char* ws, size_t off, int64_t n, size_t stride_bytes, int esize) {

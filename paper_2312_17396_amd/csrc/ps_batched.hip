@@ -110,14 +110,6 @@ __device__ inline double apriori_cost(const Layout& L, const Coefs& cf, double x
 
 __device__ inline int tiles_m(int64_t n) { return (int)((n + kTileM - 1) / kTileM); }
 
-// Y = X_s formed in FP32 under an FP64 working precision (eq. (cond-Y): Y
-// needs the accuracy of the first lower-precision Horner step), with the
-// same rule as the single-matrix path: mixed mode, FP32 allowed, s >= 2.
-// The cast launch forms Y in FP64 as well when the plan keeps a Horner
-// product in FP64.
-__device__ inline bool y_in_fp32(const BatchArgs& a, const Layout& L) {
-  return L.working == 0 && a.mode == PS_MODE_MIXED && ((a.mask >> 1) & 1u) && L.s >= 2;
-}
 
 // ---- block size: ||X||_1 = 2^-sigma ||A||_1, then the cheaper of the two layouts
 template <typename W>
@@ -227,11 +219,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const W* xa = (pa == 1) ? X1 : pw + (int64_t)(pa - 2) * se;
   const W* xb = (pb == 1) ? X1 : pw + (int64_t)(pb - 2) * se;
   const double alpha = (pa == 1 ? beta : 1.0) * (pb == 1 ? beta : 1.0);
-  if (y_in_fp32(a, L) && j == L.s) {   // Y in FP32, into the slot of its FP32 copy (as the grid path)
-    gemm_tile_f32_of_f64((const double*)xa, n, (const double*)xb, n, (float*)(it.ws + L.off_yf32), n, n,
-                         (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, alpha, smem);
-    return;
-  }
   gemm_tile<W, false, false>(xa, n, xb, n, pw + (int64_t)(j - 2) * se, n, n, n, (int64_t)(tile % ntm) * kTileM,
                              (int64_t)(tile / ntm) * kTileN, alpha, 0, smem);
 }
@@ -260,7 +247,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(W) ==
   aa.ws_stride = 0;
   aa.L = L;
   aa.tier_mask = a.mode == PS_MODE_MIXED ? a.mask : 0u;
-  aa.y_f32 = y_in_fp32(a, L) ? 1 : 0;
+  aa.y_f32 = 0;   // Y in FP64: the grid path forms it in FP32 only above order 512
   assemble_column<W, false>(aa, a.cf, aa.ws, (const W*)it.X1, col, 0);
 }
 
@@ -329,23 +316,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.yfp8s = (const uint8_t*)(ws + L.off_yfp8s);
   const int i = i0 - k;
   const bool cast = (k < 0);
-  bool y64 = false;
-  if (cast && y_in_fp32(a, L)) {
-    for (int q = 1; q <= L.r; ++q) y64 = y64 || P->tier[q] == WT;
-    if (y64) {   // a Horner product (or the folded step r) stays in FP64: Y in FP64 as well
-      const int pa = (L.s + 1) / 2, pb = L.s / 2;
-      const W* X1 = (const W*)it.X1;
-      const double beta = ldexp(1.0, -it.sigma);
-      const W* xa = (pa == 1) ? X1 : pw + (int64_t)(pa - 2) * se;
-      const W* xb = (pb == 1) ? X1 : pw + (int64_t)(pb - 2) * se;
-      gemm_tile<W, false, false>(xa, n, xb, n, (W*)(ws + L.off_pow) + (int64_t)(L.s - 2) * se, n, n, n,
-                                 (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN,
-                                 (pa == 1 ? beta : 1.0) * (pb == 1 ? beta : 1.0), 0, smem);
-    }
-  }
-  h.fy64 = L.s >= 2 ? pw + (int64_t)(L.s - 2) * se : pw;
-  h.fy32 = h.yf32;
-  h.fyc = (y64 && L.trivial_last) ? (double)(W)a.cf.c[L.m] : 0.0;   // redo the fold with Y in FP64
+  h.fy64 = nullptr;
+  h.fy32 = nullptr;
+  h.fyc = 0.0;
   const bool final_out = cast ? (i0 == 0) : (i == 1);
   h.t_in = cast ? -1 : P->tier[i];
   h.t_out = final_out ? WT : P->tier[cast ? i0 : i - 1];
