@@ -305,7 +305,8 @@ ps_status ps_expm_strided_batched(ps_dtype dtype, int batch, int64_t n,
                                   void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Many matrices of uneven sizes in one persistent launch.  Matrix b has order
+ * Many matrices of uneven sizes, each phase one launch for the whole batch
+ * (one hipGraph replay once prepared).  Matrix b has order
  * n[b] (1 <= n[b] <= 256), lives at device pointer A[b] with leading dimension
  * lda[b], and its result goes to E[b] (lde[b]).  Per-matrix block size s[b]
  * (0 = chosen per matrix from {floor(sqrt m), ceil(sqrt m)} by the lower

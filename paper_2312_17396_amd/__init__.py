@@ -496,7 +496,7 @@ def batched_workspace_bytes(mats, m, s=None, dtype=None):
 def ps_expm_batched(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, report=False,
                     outs=None, workspace=None, rule="blocks"):
     """E_b = p(2^-sigma_b A_b)^(2^sigma_b) for a list of square matrices of
-    uneven order (1..256), one persistent launch.  s: None/0 (choose per
+    uneven order (1..256), one launch per phase for the whole batch.  s: None/0 (choose per
     matrix), an int, or a list; sigma: int or list."""
     import torch
     mats = [_check_square(a) for a in mats]

@@ -1,5 +1,5 @@
 // Device building blocks of the PS kernels, shared by the grid kernels
-// (ps_kernels.hip) and the persistent batched kernel (ps_batched.hip).
+// (ps_kernels.hip) and the batched phase kernels (ps_batched.hip).
 // Every function here works on one 64 x kTileN output tile, one column, or
 // one matrix with the NT threads of a workgroup.
 #pragma once

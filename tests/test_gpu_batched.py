@@ -1,5 +1,5 @@
-"""GPU parity of the persistent batched path (many matrices of uneven order
-in one launch) against the single-matrix path and the CPU oracle, and of its
+"""GPU parity of the batched path (many matrices of uneven order, one launch
+per phase for all of them) against the single-matrix path and the CPU oracle, and of its
 captured hipGraph against eager calls."""
 import numpy as np
 import pytest
