@@ -18,6 +18,9 @@ Parts:
                IEEE-tier rounding (section 4.1.1), written independently of
                the library planner.
   metrics.py   the paper's error measure (section 3.3) and cost ratio (eq. (Cr)).
+  solve.py     the quotient r_km = q_km^{-1} p_km of section 4.1 as the textbook
+               LU solve with partial pivoting, and exp in the Pade form with
+               scaling and squaring.
 
 Parity status: every function here is pinned by tests/test_oracle_*.py against
 closed forms, exact integer arithmetic, rational arithmetic, invariants and the
@@ -284,4 +287,4 @@ def expm_ps_f64(A, coef, s, sigma):
     return E
 
 
-from . import coeffs, plan, metrics  # noqa: E402,F401
+from . import coeffs, plan, metrics, solve  # noqa: E402,F401
