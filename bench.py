@@ -349,7 +349,9 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
               m = 18, s chosen per matrix, FP32: the per-phase launches of the whole
               batch replayed from one hipGraph vs a loop of single-matrix calls;
     pade_cos  n = 2048 FP64, A = Q diag(lambda) Q^T: Pade [13/13] p and q from one
-              power table (s = 4) and Taylor cos of degree 12 in A^2 (s = 4);
+              power table (s = 4), exp as q^-1 p (the LU solve on the device;
+              its time is the difference to the pair), and Taylor cos of degree
+              12 in A^2 (s = 4);
     grad      64 FP32 matrices of order 512: forward + hand-written adjoint;
     auto      the dense n = 1024 set with the scaling chosen by the alpha_m bound
               (ps_expm_auto) instead of ceil(log2 ||A||_1);
@@ -434,8 +436,15 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
         for mode in ("fixed", "mixed"):
             tp = _time(lambda: ps.ps_eval_multi(Aq, [p, q], s=4, mode=mode), 5, torch)
             tc = _time(lambda: ps.ps_eval_multi(Aq, [c], s=4, square_arg=True, mode=mode), 5, torch)
+            wse = ps.pade_workspace(Aq, 13, 4, 0)
+            Ee = torch.empty_like(Aq)
+            te = _time(lambda: ps.ps_expm_pade(Aq, 13, s=4, sigma=0, mode=mode, out=Ee, workspace=wse), 5, torch)
             out[mode] = {"pade_pair_ms": round(tp * 1e3, 3), "pade_tflops_credited": round(9 * 2 * 2048 ** 3 / tp / 1e12, 2),
-                         "cos_ms": round(tc * 1e3, 3), "cos_tflops_credited": round(6 * 2 * 2048 ** 3 / tc / 1e12, 2)}
+                         "cos_ms": round(tc * 1e3, 3), "cos_tflops_credited": round(6 * 2 * 2048 ** 3 / tc / 1e12, 2),
+                         "expm_pade_ms": round(te * 1e3, 3),
+                         "solve_ms_by_difference": round((te - tp) * 1e3, 3),
+                         "solve_tflops_credited": round((2 / 3 + 2) * 2048 ** 3 / max(te - tp, 1e-9) / 1e12, 2)}
+            del wse, Ee
         res["pade_cos_2048"] = out
         del Aq
     # ---- adjoint batch

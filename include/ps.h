@@ -372,6 +372,46 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n,
                            int recompute, const ps_opts* opts,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Linear solve Q X = P (the quotient r_km = q_km^{-1} p_km of the Pade
+ * approximant, section 4.1).  LU factorisation with partial pivoting: at
+ * step k the row of largest |entry| in column k at or below row k (the
+ * lowest such row on ties; NaN entries are never chosen) is exchanged with
+ * row k over the full width.
+ *   Q: device, n x n (ldq >= n), overwritten by the factors: the multipliers
+ *      of the unit lower factor L below the diagonal, U on and above it.
+ *   P: device, n x nrhs (ldp >= n), overwritten by X; nrhs = 0 factors only.
+ *   ipiv: NULL, or a device array of n int32: ipiv[k] = the row (0-based)
+ *      exchanged with row k at step k, as LAPACK's getrf (which is 1-based).
+ *   info: NULL, or a HOST int that receives 0, or k + 1 when U[k,k] is the
+ *      first exactly zero pivot (then X holds non-finite values); a non-NULL
+ *      info synchronises the stream.
+ * FP64 and FP32, 1 <= n <= 8192 (PS_ERR_UNSUPPORTED above).  Row-major
+ * data solves Q^T Z = P^T instead (Z^T = P Q^{-1}, the same matrix when P
+ * and Q commute, as two polynomials in one matrix do).  Q, P, ipiv and the
+ * workspace must not overlap.
+ * ------------------------------------------------------------------------- */
+ps_status ps_workspace_size_solve(ps_dtype dtype, int64_t n, size_t* bytes);
+ps_status ps_solve(ps_dtype dtype, int64_t n, void* Q, int64_t ldq, int64_t nrhs, void* P, int64_t ldp,
+                   int32_t* ipiv, int* info, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * exp(A) in the Pade form inside scaling and squaring (section 4.1):
+ * E = r_m(X)^(2^sigma), X = 2^-sigma A, r_m = q_m^{-1} p_m the diagonal
+ * [m/m] Pade approximant (1 <= m <= 60; coefficients of ps_coef_pade_exp).
+ * p_m and q_m share one power table (as ps_eval_multi, block size s, 0 =
+ * ceil(sqrt m)), each with its own plan in mixed mode (opts as for
+ * ps_eval_multi; tier_override unsupported); the solve (ps_solve's
+ * factorisation) and the squarings run in the working precision.  reports:
+ * NULL or a host array of 2 (p_m, q_m).  The caller picks m and sigma so that
+ * q_m(X) is nonsingular (a singular q_m gives non-finite values; nothing is
+ * reported).  FP64 and FP32, n <= 8192.
+ * ------------------------------------------------------------------------- */
+ps_status ps_workspace_size_pade(ps_dtype dtype, int64_t n, int m, int s, int sigma, size_t* bytes);
+ps_status ps_expm_pade(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m, int s, int sigma,
+                       void* E, int64_t lde, const ps_opts* opts, ps_report* reports,
+                       void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

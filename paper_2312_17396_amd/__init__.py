@@ -100,6 +100,10 @@ _SIGS = {
                             _i64p, _op, _vp, _sz, _vp, ctypes.POINTER(_vp)], _i),
     "ps_batched_launch": ([_vp, _vp], _i),
     "ps_batched_destroy": ([_vp], _i),
+    "ps_workspace_size_solve": ([_i, _i64, _szp], _i),
+    "ps_solve": ([_i, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _ip, _vp, _sz, _vp], _i),
+    "ps_workspace_size_pade": ([_i, _i64, _i, _i, _i, _szp], _i),
+    "ps_expm_pade": ([_i, _i64, _vp, _i64, _i, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
     "ps_workspace_size_backward": ([_i, _i, _i64, _i, _i, _i, _i, _szp], _i),
     "ps_expm_backward": ([_i, _i, _i64, _vp, _i64, _i64, _vp, _i64, _i64, _dp, _i, _i, _i, _vp, _i64, _i64, _i,
                           _op, _vp, _sz, _vp], _i),
@@ -444,6 +448,63 @@ def ps_eval_multi(A, coefs, s=0, square_arg=False, mode="fixed", tier_mask=0, de
     if reps is not None:
         return outs, [r.to_dict() for r in reps]
     return outs
+
+
+# ---------------------------------------------------------------------------
+# linear solve and the Pade form of exp
+# ---------------------------------------------------------------------------
+def ps_solve(Q, P=None):
+    """X with Q X = P by LU with partial pivoting (torch row-major tensors;
+    the binding hands the library their column-major copies).  Returns
+    (X, LU, ipiv, info): LU holds L's multipliers below the diagonal and U on
+    and above it, ipiv[k] the row exchanged with row k at step k (0-based),
+    info 0 or k + 1 for the first zero pivot U[k,k].  P=None factors only
+    (X is None)."""
+    import torch
+    Q = _check_square(Q)
+    n = Q.shape[0]
+    dt = _dtype_code(Q)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_solve(dt, n, ctypes.byref(nbytes)))
+    ws, wsp, wsb = _workspace(nbytes.value, Q.device)
+    Qc = Q.t().contiguous()
+    nrhs, Pc = 0, None
+    if P is not None:
+        if P.dim() != 2 or P.shape[0] != n or P.dtype != Q.dtype or P.device != Q.device:
+            raise PSError("P must be n x k with Q's dtype and device")
+        nrhs = P.shape[1]
+        Pc = P.t().contiguous()
+    piv = torch.empty(n, dtype=torch.int32, device=Q.device)
+    info = ctypes.c_int(0)
+    _check(lib().ps_solve(dt, n, Qc.data_ptr(), n, nrhs, Pc.data_ptr() if Pc is not None else None, n,
+                          piv.data_ptr(), ctypes.byref(info), wsp, wsb, _stream_ptr(Q.device)))
+    return (Pc.t() if Pc is not None else None), Qc.t(), piv, info.value
+
+
+def pade_workspace(A, m, s=0, sigma=0):
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_pade(_dtype_code(A), A.shape[0], int(m), int(s), int(sigma),
+                                        ctypes.byref(nbytes)))
+    return _workspace(nbytes.value, A.device)
+
+
+def ps_expm_pade(A, m, s=0, sigma=0, mode="fixed", tier_mask=0, delta=10.0, report=False, profile=False, out=None,
+                 workspace=None, rule="blocks"):
+    """E = r_m(2^-sigma A)^(2^sigma), r_m = q_m^{-1} p_m the [m/m] Pade
+    approximant of exp: p_m and q_m from one power table, then the LU solve
+    and the squarings, all on the device."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    ws, wsp, wsb = workspace if workspace is not None else pade_workspace(A, m, s, sigma)
+    E = _check_out(out, A) if out is not None else torch.empty_like(A)
+    o, _k = _opts(mode, tier_mask, delta, None, profile, rule=rule)
+    reps = (ps_report * 2)() if (report or profile) else None
+    _check(lib().ps_expm_pade(_dtype_code(A), n, A.data_ptr(), n, int(m), int(s), int(sigma), E.data_ptr(), n,
+                              ctypes.byref(o), reps, wsp, wsb, _stream_ptr(A.device)))
+    if reps is not None:
+        return E, [r.to_dict() for r in reps]
+    return E
 
 
 # ---------------------------------------------------------------------------

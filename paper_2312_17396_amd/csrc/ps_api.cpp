@@ -1213,4 +1213,129 @@ ps_status ps_eval_multi(ps_dtype dtype, int64_t n, const void* A, int64_t lda, i
   return PS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// linear solve and the Pade form of exp
+// ---------------------------------------------------------------------------
+ps_status ps_workspace_size_solve(ps_dtype dtype, int64_t n, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  if (dtype != PS_F64 && dtype != PS_F32) return fail(PS_ERR_UNSUPPORTED, "ps_solve: FP64 or FP32 only");
+  if (n < 1) return fail(PS_ERR_ARG, "n = %lld < 1", (long long)n);
+  if (n > kMaxSolveOrder) return fail(PS_ERR_UNSUPPORTED, "ps_solve: n = %lld above %lld", (long long)n,
+                                      (long long)kMaxSolveOrder);
+  *bytes = lu_solve_ws_bytes(n);
+  return PS_OK;
+}
+
+ps_status ps_solve(ps_dtype dtype, int64_t n, void* Q, int64_t ldq, int64_t nrhs, void* P, int64_t ldp,
+                   int32_t* ipiv, int* info, void* ws, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  if (ps_status e = ps_workspace_size_solve(dtype, n, &need)) return e;
+  if (!Q) return fail(PS_ERR_ARG, "Q == NULL");
+  if (ldq < n) return fail(PS_ERR_ARG, "ldq < n");
+  if (nrhs < 0 || nrhs > (int64_t)1 << 30) return fail(PS_ERR_ARG, "nrhs = %lld out of range", (long long)nrhs);
+  if (nrhs > 0 && !P) return fail(PS_ERR_ARG, "P == NULL");
+  if (nrhs > 0 && ldp < n) return fail(PS_ERR_ARG, "ldp < n");
+  const int esize = dtype == PS_F64 ? 8 : 4;
+  const size_t spanQ = mat_span_bytes(n, ldq, esize);
+  const size_t spanP = nrhs > 0 ? (size_t)((nrhs - 1) * ldp + n) * esize : 0;
+  if (nrhs > 0 && overlap(Q, spanQ, P, spanP)) return fail(PS_ERR_ALIAS, "P overlaps Q");
+  if (ps_status e = check_ws(ws, ws_bytes, need)) return e;
+  if (overlap(ws, need, Q, spanQ) || (nrhs > 0 && overlap(ws, need, P, spanP)))
+    return fail(PS_ERR_ALIAS, "the workspace overlaps Q or P");
+  if (ipiv && (overlap(ipiv, (size_t)n * 4, Q, spanQ) || (nrhs > 0 && overlap(ipiv, (size_t)n * 4, P, spanP)) ||
+               overlap(ipiv, (size_t)n * 4, ws, need)))
+    return fail(PS_ERR_ALIAS, "ipiv overlaps Q, P or the workspace");
+  hipStream_t st = (hipStream_t)stream;
+  PS_HIP(launch_lu_solve(dtype == PS_F64 ? 0 : 1, n, Q, ldq, nrhs, P, ldp, ipiv, (char*)ws, st));
+  if (info) {
+    PS_HIP(hipMemcpyAsync(info, ws, sizeof(int), hipMemcpyDeviceToHost, st));
+    PS_HIP(hipStreamSynchronize(st));
+  }
+  return PS_OK;
+}
+
+static ps_status pade_layout(ps_dtype dtype, int64_t n, int m, int* s, std::vector<Layout>& Ls, size_t* total,
+                             size_t* off_q, size_t* off_w, size_t* off_solve) {
+  if (dtype != PS_F64 && dtype != PS_F32) return fail(PS_ERR_UNSUPPORTED, "ps_expm_pade: FP64 or FP32 only");
+  if (m < 1 || m > 60) return fail(PS_ERR_ARG, "Pade degree m = %d out of range [1, 60]", m);
+  if (n > kMaxSolveOrder) return fail(PS_ERR_UNSUPPORTED, "ps_expm_pade: n = %lld above %lld", (long long)n,
+                                      (long long)kMaxSolveOrder);
+  const int degrees[2] = {m, m};
+  size_t base = 0;
+  if (ps_status e = multi_layouts(dtype, n, 2, degrees, s, 0, Ls, &base)) return e;
+  const size_t slot = Ls[0].slot;
+  *off_q = base;
+  *off_w = base + slot;
+  *off_solve = base + 2 * slot;
+  *total = *off_solve + al256(lu_solve_ws_bytes(n));
+  return PS_OK;
+}
+
+ps_status ps_workspace_size_pade(ps_dtype dtype, int64_t n, int m, int s, int sigma, size_t* bytes) {
+  if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
+  if (sigma < 0 || sigma > kMaxSigma) return fail(PS_ERR_ARG, "sigma = %d out of range", sigma);
+  std::vector<Layout> Ls;
+  size_t oq, ow, os;
+  return pade_layout(dtype, n, m, &s, Ls, bytes, &oq, &ow, &os);
+}
+
+ps_status ps_expm_pade(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m, int s, int sigma, void* E,
+                       int64_t lde, const ps_opts* opts, ps_report* reports, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (sigma < 0 || sigma > kMaxSigma) return fail(PS_ERR_ARG, "sigma = %d out of range", sigma);
+  std::vector<Layout> Ls;
+  size_t total = 0, off_q = 0, off_w = 0, off_solve = 0;
+  if (ps_status e = pade_layout(dtype, n, m, &s, Ls, &total, &off_q, &off_w, &off_solve)) return e;
+  if (!A || !E) return fail(PS_ERR_ARG, "NULL argument");
+  if (lda < n || lde < n) return fail(PS_ERR_ARG, "lda or lde < n");
+  const int esize = dtype == PS_F64 ? 8 : 4;
+  const size_t spanA = mat_span_bytes(n, lda, esize), spanE = mat_span_bytes(n, lde, esize);
+  if (overlap(A, spanA, E, spanE)) return fail(PS_ERR_ALIAS, "E overlaps A");
+  if (ps_status e = check_ws(ws, ws_bytes, total)) return e;
+  if (overlap(ws, total, E, spanE) || overlap(ws, total, A, spanA))
+    return fail(PS_ERR_ALIAS, "the workspace overlaps A or E");
+  Opts o = read_opts(opts, dtype == PS_F64 ? 0 : 1);
+  if (ps_status e = check_opts(o)) return e;
+  if (o.override_tiers) return fail(PS_ERR_UNSUPPORTED, "tier_override is not supported by ps_expm_pade");
+  double pc[61], qc[61];
+  if (ps_status e = ps_coef_pade_exp(m, pc, qc)) return e;
+  hipStream_t st = (hipStream_t)stream;
+  const int W = dtype == PS_F64 ? 0 : 1;
+  char* w = (char*)ws;
+  // the squarings alternate between E and a workspace slot and end in E, so
+  // r_m lands in E when sigma is even and in the slot when it is odd
+  MatArg Eo{E, lde, 0};
+  MatArg Wk = ws_mat(w, off_w, n, total, esize);
+  MatArg Qk = ws_mat(w, off_q, n, total, esize);
+  MatArg R0 = (sigma % 2 == 0) ? Eo : Wk;
+  for (int t = 0; t < 2; ++t) {
+    Job J;
+    J.L = &Ls[t];
+    J.batch = 1;
+    J.X1 = MatArg{A, lda, 0};
+    J.beta = ldexp(1.0, -sigma);
+    J.coef = t == 0 ? pc : qc;
+    J.out = t == 0 ? R0 : Qk;
+    J.ws = w;
+    J.ws_stride = total;
+    J.opts = o;
+    J.write_y = (t == 0);
+    J.build_powers = (t == 0);
+    J.skip_square = true;
+    float ms[4] = {0, 0, 0, 0};
+    if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
+    if (reports)
+      if (ps_status e = fill_report(Ls[t], J, 0, &reports[t], st, o.profile ? ms : nullptr)) return e;
+  }
+  // r_m = q_m^{-1} p_m (section 4.1)
+  PS_HIP(launch_lu_solve(W, n, (void*)Qk.p, n, n, (void*)R0.p, R0.ld, nullptr, w + off_solve, st));
+  MatArg cur = R0;
+  for (int i = 0; i < sigma; ++i) {
+    MatArg dst = (cur.p == E) ? Wk : Eo;
+    PS_HIP(launch_gemm(W, n, 1, cur, 0, cur, 0, dst, 1.0, 0, st));
+    cur = dst;
+  }
+  return PS_OK;
+}
+
 }  // extern "C"

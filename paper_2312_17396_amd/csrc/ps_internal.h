@@ -245,4 +245,13 @@ hipError_t launch_tgemm(int working, const TGemmArgs& a, int batch, hipStream_t 
 hipError_t launch_axpby(int working, int64_t n, int batch, MatArg x, MatArg y, MatArg dst, double alpha,
                         hipStream_t st);
 
+// LU solve Q X = P (ps_solve.hip): Q (n x n) is overwritten by its factors
+// (unit L below the diagonal, U on and above), P (n x nrhs) by X.  ws holds
+// lu_solve_ws_bytes(n): the first int is the first zero pivot (1-based, 0 =
+// none) and the pivots follow unless piv_out (device, n ints) is given.
+size_t lu_solve_ws_bytes(int64_t n);
+constexpr int64_t kMaxSolveOrder = 8192;
+hipError_t launch_lu_solve(int working, int64_t n, void* Q, int64_t ldq, int64_t nrhs, void* P, int64_t ldp,
+                           int* piv_out, char* ws, hipStream_t st);
+
 }  // namespace psk

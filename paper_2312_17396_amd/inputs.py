@@ -101,3 +101,8 @@ def class_b(n: int, k: int = 0) -> np.ndarray:
 
 def shifted_1024(t: float = 0.5, eps: float = 0.05, n: int = 1024) -> np.ndarray:
     return -t * np.eye(n) + rescaled_normal(n, eps, rng(8))
+
+
+def gaussian(rows: int, cols: int, k: int = 0) -> np.ndarray:
+    """N(0,1) entries: the matrices and right-hand sides of the linear solve."""
+    return rng(6, k).standard_normal((rows, cols))

@@ -132,3 +132,50 @@ def test_rule_names_checked_on_the_host():
     assert o.rule == 0
     with pytest.raises(ps.PSError):
         ps._opts("mixed", rule="nonsense")
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(n=0), -1), (dict(n=9000), -5), (dict(dtype=2), -5), (dict(Q=0), -1), (dict(ldq=3, n=4), -1),
+    (dict(nrhs=-1), -1), (dict(P=0), -1), (dict(ldp=2, n=4), -1), (dict(alias=True), -2),
+    (dict(ws_small=True), -3), (dict(ws_misaligned=True), -3), (dict(piv_alias=True), -2),
+])
+def test_solve_argument_validation(ps, args, code):
+    L = ps.lib()
+    n = args.get("n", 4)
+    Q = args.get("Q", 0x10000000)
+    P = Q if args.get("alias") else args.get("P", 0x20000000)
+    ws = 0x40000010 if args.get("ws_misaligned") else 0x40000000
+    wsb = 16 if args.get("ws_small") else (1 << 30)
+    piv = 0x40000000 if args.get("piv_alias") else 0x50000000
+    st = L.ps_solve(args.get("dtype", 0), n, Q, args.get("ldq", n), args.get("nrhs", 3), P, args.get("ldp", n),
+                    piv, None, ws, wsb, None)
+    assert st == code, (st, L.ps_last_error())
+    assert L.ps_last_error()
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(m=0), -1), (dict(m=61), -1), (dict(sigma=-1), -1), (dict(dtype=2), -5), (dict(n=9000), -5),
+    (dict(alias=True), -2), (dict(ws_small=True), -3), (dict(A=0), -1), (dict(s=9, m=6), -1),
+])
+def test_expm_pade_argument_validation(ps, args, code):
+    L = ps.lib()
+    n = args.get("n", 4)
+    A = args.get("A", 0x10000000)
+    E = A if args.get("alias") and A else 0x20000000
+    wsb = 16 if args.get("ws_small") else (1 << 34)
+    st = L.ps_expm_pade(args.get("dtype", 0), n, A, n, args.get("m", 13), args.get("s", 0), args.get("sigma", 0),
+                        E, n, None, None, 0x400000000, wsb, None)
+    assert st == code, (st, L.ps_last_error())
+    assert L.ps_last_error()
+
+
+def test_solve_and_pade_workspace_sizes(ps):
+    L = ps.lib()
+    sz = ctypes.c_size_t()
+    assert L.ps_workspace_size_solve(0, 2048, ctypes.byref(sz)) == 0
+    assert sz.value >= 2048 * 4 and sz.value % 256 == 0
+    multi, pade = ctypes.c_size_t(), ctypes.c_size_t()
+    deg = (ctypes.c_int * 2)(13, 13)
+    assert L.ps_workspace_size_multi(0, 2048, 2, deg, 4, 0, ctypes.byref(multi)) == 0
+    assert L.ps_workspace_size_pade(0, 2048, 13, 4, 2, ctypes.byref(pade)) == 0
+    assert pade.value >= multi.value + 2 * 2048 * 2048 * 8 + sz.value

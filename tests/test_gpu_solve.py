@@ -1,0 +1,165 @@
+"""GPU parity of the linear solve (LU with partial pivoting, ps_solve) and of
+exp in the Pade form (ps_expm_pade: r_m = q_m^{-1} p_m, section 4.1, inside
+scaling and squaring) against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import solve as osolve
+from paper_2312_17396_amd import inputs
+
+from helpers import U32, U64, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ps():
+    import paper_2312_17396_amd as ps
+    ps.lib()
+    return ps
+
+
+def _apply_piv(Q, piv):
+    Q = np.array(Q, copy=True)
+    for k, p in enumerate(piv):
+        if p != k:
+            Q[[k, p], :] = Q[[p, k], :]
+    return Q
+
+
+# orders: one panel, a panel boundary, several panels with ragged tails, and
+# the two- and four-rows-per-thread panels (n - k0 > 1024, > 2048)
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (5, 3), (24, 24), (63, 7), (64, 64), (100, 100), (257, 40),
+                                    (1030, 1030), (2100, 9)])
+def test_solve_fp64_matches_oracle(ps, n, nrhs):
+    import torch
+    Q = inputs.gaussian(n, n, n)
+    P = inputs.gaussian(n, nrhs, n + 1)
+    X, LU, piv, info = ps.ps_solve(to_dev(Q), to_dev(P))
+    torch.cuda.synchronize()
+    X, LU, piv = to_np(X), to_np(LU), piv.cpu().numpy()
+    LUo, pivo, infoo = osolve.lu_pp(Q)
+    assert info == infoo == 0
+    np.testing.assert_array_equal(piv, pivo)
+    L = np.tril(LU, -1) + np.eye(n)
+    Um = np.triu(LU)
+    assert np.max(np.abs(L)) <= 1.0
+    back = np.linalg.norm(_apply_piv(Q, piv) - L @ Um, 1) / (np.linalg.norm(Q, 1))
+    assert back <= 4 * n * U64 * max(1.0, np.max(np.abs(Um)) / np.max(np.abs(Q)))
+    Xo = osolve.lu_solve(LUo, pivo, P)
+    kappa = np.linalg.cond(Q, 1)
+    err = np.linalg.norm(X - Xo, 1) / np.linalg.norm(Xo, 1)
+    assert err <= 8 * n * kappa * U64, (err, kappa)
+
+
+@pytest.mark.parametrize("n", [40, 300, 1100])
+def test_solve_fp32(ps, n):
+    import torch
+    Q = inputs.gaussian(n, n, 50 + n) + 4.0 * np.sqrt(n) * np.eye(n)
+    P = inputs.gaussian(n, 16, 51 + n)
+    X, LU, piv, info = ps.ps_solve(to_dev(Q, torch.float32), to_dev(P, torch.float32))
+    torch.cuda.synchronize()
+    Q32 = Q.astype(np.float32).astype(np.float64)
+    P32 = P.astype(np.float32).astype(np.float64)
+    Xo, _ = osolve.solve(Q32, P32)
+    assert info == 0
+    err = np.linalg.norm(to_np(X) - Xo, 1) / np.linalg.norm(Xo, 1)
+    assert err <= 8 * n * np.linalg.cond(Q32, 1) * U32, err
+
+
+def test_solve_factor_only_and_zero_pivot(ps):
+    import torch
+    n = 70
+    Q = inputs.gaussian(n, n, 7)
+    Q[:, 33] = 0.0
+    Q[:, 50] = 0.0
+    _, LU, piv, info = ps.ps_solve(to_dev(Q))
+    torch.cuda.synchronize()
+    LUo, pivo, infoo = osolve.lu_pp(Q)
+    assert info == infoo == 34
+    np.testing.assert_array_equal(piv.cpu().numpy(), pivo)
+    assert np.all(np.isfinite(to_np(LU)))
+
+
+def test_solve_permutation_exact(ps):
+    import torch
+    n = 200
+    perm = np.random.default_rng(4).permutation(n)
+    Q = np.eye(n)[perm]
+    P = inputs.gaussian(n, 5, 9)
+    X, _, _, info = ps.ps_solve(to_dev(Q), to_dev(P))
+    torch.cuda.synchronize()
+    assert info == 0
+    np.testing.assert_array_equal(to_np(X), Q.T @ P)
+
+
+def test_solve_full_size_property(ps):
+    """n = 4100: the first panels hold eight rows per thread (n - k0 > 4096);
+    checked by the residual and the backward error of the factors."""
+    import torch
+    n = 4100
+    g = torch.Generator(device="cuda:0").manual_seed(11)
+    Q = torch.randn(n, n, dtype=torch.float64, device="cuda:0", generator=g)
+    P = torch.randn(n, 8, dtype=torch.float64, device="cuda:0", generator=g)
+    X, LU, piv, info = ps.ps_solve(Q, P)
+    torch.cuda.synchronize()
+    assert info == 0
+    pv = piv.cpu().numpy()
+    assert np.all((pv >= np.arange(n)) & (pv < n))
+    res = torch.linalg.matrix_norm(Q @ X - P, 1) / (torch.linalg.matrix_norm(Q, 1) * torch.linalg.matrix_norm(X, 1))
+    assert float(res) <= 4 * n * U64
+    L = torch.tril(LU, -1) + torch.eye(n, dtype=LU.dtype, device=LU.device)
+    assert float(L.abs().max()) <= 1.0
+    Qp = Q.clone()
+    for k in range(n):                      # row exchanges on the host order
+        p = int(pv[k])
+        if p != k:
+            Qp[[k, p], :] = Qp[[p, k], :]
+    back = torch.linalg.matrix_norm(Qp - L @ torch.triu(LU), 1) / torch.linalg.matrix_norm(Q, 1)
+    assert float(back) <= 4 * n * U64 * float(torch.triu(LU).abs().max() / Q.abs().max())
+
+
+@pytest.mark.parametrize("n,m,sigma,mode", [(50, 13, 2, "fixed"), (50, 7, 0, "mixed"), (300, 13, 1, "mixed"),
+                                             (1030, 13, 0, "fixed"), (1030, 13, 3, "mixed")])
+def test_expm_pade_fp64_matches_oracle(ps, n, m, sigma, mode):
+    import torch
+    A = inputs.rescaled_normal(n, 2.0 ** sigma * 3.0, inputs.rng(7, n + m))
+    E = ps.ps_expm_pade(to_dev(A), m, sigma=sigma, mode=mode)
+    torch.cuda.synchronize()
+    Eo = osolve.expm_pade(A, m, sigma)
+    err = np.linalg.norm(to_np(E) - Eo, 1) / np.linalg.norm(Eo, 1)
+    assert err <= (1 + sigma) * 2e-14 * max(1.0, np.sqrt(n / 50)), err
+
+
+def test_expm_pade_fp32(ps):
+    import torch
+    A = inputs.rescaled_normal(200, 2.0, inputs.rng(7, 1))
+    E = ps.ps_expm_pade(to_dev(A, torch.float32), 9, sigma=0, mode="mixed")
+    torch.cuda.synchronize()
+    Eo = osolve.expm_pade(A.astype(np.float32).astype(np.float64), 9, 0)
+    assert np.linalg.norm(to_np(E) - Eo, 1) / np.linalg.norm(Eo, 1) <= 2e-5
+
+
+def test_expm_pade_odd_even_sigma_and_reports(ps):
+    """The squarings alternate between E and a workspace slot; both parities
+    end in E.  Reports come back for p_m and q_m."""
+    import torch
+    A = inputs.rescaled_normal(96, 10.0, inputs.rng(7, 2))
+    for sigma in (3, 4):
+        E, reps = ps.ps_expm_pade(to_dev(A), 13, sigma=sigma, mode="mixed", report=True)
+        torch.cuda.synchronize()
+        Eo = osolve.expm_pade(A, 13, sigma)
+        assert np.linalg.norm(to_np(E) - Eo, 1) / np.linalg.norm(Eo, 1) <= 2e-13
+        assert len(reps) == 2 and reps[0]["s"] == reps[1]["s"] == 4
+
+
+def test_expm_pade_2048_against_taylor(ps):
+    """The Pade evaluation at the 2048 order, checked against the Taylor
+    evaluation (m = 30) of the same matrix: both approximate exp(A) to u."""
+    import torch
+    A = to_dev(inputs.orthosim_2048())
+    E1 = ps.ps_expm_pade(A, 13, s=4, sigma=0, mode="mixed")
+    E2 = ps.ps_expm(A, 30, s=6, sigma=1, mode="fixed")
+    torch.cuda.synchronize()
+    d = float(torch.linalg.matrix_norm(E1 - E2, 1) / torch.linalg.matrix_norm(E2, 1))
+    assert d <= 1e-13, d

@@ -1,8 +1,8 @@
 """The oracle's pins have teeth: plausible slips are planted in copies of the
 oracle (a dropped term, a wrong sign, an index off by one, a transposed
 operand, a wrong block boundary, a missing squaring, a wrong tier rule), and
-every such copy must fail at least one pin of tests/test_oracle_pins.py or
-tests/test_oracle_arith.py.
+every such copy must fail at least one pin of tests/test_oracle_pins.py,
+tests/test_oracle_arith.py or tests/test_oracle_solve.py.
 
 Each mutant is a copy of the whole oracle package in a temporary directory
 with one textual change (its C part is recompiled there); the pin files run
@@ -19,7 +19,7 @@ import tempfile
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-PIN_FILES = ["test_oracle_pins.py", "test_oracle_arith.py"]
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_arith.py", "test_oracle_solve.py"]
 
 # (label, file in oracle/, exact text, replacement); each text occurs once.
 # Mutations that cannot change any result are not listed: e.g. counting the
@@ -143,6 +143,24 @@ MUTANTS = [
     ("degree selection: q(q+1) candidates left out", "metrics.py",
      "cands.append(q * (q + 1))", "pass"),
     # the adjoint (block upper-triangular argument)
+    # linear solve and the Pade form
+    ("LU pivot by signed value instead of magnitude", "solve.py",
+     "p = k + int(np.argmax(np.abs(A[k:, k])))", "p = k + int(np.argmax(A[k:, k]))"),
+    ("LU exchanges only the trailing columns", "solve.py",
+     "A[[k, p], :] = A[[p, k], :]", "A[[k, p], k:] = A[[p, k], k:]"),
+    ("LU multipliers not divided by the pivot", "solve.py",
+     "A[k + 1:, k] = A[k + 1:, k] / d", "A[k + 1:, k] = A[k + 1:, k]"),
+    ("LU update with the wrong sign", "solve.py",
+     "A[k + 1:, k + 1:] -= np.outer(A[k + 1:, k], A[k, k + 1:])",
+     "A[k + 1:, k + 1:] += np.outer(A[k + 1:, k], A[k, k + 1:])"),
+    ("LU zero pivot recorded 0-based", "solve.py", "info = k + 1", "info = k"),
+    ("solve skips the row exchanges", "solve.py", "            X[[k, p], :] = X[[p, k], :]", "            pass"),
+    ("back substitution without the division", "solve.py",
+     "X[k, :] = X[k, :] / LU[k, k]", "X[k, :] = X[k, :]"),
+    ("forward substitution with the transposed factor", "solve.py",
+     "X[k + 1:, :] -= np.outer(LU[k + 1:, k], X[k, :])", "X[k + 1:, :] -= np.outer(LU[k, k + 1:], X[k, :])"),
+    ("Pade exp as p q^-1 with q and p swapped", "solve.py", "R, _ = solve(Qm, P)", "R, _ = solve(P, Qm)"),
+    ("Pade exp: one squaring missing", "solve.py", "for _ in range(int(sigma)):", "for _ in range(int(sigma) - 1):"),
     ("gradient oracle without the transposes", "__init__.py",
      "Z[:n, :n] = A.T\n    Z[n:, n:] = A.T", "Z[:n, :n] = A\n    Z[n:, n:] = A"),
     ("gradient oracle with G transposed", "__init__.py",
