@@ -7,8 +7,9 @@
 // L^{-1} Pi P and only the back substitution with U remains.
 //
 // Kernels (working type T = double or float):
-//   k_lu_panel       one 1024-thread workgroup factors the (n - k0) x nb panel
-//                    held in registers (thread t owns rows k0 + t + 1024 q);
+//   k_lu_panel       one workgroup (1024 threads; 256 or 512 for panels of
+//                    at most that many rows) factors the (n - k0) x nb panel
+//                    held in registers (thread t owns rows k0 + t + NT q);
 //                    per column a workgroup arg-max picks the pivot (largest
 //                    |entry|, lowest row on ties), the two rows are exchanged
 //                    through LDS, the multipliers are formed by division and
@@ -18,7 +19,8 @@
 //                    the gather list applied in one load/store round, then,
 //                    right of the panel, the unit-lower triangular solve with
 //                    the panel's L11 (lanes = rows, shuffles for the pivots).
-//   k_lu_update      C -= A B with K <= 64 for 64 x 64 tiles of C, 256
+//   k_lu_update      C -= A B with K <= 32 (panels) or 64 (back
+//                    substitution, LDS sized for each) for 64 x 64 tiles of C, 256
 //                    threads, FMA in the working type (HBM bound: every C
 //                    element is read and written once per panel).
 //   k_lu_trsm_upper  back substitution with a <= 64-row diagonal block of U,
@@ -40,11 +42,10 @@ __global__ void k_fill_int(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
-template <typename T, int R, int NB>
-__global__ __launch_bounds__(kPanelThreads) void k_lu_panel(T* __restrict__ Q, int64_t ld, int n, int k0,
-                                                           int* __restrict__ piv, int* __restrict__ list,
-                                                           int* __restrict__ info) {
-  constexpr int NT = kPanelThreads;
+template <typename T, int R, int NB, int NT>
+__global__ __launch_bounds__(NT) void k_lu_panel(T* __restrict__ Q, int64_t ld, int n, int k0,
+                                                int* __restrict__ piv, int* __restrict__ list,
+                                                int* __restrict__ info) {
   constexpr int NW = NT / 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (n - k0 > R * NT || n <= k0) return;   // the host never launches this
@@ -53,7 +54,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(T* __restrict__ Q, i
   __shared__ int s_row[NW];
   __shared__ T s_prow[NB], s_krow[NB];
   __shared__ int s_piv[NB];
-  __shared__ int s_pos[2 * NB], s_org[2 * NB];
 
   T a[R][NB];
 #pragma unroll
@@ -125,7 +125,6 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(T* __restrict__ Q, i
       const T d = s_prow[j];
       if (t == 0) {
         s_piv[j] = p;
-        piv[kk] = p;
         if (d == T(0) && first_zero == 0) first_zero = kk + 1;
       }
       // multipliers and the rank-one update of the panel's remaining columns
@@ -153,24 +152,35 @@ __global__ __launch_bounds__(kPanelThreads) void k_lu_panel(T* __restrict__ Q, i
         if (jj < nbe) Q[row + (int64_t)(k0 + jj) * ld] = a[q][jj];
     }
   }
-  // the panel's exchanges as one gather: new row s_pos[i] <- old row s_org[i]
-  if (t == 0) {
+  __syncthreads();   // s_piv (written by thread 0) is read by all of wave 0
+  // the panel's exchanges as one gather: new row pos <- old row org, one
+  // touched row per lane of wave 0 (rows k0 .. k0 + nbe - 1 in lanes 0 ..
+  // nbe - 1, then each pivot row from below the panel's block)
+  if (w == 0) {
+    if (lane < nbe) piv[k0 + lane] = s_piv[lane];
+    int pos = lane < nbe ? k0 + lane : -1;
+    int org = pos;
     int cnt = nbe;
-    for (int i = 0; i < nbe; ++i) { s_pos[i] = k0 + i; s_org[i] = k0 + i; }
     for (int j = 0; j < nbe; ++j) {
       const int p = s_piv[j];
       if (p == k0 + j) continue;
-      int idx = -1;
-      for (int i = 0; i < cnt; ++i)
-        if (s_pos[i] == p) { idx = i; break; }
-      if (idx < 0) { idx = cnt++; s_pos[idx] = p; s_org[idx] = p; }
-      const int tmp = s_org[j];
-      s_org[j] = s_org[idx];
-      s_org[idx] = tmp;
+      const unsigned long long hit = __ballot(pos == p);
+      int idx;
+      if (hit) {
+        idx = __ffsll((long long)hit) - 1;
+      } else {
+        idx = cnt++;
+        if (lane == idx) { pos = p; org = p; }
+      }
+      const int oj = __shfl(org, j, 64), oi = __shfl(org, idx, 64);
+      if (lane == j) org = oi;
+      if (lane == idx) org = oj;
     }
-    list[0] = cnt;
-    for (int i = 0; i < cnt; ++i) { list[1 + i] = s_pos[i]; list[1 + kListMax + i] = s_org[i]; }
-    if (first_zero != 0 && *info == 0) *info = first_zero;
+    if (lane < cnt) { list[1 + lane] = pos; list[1 + kListMax + lane] = org; }
+    if (lane == 0) {
+      list[0] = cnt;
+      if (first_zero != 0 && *info == 0) *info = first_zero;
+    }
   }
 }
 
@@ -220,11 +230,11 @@ struct UpdSeg {
 
 // C(r, col) -= sum_k A(r, ac0 + k) B(kb0 + k, col) for rows r in [cr0, cr1);
 // C and B are the segment's matrix, columns col0 .. col0 + ncols - 1.
-template <typename T>
+template <typename T, int KMAX>
 __global__ __launch_bounds__(256) void k_lu_update(const T* __restrict__ A, int64_t lda, int ac0, int K, int kb0,
                                                    int cr0, int cr1, UpdSeg s0, UpdSeg s1, int tiles0) {
-  __shared__ T As[64][64];   // As[k][i]
-  __shared__ T Bs[64][64];   // Bs[k][c]
+  __shared__ T As[KMAX][64];   // As[k][i]
+  __shared__ T Bs[KMAX][64];   // Bs[k][c]
   const int t = threadIdx.x;
   const int ct = blockIdx.y;
   const UpdSeg S = ct < tiles0 ? s0 : s1;
@@ -293,21 +303,31 @@ hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int
   for (int k0 = 0; k0 < n;) {
     const int rem = n - k0;
     int nb;
-    if (rem <= kPanelThreads) {
-      // 32 doubles per thread leave no room under the 128-VGPR limit of a
-      // 1024-thread workgroup (the compiler moves the array to scratch)
-      constexpr int NB1 = sizeof(T) == 8 ? 24 : 32;
+    // 32 doubles per thread leave no room under the 128-VGPR limit of a
+    // 1024-thread workgroup (the compiler moves the array to scratch)
+    constexpr int NB1 = sizeof(T) == 8 ? 24 : 32;
+    if (rem <= 256) {
       nb = NB1;
-      hipLaunchKernelGGL((k_lu_panel<T, 1, NB1>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0, piv, list, info);
+      hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, 256>), dim3(1), dim3(256), 0, st, Q, ldq, n, k0, piv, list, info);
+    } else if (rem <= 512) {
+      nb = NB1;
+      hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
+    } else if (rem <= kPanelThreads) {
+      nb = NB1;
+      hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
+                         piv, list, info);
     } else if (rem <= 2 * kPanelThreads) {
       nb = 16;
-      hipLaunchKernelGGL((k_lu_panel<T, 2, 16>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0, piv, list, info);
+      hipLaunchKernelGGL((k_lu_panel<T, 2, 16, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
+                         piv, list, info);
     } else if (rem <= 4 * kPanelThreads) {
       nb = 8;
-      hipLaunchKernelGGL((k_lu_panel<T, 4, 8>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0, piv, list, info);
+      hipLaunchKernelGGL((k_lu_panel<T, 4, 8, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
+                         piv, list, info);
     } else {
       nb = 4;
-      hipLaunchKernelGGL((k_lu_panel<T, 8, 4>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0, piv, list, info);
+      hipLaunchKernelGGL((k_lu_panel<T, 8, 4, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
+                         piv, list, info);
     }
     const int nbe = nb < rem ? nb : rem;
     const int64_t cols = (int64_t)n - nbe + nrhs;   // every column outside the panel
@@ -318,7 +338,7 @@ hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int
     if (r1 < n) {
       UpdSeg s0{Q, ldq, r1, n - r1}, s1{P, ldp, 0, nrhs};
       const int t0 = (n - r1 + 63) / 64, t1 = (nrhs + 63) / 64;
-      hipLaunchKernelGGL(k_lu_update<T>, dim3((n - r1 + 63) / 64, t0 + t1), dim3(256), 0, st, (const T*)Q, ldq, k0,
+      hipLaunchKernelGGL((k_lu_update<T, 32>), dim3((n - r1 + 63) / 64, t0 + t1), dim3(256), 0, st, (const T*)Q, ldq, k0,
                          nbe, k0, r1, n, s0, s1, t0);
     }
     k0 += nbe;
@@ -331,7 +351,7 @@ hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int
       if (k0 > 0) {
         UpdSeg s0{P, ldp, 0, nrhs}, s1{nullptr, 0, 0, 0};
         const int t0 = (nrhs + 63) / 64;
-        hipLaunchKernelGGL(k_lu_update<T>, dim3((k0 + 63) / 64, t0), dim3(256), 0, st, (const T*)Q, ldq, k0, b, k0,
+        hipLaunchKernelGGL((k_lu_update<T, 64>), dim3((k0 + 63) / 64, t0), dim3(256), 0, st, (const T*)Q, ldq, k0, b, k0,
                            0, k0, s0, s1, t0);
       }
     }
