@@ -163,3 +163,41 @@ def test_expm_pade_2048_against_taylor(ps):
     torch.cuda.synchronize()
     d = float(torch.linalg.matrix_norm(E1 - E2, 1) / torch.linalg.matrix_norm(E2, 1))
     assert d <= 1e-13, d
+
+
+def test_expm_pade_graph_replays_match_eager(ps):
+    """The whole Pade evaluation (power table, blocks, plans, Horner steps,
+    LU solve, squarings) captured into one graph: every replay, with eager
+    calls between the replays, equals the eager result bit for bit."""
+    import torch
+    n = 700
+    A = to_dev(inputs.rescaled_normal(n, 6.0, inputs.rng(7, 3)))
+    ws = ps.pade_workspace(A, 13, 4, 1)
+    E = torch.empty_like(A)
+
+    def run():
+        ps.ps_expm_pade(A, 13, s=4, sigma=1, mode="mixed", out=E, workspace=ws)
+
+    run()
+    torch.cuda.synchronize()
+    ref = E.clone()
+    Eo = osolve.expm_pade(to_np(A), 13, 1)
+    assert np.linalg.norm(to_np(ref) - Eo, 1) / np.linalg.norm(Eo, 1) <= 1e-13
+    side = torch.cuda.Stream(device=A.device)
+    side.wait_stream(torch.cuda.current_stream(A.device))
+    with torch.cuda.stream(side):
+        run()
+    torch.cuda.current_stream(A.device).wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for _ in range(3):
+        E.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(E, ref)
+        run()                          # eager work between the replays
+        torch.cuda.synchronize()
+        assert torch.equal(E, ref)
+    del g
