@@ -7,8 +7,8 @@
 // L^{-1} Pi P and only the back substitution with U remains.
 //
 // Kernels (working type T = double or float):
-//   k_lu_panel       one workgroup (1024 threads; 256 or 512 for panels of
-//                    at most that many rows) factors the (n - k0) x nb panel
+//   k_lu_panel       one workgroup (256 threads up to 256 rows, 512 up to
+//                    2048 rows, 1024 above) factors the (n - k0) x nb panel
 //                    held in registers (thread t owns rows k0 + t + NT q);
 //                    per column a workgroup arg-max picks the pivot (largest
 //                    |entry|, lowest row on ties), the two rows are exchanged
@@ -25,9 +25,9 @@
 //                    element is read and written once per panel).
 //   k_lu_trsm_upper  back substitution with a <= 64-row diagonal block of U,
 //                    one wave per right-hand side.
-// Panel width: nb = 32 / R for R = ceil((n - k0) / 1024) rows per thread,
-// so every thread holds 32 values (24 FP64 values when R = 1); orders up to
-// 8192.
+// Panel width: 24 (FP64) or 32 (FP32) columns while at most 1024 rows are
+// left, then 16, 8 and 4 columns up to 2048, 4096 and 8192 rows (the
+// largest order), so that a thread's rows fit its registers.
 #include <hip/hip_runtime.h>
 
 #include "ps_internal.h"
@@ -313,13 +313,17 @@ hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int
       nb = NB1;
       hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
     } else if (rem <= kPanelThreads) {
+      // FP64: fewer waves per barrier, 512 threads with two rows each (64
+      // FP32 values per thread would go to scratch: 1024 threads there)
       nb = NB1;
-      hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
-                         piv, list, info);
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((k_lu_panel<T, 2, NB1, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
+      else
+        hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n,
+                           k0, piv, list, info);
     } else if (rem <= 2 * kPanelThreads) {
       nb = 16;
-      hipLaunchKernelGGL((k_lu_panel<T, 2, 16, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
-                         piv, list, info);
+      hipLaunchKernelGGL((k_lu_panel<T, 4, 16, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
     } else if (rem <= 4 * kPanelThreads) {
       nb = 8;
       hipLaunchKernelGGL((k_lu_panel<T, 4, 8, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
