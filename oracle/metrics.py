@@ -15,21 +15,38 @@ TEST INFRASTRUCTURE ONLY (part of the oracle).
       d = floor((1 + sqrt(4m + 5)) / 2)  (section 3.2).
   extra_scaling(normX, s)  l_0 = ceil(log2(e ||X||_1 / s)), the number of
       extra squarings that would force ||X||_1 <= s/e (section 3.2).
-  theta_taylor(m, u)  the largest theta with sum_{k>m} theta^k / k! <= u, the
-      Taylor truncation error at the scalar alpha_m of eq. (alpha_m-X) with
-      the practical estimate xi(X) taken as 1 (50-digit decimal arithmetic,
-      bisection).
+  theta_taylor(m, u)  the largest theta with sum_{k>m} theta^k / k! <= u: the
+      Taylor truncation threshold at the scalar alpha_m of eq. (alpha_m-X)
+      when xi(X) = 1 (50-digit decimal arithmetic, bisection).  Used only for
+      the first scaling sigma0 that keeps the powers of X0 = 2^-sigma0 A
+      bounded; the acceptance itself uses xi_b0 below.
+  taylor_tail(t, m)  sum_{k>m} t^k / k! in 50-digit decimal arithmetic.
+  xi_b0(X, s)  the estimate xi(X) of ||e^X||_1 in eq. (alpha_m-X), which the
+      paper leaves as "a practical estimate": ||B_0(X)||_1 with
+      B_0 = sum_{j<s} X^j / j!, the leading block of the PS form.  Section 3.1
+      itself takes B_0(X) as the approximation of e^X (its check of eq.
+      (cond-Y)).  Powers by repeated multiplication (Fragment EvalB0), IEEE
+      double, coefficients 1/j! correctly rounded.
+  accepts(A, sigma, m, s, u, alpha_A)  eq. (alpha_m-X) at X = 2^-sigma A:
+      taylor_tail(2^-sigma alpha_m(A), m) <= u xi_b0(X, s).  A non-finite
+      xi rejects.  For t = 2^-sigma alpha_m(A) > 800 (then t >= m + 2 for
+      every m <= 170, so at least half of the Poisson(t) mass lies above m and
+      the tail is at least e^t / 2 > e^799, more than u times the largest
+      double) the candidate is rejected without summing the series.
   auto_sigma(A, m, s, u, norm_guard)  the scaling chosen by the alpha_m
-      bound: sigma0 from ||A||_1 <= 2^sigma0 theta_m, alpha_m of
-      X0 = 2^-sigma0 A from its powers (repeated multiplication in IEEE
-      double), sigma the smallest with 2^-sigma alpha_m(A) <= theta_m; with
-      norm_guard also ||2^-sigma A||_1 <= s / e (section 3.2).
+      bound: sigma0 from ||A||_1 <= 2^sigma0 theta_m, alpha_m(A) =
+      2^sigma0 alpha_m(X0) from the powers of X0 = 2^-sigma0 A (repeated
+      multiplication in IEEE double), sigma the least sigma >= 0 that
+      `accepts`; with norm_guard also ||2^-sigma A||_1 <= s / e (section 3.2).
   select_degree(A, m_max, u)  the joint choice of (m, s, sigma) by the
       alpha_m bound: candidates m = q^2, q(q+1) <= m_max with PS cost
       (s - 1) + floor(m/s) - [s | m], s = ceil(sqrt(m)); alpha_m(A) from the
-      powers of A (repeated multiplication in IEEE double); for each m the
-      least sigma with 2^-sigma alpha_m(A) <= theta_m; the least cost plus
-      sigma wins, the smaller m on ties (section 3.2).
+      powers of X0 = 2^-sigma0 A (sigma0 from the largest candidate's theta,
+      repeated multiplication in IEEE double); for each m the least sigma
+      that `accepts` (with that m and s); the least cost plus sigma wins, the
+      smaller m on ties.  The cost rule is this build's reading (parity
+      unpinned: the paper takes m from its reference algorithm and gives no
+      cost rule).
   variable_s(X, coef)  the block size of Algorithm 2's variable-s branch
       (fix_params = false, section 3.3): s = ceil(sqrt(m)); only when
       ||X||_1 <= s / e, B_0 = sum_{j<s} c_j X^j and Y = X^s, then while
@@ -41,6 +58,8 @@ from __future__ import annotations
 import math
 
 import numpy as np
+
+from .coeffs import taylor_exp
 
 
 def norm1(A) -> float:
@@ -130,19 +149,63 @@ def _smallest_shift(a: float, b: float) -> int:
     return k
 
 
-def auto_sigma(A, m: int, s: int, u: float, norm_guard: bool = False) -> int:
-    A = np.asarray(A, dtype=np.float64)
-    th = theta_taylor(m, u)
-    nA = norm1(A)
-    s0 = _smallest_shift(nA, th)
-    X0 = A * math.ldexp(1.0, -s0)
+def taylor_tail(t, m: int):
+    """sum_{k>m} t^k / k! (t >= 0) as a 50-digit Decimal."""
+    return _taylor_tail_dec(t, m)
+
+
+def xi_b0(X, s: int) -> float:
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    c = taylor_exp(max(s - 1, 0))
+    B0 = np.eye(n) * c[0]
+    P = np.eye(n)
+    with np.errstate(over="ignore", invalid="ignore"):
+        for j in range(1, s):
+            P = P @ X                       # X^j = X^(j-1) X
+            B0 = B0 + c[j] * P
+        return norm1(B0)
+
+
+def accepts(A, sigma: int, m: int, s: int, u: float, alpha_A: float) -> bool:
+    from decimal import Decimal
+    t = math.ldexp(alpha_A, -sigma)
+    if t > 800.0:
+        return False
+    xi = xi_b0(np.ldexp(np.asarray(A, dtype=np.float64), -sigma), s)
+    if not math.isfinite(xi):
+        return False
+    return taylor_tail(t, m) <= Decimal(u) * Decimal(xi)
+
+
+def _alpha_scaled(A, m: int, sigma0: int) -> float:
+    """alpha_m(A) = 2^sigma0 alpha_m(X0), X0 = 2^-sigma0 A, powers of X0 by
+    repeated multiplication"""
+    X0 = np.ldexp(np.asarray(A, dtype=np.float64), -sigma0)
     d = 1
     while (d + 1) * d <= m + 1:
         d += 1
     Pd = np.linalg.matrix_power(X0, d)
     Pd1 = Pd @ X0
     a0 = max(norm1(Pd) ** (1.0 / d), norm1(Pd1) ** (1.0 / (d + 1)))
-    sig = min(s0, _smallest_shift(math.ldexp(a0, s0), th))
+    return math.ldexp(a0, sigma0)
+
+
+def least_sigma(A, m: int, s: int, u: float, alpha_A: float, sigma_max: int = 1100) -> int:
+    """the least sigma >= 0 with accepts(A, sigma, ...)"""
+    for sig in range(sigma_max + 1):
+        if accepts(A, sig, m, s, u, alpha_A):
+            return sig
+    raise ValueError("no scaling up to %d meets the bound" % sigma_max)
+
+
+def auto_sigma(A, m: int, s: int, u: float, norm_guard: bool = False) -> int:
+    A = np.asarray(A, dtype=np.float64)
+    th = theta_taylor(m, u)
+    nA = norm1(A)
+    s0 = _smallest_shift(nA, th)
+    alpha = _alpha_scaled(A, m, s0)
+    sig = least_sigma(A, m, s, u, alpha)
     if norm_guard:
         sig = max(sig, _smallest_shift(math.e * nA, float(s)))
     return sig
@@ -187,27 +250,12 @@ def select_degree(A, m_max: int, u: float):
         if q * (q + 1) <= m_max:
             cands.append(q * (q + 1))
         q += 1
-    thetas = [theta_taylor(m, u) for m in cands]
     nA = norm1(A)
-    s0 = _smallest_shift(nA, thetas[-1])
-    X0 = A * math.ldexp(1.0, -s0)
-    dstar = []
-    for m in cands:
-        d = 1
-        while (d + 1) * d <= m + 1:
-            d += 1
-        dstar.append(d)
-    D = max(max(_ceil_sqrt(m), d + 1) for m, d in zip(cands, dstar))
-    norms = {1: norm1(X0)}
-    P = X0
-    for d in range(2, D + 1):
-        P = P @ X0
-        norms[d] = norm1(P)
+    s0 = _smallest_shift(nA, theta_taylor(cands[-1], u))
     best = None
-    for m, d, th in zip(cands, dstar, thetas):
-        a0 = max(norms[d] ** (1.0 / d), norms[d + 1] ** (1.0 / (d + 1)))
-        sig = _smallest_shift(math.ldexp(a0, s0), th)
+    for m in cands:
         s = _ceil_sqrt(m)
+        sig = least_sigma(A, m, s, u, _alpha_scaled(A, m, s0))
         r = m // s
         cost = (s - 1) + r - (1 if m == s * r else 0) + sig
         if best is None or cost < best[0]:

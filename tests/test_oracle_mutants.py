@@ -131,7 +131,16 @@ MUTANTS = [
     ("alpha_m: d* one too small", "metrics.py",
      "d = int(math.floor((1 + math.sqrt(4 * m + 5)) / 2))", "d = int(math.floor((1 + math.sqrt(4 * m + 5)) / 2)) - 1"),
     ("automatic sigma: the 1-norm choice kept", "metrics.py",
-     "sig = min(s0, _smallest_shift(math.ldexp(a0, s0), th))", "sig = s0"),
+     "sig = least_sigma(A, m, s, u, alpha)", "sig = s0"),
+    ("alpha_m acceptance with xi(X) = 1 (an absolute tolerance)", "metrics.py",
+     "return taylor_tail(t, m) <= Decimal(u) * Decimal(xi)", "return taylor_tail(t, m) <= Decimal(u)"),
+    ("xi: B_0 with the power X^s as well", "metrics.py",
+     "for j in range(1, s):\n            P = P @ X", "for j in range(1, s + 1):\n            P = P @ X"),
+    ("xi: B_0 of the unscaled matrix", "metrics.py",
+     "xi = xi_b0(np.ldexp(np.asarray(A, dtype=np.float64), -sigma), s)",
+     "xi = xi_b0(np.asarray(A, dtype=np.float64), s)"),
+    ("alpha_m(A) not rescaled by 2^sigma0", "metrics.py",
+     "return math.ldexp(a0, sigma0)", "return a0"),
     ("shift search: a < 2^k b instead of a <= 2^k b", "metrics.py",
      "while a > math.ldexp(b, k):", "while a >= math.ldexp(b, k):"),
     ("variable s: growth test against ||X||^(s+1)", "metrics.py",

@@ -300,6 +300,12 @@ def test_nonnormal_example_numbers():
     s = math.ceil(math.sqrt(42))
     assert s == 7
     assert metrics.extra_scaling(nx, s) == int(g["l0"][0])
+    # the scaling the paper's Taylor-based algorithm chooses at u = 1e-64, m = 42:
+    # X = A/2 is accepted, i.e. one squaring (with xi(X) = 1 the bound would ask
+    # for two: the relative acceptance needs the estimate of ||e^X||_1 ~ 4.8e5)
+    m, u = int(g["m"][0]), g["u"][0]
+    assert metrics.auto_sigma(A, m, s, u) == int(g["l"][0])
+    assert metrics.xi_b0(X, s) == pytest.approx(math.exp(-0.05) * (1 + 5e5), rel=1e-4)
 
 
 # ---------------------------------------------- P9: cost model
@@ -502,6 +508,68 @@ def test_auto_sigma_on_the_nonnormal_example():
     assert metrics.auto_sigma(D, 30, 6, u) == math.ceil(math.log2(9.0 / th))
 
 
+def _tail_bounds(t, m):
+    """exact rational bounds lo <= sum_{k>m} t^k / k! <= hi for the double t >= 0:
+    a partial sum, and the partial sum plus the geometric bound of the rest"""
+    t = F(t)
+    term = F(1)
+    for k in range(1, m + 2):
+        term = term * t / k
+    lo = F(0)
+    k = m + 1
+    while True:
+        lo += term
+        k += 1
+        term = term * t / k
+        if k > t + 1 and term < lo * F(1, 10 ** 40):
+            break
+    return lo, lo + term / (1 - t / (k + 1))
+
+
+def _taylor_partial(x, s):
+    """sum_{j<s} x^j / j! exactly (x a double)"""
+    x = F(x)
+    return sum(x ** j / math.factorial(j) for j in range(s))
+
+
+def test_xi_b0_closed_forms():
+    # diagonal: B_0(D) = diag(T(d_i)), T the degree-(s-1) Taylor sum
+    d = [-2.25, 0.75, 0.5, -0.125]
+    for s in (1, 2, 4, 6, 7):
+        want = max(abs(_taylor_partial(x, s)) for x in d)
+        assert metrics.xi_b0(np.diag(d), s) == pytest.approx(float(want), rel=1e-14)
+    # Jordan block [[a, b], [0, a]]: X^j = a^j I + j a^(j-1) b N, so
+    # B_0 = T(a) I + b T'(a) N and ||B_0||_1 = |T(a)| + |b| |T'(a)|
+    for a, b, s in ((-0.05, 5e5, 7), (0.5, -3.0, 4), (-1.5, 0.25, 6)):
+        T = _taylor_partial(a, s)
+        Tp = sum(F(j) * F(a) ** (j - 1) / math.factorial(j) for j in range(1, s))
+        want = max(abs(T), abs(T) + abs(F(b)) * abs(Tp))
+        X = np.array([[a, b], [0.0, a]])
+        assert metrics.xi_b0(X, s) == pytest.approx(float(want), rel=1e-13)
+
+
+@pytest.mark.parametrize("d,m,s,u", [([-9.0, 3.0, 1.0], 30, 6, U), ([6.0, -0.5], 30, 6, U),
+                                     ([-40.0, -3.0], 18, 5, 2.0 ** -24), ([2.5, 1.25, -0.75], 16, 4, U),
+                                     ([100.0, -100.0, 1.0], 42, 7, 1e-64)])
+def test_auto_sigma_is_the_least_accepted_scaling(d, m, s, u):
+    # diagonal D: alpha_m(D) = max|d_i| and xi(2^-k D) = max_i |T(2^-k d_i)|, so the
+    # acceptance test of eq. (alpha_m-X) can be decided in exact rationals: the
+    # chosen k passes with the tail's upper bound and every smaller k fails with
+    # its lower bound (the cases are far from ties)
+    D = np.diag(d)
+    sig = metrics.auto_sigma(D, m, s, u)
+    a = max(abs(x) for x in d)
+
+    def passes(k, bound):
+        lo, hi = _tail_bounds(math.ldexp(a, -k), m)
+        xi = max(abs(_taylor_partial(math.ldexp(x, -k), s)) for x in d)
+        return (hi if bound == "hi" else lo) <= F(u) * xi
+
+    assert passes(sig, "hi")
+    for k in range(sig):
+        assert not passes(k, "lo"), k
+
+
 # --------------------------------------------------------------------------
 # Algorithm 2's variable-s branch (fix_params = false, section 3.3)
 # --------------------------------------------------------------------------
@@ -581,6 +649,22 @@ def test_select_degree_zero_and_nilpotent():
     assert metrics.select_degree(np.array([[0.0, 5.0], [0.0, 0.0]]), 42, u) == (1, 1, 0)
 
 
+def _accepts_brute(A, k, m, u):
+    """eq. (alpha_m-X) at X = 2^-k A with alpha_m and B_0 from numpy's
+    matrix_power and the tail's exact rational bounds; None when the two
+    bounds disagree (a near-tie)"""
+    X = np.ldexp(A, -k)
+    s = math.isqrt(m - 1) + 1 if m > 1 else 1
+    a = _alpha_brute(X, m)
+    xi = metrics.norm1(sum(np.linalg.matrix_power(X, j) / math.factorial(j) for j in range(s)))
+    lo, hi = _tail_bounds(a, m)
+    if hi <= F(u) * F(xi):
+        return True
+    if lo > F(u) * F(xi):
+        return False
+    return None
+
+
 @pytest.mark.parametrize("t,seed", [(0.01, 1), (0.3, 2), (1.0, 3), (8.0, 4), (64.0, 5), (1e3, 6)])
 def test_select_degree_is_the_cheapest_admissible_choice(t, seed):
     u = 2.0 ** -53
@@ -588,18 +672,22 @@ def test_select_degree_is_the_cheapest_admissible_choice(t, seed):
     A = G * (t / metrics.norm1(G))
     m, s, sig = metrics.select_degree(A, 42, u)
     assert s == (math.isqrt(m - 1) + 1 if m > 1 else 1)
-    # the bound holds at the chosen pair
-    assert math.ldexp(_alpha_brute(A, m), -sig) <= metrics.theta_taylor(m, u) * (1 + 1e-12)
+    # the bound holds at the chosen pair, and one squaring fewer fails it
+    assert _accepts_brute(A, sig, m, u) is True
+    if sig > 0:
+        assert _accepts_brute(A, sig - 1, m, u) is False
     # no candidate is cheaper at its own least admissible scaling
     best = _cost_brute(m) + sig
     for q in range(1, 7):
         for mc in (q * q, q * (q + 1)):
             if mc > 42:
                 continue
-            a = _alpha_brute(A, mc)
-            th = metrics.theta_taylor(mc, u)
             sc = 0
-            while math.ldexp(a, -sc) > th * (1 + 1e-12):
+            while True:
+                ok = _accepts_brute(A, sc, mc, u)
+                assert ok is not None, (mc, sc)
+                if ok:
+                    break
                 sc += 1
             assert _cost_brute(mc) + sc >= best, (mc, sc, m, sig)
             if _cost_brute(mc) + sc == best:
