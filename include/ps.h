@@ -172,8 +172,10 @@ ps_status ps_expm(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
 /* Automatic scaling for the Taylor approximant (section 3.2, eq.
  * (alpha_m-X)).  theta_m: the largest theta with
  * sum_{k>m} theta^k / k! <= u, u the unit roundoff of dtype (2^-53 or
- * 2^-24), so that the truncation error of p_m at alpha = alpha_m(X) is at
- * most u.  Host only.  0 <= m <= 170. */
+ * 2^-24), i.e. the bound's threshold when the estimate xi(X) of ||e^X||_1
+ * is 1.  ps_expm_auto and ps_expm_select use it only for the first scaling
+ * sigma0 of the powers; their acceptance test scales u by xi(X).  Host only.
+ * 0 <= m <= 170. */
 ps_status ps_theta_taylor(ps_dtype dtype, int m, double* theta);
 
 /* Workspace bytes for ps_expm_auto (the power table reaches
@@ -184,15 +186,21 @@ ps_status ps_workspace_size_auto(ps_dtype dtype, int64_t n, int m, int s, size_t
  *   sigma0 = the smallest sigma >= 0 with 2^-sigma ||A||_1 <= theta_m;
  *   X0 = 2^-sigma0 A; the powers X0^2 .. X0^max(s, d*+1) are formed once;
  *   alpha = 2^sigma0 max(||X0^d*||_1^(1/d*), ||X0^(d*+1)||_1^(1/(d*+1)));
- *   sigma = the smallest sigma >= 0 with 2^-sigma alpha <= theta_m
- *   (<= sigma0); with norm_guard != 0 also ||2^-sigma A||_1 <= s / e, the
- *   norm under which section 3 guarantees the decay the mixed plan relies on.
+ *   sigma = the smallest sigma >= 0 whose X = 2^-sigma A passes eq.
+ *   (alpha_m-X): sum_{k>m} t^k / k! <= u xi(X) at t = 2^-sigma alpha, with
+ *   xi(X) = ||B_0(X)||_1, B_0 = sum_{j<s} X^j / j! (the leading PS block),
+ *   as the estimate of ||e^X||_1 (t > 800 fails without the series; sigma
+ *   may exceed sigma0 when xi < 1); with norm_guard != 0 also
+ *   ||2^-sigma A||_1 <= s / e, the norm under which section 3 guarantees
+ *   the decay the mixed plan relies on.
  * The PS evaluation reuses the power table (X^j = 2^(j (sigma0 - sigma)) X0^j,
  * an exact rescaling).  Taylor coefficients 1/k!, m <= 170; s as in
  * ps_expm.  The chosen sigma is written to *sigma_out (may be NULL).
  * Norms are 1-norms of the column-major matrix.  The call synchronizes the
- * stream twice (it reads two norms back to the host), so it cannot be
- * captured into a graph.  Errors: PS_ERR_ARG also for non-finite input. */
+ * stream for ||A||_1, for the two alpha_m norms and once per window of 16
+ * candidate scalings (one launch forms xi for all of them), so it cannot be
+ * captured into a graph.  Errors: PS_ERR_ARG also for non-finite input, and
+ * when no sigma <= 500 passes. */
 ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m, int s,
                        int norm_guard, void* E, int64_t lde, const ps_opts* opts,
                        ps_report* report, int* sigma_out, void* ws, size_t ws_bytes,
@@ -208,17 +216,19 @@ ps_status ps_workspace_size_select(ps_dtype dtype, int64_t n, int m_max, size_t*
  * m_max (the PS-optimal degrees: s = ceil(sqrt(m)) gives s - 1 powers and
  * floor(m/s) - [s | m] Horner products); sigma0 makes ||2^-sigma0 A||_1 at
  * most the largest candidate's theta; the powers of X0 = 2^-sigma0 A give
- * alpha_m; for each candidate the least sigma with
- * 2^-sigma alpha_m(A) <= theta_m (theta_m as in ps_theta_taylor) is taken,
- * and the candidate with the fewest products plus squarings (the smaller m
+ * alpha_m; for each candidate the least sigma that passes the acceptance
+ * test of ps_expm_auto (xi from that candidate's s) is taken, and the
+ * candidate with the fewest products plus squarings (the smaller m
  * on ties) is evaluated on the same powers (exact power-of-two rescaling).
  * The candidates are examined in increasing m, and the search stops at the
  * first one whose products alone reach the best total (the PS cost grows
  * strictly along the list), so powers are formed only as far as
  * max(s, d* + 1) of the examined candidates.  chosen: host array of 3 ints
  * receiving m, s, sigma (may be NULL).  1 <= m_max <= 170.  The call
- * synchronizes the stream once for ||A||_1 and once per extension of the
- * powers.  Errors: as ps_expm_auto. */
+ * synchronizes the stream once for ||A||_1, once per extension of the
+ * powers and once per window of candidate scalings.  The cost rule is this
+ * library's own (the paper takes m from its reference algorithm).  Errors:
+ * as ps_expm_auto. */
 ps_status ps_expm_select(ps_dtype dtype, int64_t n, const void* A, int64_t lda, int m_max,
                          void* E, int64_t lde, const ps_opts* opts, ps_report* report,
                          int* chosen, void* ws, size_t ws_bytes, void* stream);

@@ -491,6 +491,76 @@ int ceil_log2_ratio(double a, double b) {   // smallest k >= 0 with a <= 2^k b
   return k;
 }
 
+// The acceptance test of eq. (alpha_m-X) for X = 2^-sigma A: the Taylor tail
+// at t = 2^-sigma alpha_m(A) is at most u xi(X), with xi(X) = ||B_0(X)||_1,
+// B_0 = sum_{j<s} X^j / j! (the leading PS block, section 3.1's stand-in for
+// e^X), as the estimate of ||e^X||_1.  t > 800 is rejected without the series
+// (the tail then exceeds e^t / 2, beyond u times any double).
+constexpr double kTailCap = 800.0;
+
+// Least sigma >= 0 accepted by that test.  power(1) is A itself and power(j)
+// (j = 2..s-1) is X0^j with X0 = 2^-sigma0 A, so X = 2^-sigma A and
+// X^j = 2^(j (sigma0 - sigma)) X0^j.  Scalings below a
+// host lower bound (the tail above u times the triangle-inequality bound
+// sum_j |c_j| (2^-sigma ||A||_1)^j of xi, with a margin for rounding) cannot
+// pass; from there, windows of kXiWin scalings are decided with one launch of
+// k_xi_norms and one read-back each.  Fails with PS_ERR_ARG when no sigma up to
+// kMaxSigma passes.
+template <typename PowerFn>
+ps_status least_accepted_sigma(int W, int64_t n, int m, int s, double u, double alphaA, double normA, int sigma0,
+                               PowerFn power, double* wg, hipStream_t st, int* out) {
+  std::vector<double> c(s);
+  {
+    DD x = {1.0, 0.0};
+    c[0] = 1.0;
+    for (int j = 1; j < s; ++j) {
+      x = dd_div_int(x, (double)j);
+      c[j] = x.hi + x.lo;
+    }
+  }
+  int lo = 0;
+  while (lo <= kMaxSigma && !(std::ldexp(alphaA, -lo) <= kTailCap)) ++lo;
+  for (; lo <= kMaxSigma; ++lo) {
+    const long double t = std::ldexp(alphaA, -lo), x = std::ldexp(normA, -lo);
+    long double up = 0.0L, xp = 1.0L;
+    for (int j = 0; j < s; ++j, xp *= x) up += (long double)c[j] * xp;
+    if (!(taylor_tail(t, m) > (long double)u * up * 1.001L)) break;
+  }
+  const int64_t G = norm1_groups(n);
+  std::vector<double> h((size_t)kXiWin * G);
+  for (int base = lo; base <= kMaxSigma; base += kXiWin) {
+    XiArgs xa;
+    memset(&xa, 0, sizeof xa);
+    xa.J = s - 1;
+    xa.K = std::min(kXiWin, kMaxSigma - base + 1);
+    for (int j = 1; j < s; ++j) xa.M[j - 1] = power(j);
+    for (int k = 0; k < xa.K; ++k) {
+      const int sg = base + k;
+      xa.w[k][0] = c[0];
+      if (s > 1) xa.w[k][1] = std::ldexp(c[1], -sg);
+      for (int j = 2; j < s; ++j) xa.w[k][j] = std::ldexp(c[j], j * (sigma0 - sg));
+    }
+    xa.wg = wg;
+    PS_HIP(launch_xi_norms(W, n, xa, st));
+    PS_HIP(hipMemcpyAsync(h.data(), wg, (size_t)xa.K * G * sizeof(double), hipMemcpyDeviceToHost, st));
+    PS_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < xa.K; ++k) {
+      const int sg = base + k;
+      const double t = std::ldexp(alphaA, -sg);
+      if (!(t <= kTailCap)) continue;
+      double xi = 0.0;
+      for (int64_t g = 0; g < G; ++g)
+        if (h[(size_t)k * G + g] > xi || h[(size_t)k * G + g] != h[(size_t)k * G + g]) xi = h[(size_t)k * G + g];
+      if (!std::isfinite(xi)) continue;
+      if (taylor_tail(t, m) <= (long double)u * (long double)xi) {
+        *out = sg;
+        return PS_OK;
+      }
+    }
+  }
+  return fail(PS_ERR_ARG, "no scaling up to %d squarings meets the alpha_m bound (m = %d)", kMaxSigma, m);
+}
+
 }  // namespace
 
 // Variable block size (Algorithm 2 with fix_params = false): the power slots
@@ -551,7 +621,7 @@ static SelectPlan select_plan(ps_dtype dtype, int64_t n, int m_max) {
   size_t mx = 0;
   for (int m : P.cand) mx = std::max(mx, make_layout(dtype, n, m, default_s(m), 1, 0, P.D - 1).bytes);
   P.off_wg = mx;
-  P.bytes = al256(mx + (size_t)P.D * norm1_groups(n) * sizeof(double));
+  P.bytes = al256(mx + (size_t)(P.D + kXiWin) * norm1_groups(n) * sizeof(double));
   return P;
 }
 
@@ -744,6 +814,10 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
   if (ps_status e = check_ws(ws, ws_bytes, L.bytes)) return e;
   if (overlap(ws, L.bytes, E, spanE) || overlap(ws, L.bytes, A, spanA))
     return fail(PS_ERR_ALIAS, "workspace overlaps a matrix argument");
+  // the column-sum region (at least 3n doubles, 256-byte rounded) holds the
+  // kXiWin * ceil(n/8) workgroup maxima of the acceptance windows
+  if (L.off_plan - L.off_colsum < (size_t)kXiWin * norm1_groups(n) * sizeof(double))
+    return fail(PS_ERR_UNSUPPORTED, "ps_expm_auto: scratch region too small");
   hipStream_t st = (hipStream_t)stream;
   const int W = dtype == PS_F64 ? 0 : 1;
   const double theta = theta_taylor(m, W == 0 ? 0x1p-53 : 0x1p-24);
@@ -787,8 +861,12 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
     if (ps_status e = read_norm1(wg, n, st, &nd[q])) return e;
   }
   const double alpha0 = std::max(std::pow(nd[0], 1.0 / dstar), std::pow(nd[1], 1.0 / (dstar + 1)));
-  // alpha_m(A) = 2^sigma0 alpha_m(X0) <= ||A||_1, so sigma <= sigma0
-  int sigma = std::min(sigma0, ceil_log2_ratio(ldexp(alpha0, sigma0), theta));
+  // alpha_m(A) = 2^sigma0 alpha_m(X0); sigma the least scaling that passes
+  // the acceptance test with xi(X) = ||B_0(X)||_1
+  int sigma = 0;
+  if (ps_status e = least_accepted_sigma(W, n, m, s, W == 0 ? 0x1p-53 : 0x1p-24, ldexp(alpha0, sigma0), nA, sigma0,
+                                         power, wg, st, &sigma))
+    return e;
   if (norm_guard) sigma = std::max(sigma, ceil_log2_ratio(M_E * nA, (double)s));   // ||X||_1 <= s / e
   if (sigma > kMaxSigma) return fail(PS_ERR_ARG, "the norm guard needs more than %d squarings", kMaxSigma);
   // 4. evaluation on X = 2^-sigma A with the prebuilt powers: X^j = 2^(j (sigma0 - sigma)) X0^j
@@ -855,13 +933,12 @@ ps_status ps_expm_select(ps_dtype dtype, int64_t n, const void* A, int64_t lda, 
   const Layout L0 = make_layout(dtype, n, SP.cand.back(), default_s(SP.cand.back()), 1, 0, SP.D - 1);
   auto power = [&](int j) { return j == 1 ? X1 : ws_mat(wsc, L0.off_pow + (size_t)(j - 2) * L0.slot, n, 0, esize); };
   // 1. ||A||_1; sigma0 from the largest candidate's theta (the smallest scaling)
-  std::vector<double> theta(SP.cand.size());
-  for (size_t k = 0; k < SP.cand.size(); ++k) theta[k] = theta_taylor(SP.cand[k], u);
+  const double theta_last = theta_taylor(SP.cand.back(), u);
   double nA = 0.0;
   PS_HIP(launch_norm1(W, n, X1, wg, st));
   if (ps_status e = read_norm1(wg, n, st, &nA)) return e;
   if (!std::isfinite(nA)) return fail(PS_ERR_ARG, "input matrix has non-finite entries");
-  const int sigma0 = ceil_log2_ratio(nA, theta.back());
+  const int sigma0 = ceil_log2_ratio(nA, theta_last);
   if (sigma0 > kMaxSigma) return fail(PS_ERR_ARG, "||A||_1 = %g needs more than %d squarings", nA, kMaxSigma);
   const double beta0 = ldexp(1.0, -sigma0);
   // 2. candidates in increasing m; PS cost grows strictly along them, so the
@@ -901,16 +978,20 @@ ps_status ps_expm_select(ps_dtype dtype, int64_t n, const void* A, int64_t lda, 
       }
     return PS_OK;
   };
-  // 3. per candidate: alpha_m(A) = 2^sigma0 alpha_m(X0), the least sigma with
-  //    2^-sigma alpha_m(A) <= theta_m, and the products it costs
+  // 3. per candidate: alpha_m(A) = 2^sigma0 alpha_m(X0), the least sigma that
+  //    passes the acceptance test (with that candidate's s), and the products
+  //    it costs
   int best = -1, best_cost = 0, best_sigma = 0;
   for (size_t k = 0; k < SP.cand.size(); ++k) {
     const int m = SP.cand[k], d = alpha_dstar(m);
     if (best >= 0 && ps_cost(m) >= best_cost) break;
     if (ps_status e = build_to(std::max(default_s(m), d + 1))) return e;
     const double a0 = std::max(std::pow(nrm[d], 1.0 / d), std::pow(nrm[d + 1], 1.0 / (d + 1)));
-    const int sg = ceil_log2_ratio(ldexp(a0, sigma0), theta[k]);
-    if (sg > kMaxSigma) continue;
+    int sg = 0;
+    const ps_status e = least_accepted_sigma(W, n, m, default_s(m), u, ldexp(a0, sigma0), nA, sigma0, power,
+                                             wg + (size_t)SP.D * G, st, &sg);
+    if (e == PS_ERR_HIP) return e;
+    if (e != PS_OK) continue;   // no scaling within kMaxSigma for this degree
     const int cost = ps_cost(m) + sg;
     if (best < 0 || cost < best_cost) {
       best = (int)k;

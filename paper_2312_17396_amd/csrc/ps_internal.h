@@ -154,6 +154,18 @@ struct CombArgs {
 };
 hipError_t launch_comb_norm(int working, int64_t n, const CombArgs& a, hipStream_t st);
 
+// Estimates of ||e^X||_1 for K scalings at once (eq. (alpha_m-X)): for each
+// k < K the per-workgroup maxima (norm1_groups(n) of each, at wg + k * G) of
+// the column abs sums of w[k][0] I + sum_{j=1..J} w[k][j] M[j-1].
+constexpr int kXiWin = 16;
+struct XiArgs {
+  MatArg M[kMaxComb];
+  int J, K;
+  double w[kXiWin][kMaxComb + 1];
+  double* wg;
+};
+hipError_t launch_xi_norms(int working, int64_t n, const XiArgs& a, hipStream_t st);
+
 // One Horner step: P_{i-1} = B_{i-1} + P_i Y (or, with cast_only, P = B_src
 // converted to the format of the consumer step).
 struct HornerArgs {

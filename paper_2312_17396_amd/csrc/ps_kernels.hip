@@ -384,6 +384,59 @@ hipError_t launch_comb_norm(int working, int64_t n, const CombArgs& a, hipStream
 }
 
 // ---------------------------------------------------------------------------
+// k_xi_norms: column abs sums of K combinations of the same J matrices (one
+// wave per column, every matrix read once), maximum per workgroup and
+// combination
+// ---------------------------------------------------------------------------
+template <typename W>
+__global__ __launch_bounds__(NT) void k_xi_norms(int64_t n, XiArgs a) {
+  __shared__ double red[kXiWin][NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t col = (int64_t)blockIdx.x * NW + w;
+  double acc[kXiWin];
+#pragma unroll
+  for (int k = 0; k < kXiWin; ++k) acc[k] = 0.0;
+  if (col < n) {
+    for (int64_t rw = lane; rw < n; rw += 64) {
+      double x[kMaxComb];
+#pragma unroll
+      for (int j = 0; j < kMaxComb; ++j)
+        x[j] = j < a.J ? (double)((const W*)a.M[j].p)[rw + col * a.M[j].ld] : 0.0;
+      const double id = rw == col ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < kXiWin; ++k) {
+        double v = a.w[k][0] * id;
+#pragma unroll
+        for (int j = 0; j < kMaxComb; ++j)
+          if (j < a.J) v += a.w[k][j + 1] * x[j];
+        acc[k] += fabs(v);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kXiWin; ++k)
+      for (int off = 32; off >= 1; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < kXiWin; ++k) red[k][w] = acc[k];
+  __syncthreads();
+  if (t < a.K) {
+    double m = red[t][0];
+    for (int q = 1; q < NW; ++q)
+      if (red[t][q] > m || red[t][q] != red[t][q]) m = red[t][q];
+    a.wg[(int64_t)t * gridDim.x + blockIdx.x] = m;
+  }
+}
+
+hipError_t launch_xi_norms(int working, int64_t n, const XiArgs& a, hipStream_t st) {
+  if (a.J < 0 || a.J > kMaxComb || a.K < 1 || a.K > kXiWin || NT / 64 != NW) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)norm1_groups(n)), block(NT);
+  if (working == 0) hipLaunchKernelGGL(k_xi_norms<double>, grid, block, 0, st, n, a);
+  else hipLaunchKernelGGL(k_xi_norms<float>, grid, block, 0, st, n, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // k_plan: one workgroup per matrix
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void k_plan(PlanArgs a) {
