@@ -169,6 +169,28 @@ ps_status ps_expm(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
                   void* E, int64_t lde, const ps_opts* opts, ps_report* report,
                   void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ps_expm
+ * with its workspace taken from a static device array of
+ * PS_NOALLOC_SCRATCH_BYTES (128 MiB) that the library holds on each device it
+ * runs on until the process ends (FP64, m = 30, s = 6, sigma > 0 fits up to
+ * n = 1024).  Same arguments, kernels and results as ps_expm, minus the
+ * workspace.  The call allocates nothing: no hipMalloc, hipFree or event; the
+ * array's device address is looked up once per device (hipGetSymbolAddress,
+ * under a lock).  The stream must belong to the current device.  Every call
+ * on one device shares that device's array and leaves its contents behind;
+ * nothing in it needs to start at zero, but calls that overlap on one device
+ * (concurrent streams or host threads) race on it and must be serialised by
+ * the caller.  Errors: PS_ERR_WORKSPACE when the layout of (n, m, s, sigma)
+ * needs more than PS_NOALLOC_SCRATCH_BYTES (checked before any device work);
+ * PS_ERR_UNSUPPORTED for opts->profile (it creates events); otherwise as
+ * ps_expm. */
+#define PS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+ps_status ps_expm_noalloc(ps_dtype dtype, int64_t n, const void* A, int64_t lda,
+                          const double* coef, int m, int s, int sigma,
+                          void* E, int64_t lde, const ps_opts* opts, ps_report* report,
+                          void* stream);
+
 /* Automatic scaling for the Taylor approximant (section 3.2, eq.
  * (alpha_m-X)).  theta_m: the largest theta with
  * sum_{k>m} theta^k / k! <= u, u the unit roundoff of dtype (2^-53 or

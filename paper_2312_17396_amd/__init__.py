@@ -75,6 +75,7 @@ _SIGS = {
     "ps_workspace_size": ([_i, _i64, _i, _i, _i, _szp], _i),
     "ps_eval": ([_i, _i64, _vp, _i64, _dp, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
     "ps_expm": ([_i, _i64, _vp, _i64, _dp, _i, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
+    "ps_expm_noalloc": ([_i, _i64, _vp, _i64, _dp, _i, _i, _i, _vp, _i64, _op, _rp, _vp], _i),
     "ps_theta_taylor": ([_i, _i, _dp], _i),
     "ps_workspace_size_auto": ([_i, _i64, _i, _i, _szp], _i),
     "ps_expm_auto": ([_i, _i64, _vp, _i64, _i, _i, _i, _vp, _i64, _op, _rp, _ip, _vp, _sz, _vp], _i),
@@ -269,6 +270,24 @@ def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
     c = _darr(coef) if coef is not None else None
     _check(lib().ps_expm(dt, n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n, ctypes.byref(o),
                          ctypes.byref(rep) if rep is not None else None, wsp, wsb, _stream_ptr(A.device)))
+    return (E, rep.to_dict()) if rep is not None else E
+
+
+def ps_expm_noalloc(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, tier_override=None,
+                    report=False, out=None, rule="blocks"):
+    """ps_expm on the library's static device scratch array: no workspace is
+    allocated (the output is, unless `out` is given)."""
+    import torch
+    A = _check_square(A)
+    n = A.shape[0]
+    dt = _dtype_code(A)
+    E = torch.empty_like(A) if out is None else _check_out(out, A)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, False, rule=rule)
+    rep = ps_report() if report else None
+    c = _darr(coef) if coef is not None else None
+    _check(lib().ps_expm_noalloc(dt, n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n,
+                                 ctypes.byref(o), ctypes.byref(rep) if rep is not None else None,
+                                 _stream_ptr(A.device)))
     return (E, rep.to_dict()) if rep is not None else E
 
 

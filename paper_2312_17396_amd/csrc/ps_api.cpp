@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -753,19 +754,19 @@ static ps_status expm_impl(ps_dtype dtype, int batch, int64_t n, const void* A, 
   if (ps_status e = check_ws(ws, ws_bytes, L.bytes * (size_t)batch)) return e;
   if (overlap(ws, L.bytes * (size_t)batch, E, spanE) || overlap(ws, L.bytes * (size_t)batch, A, spanA))
     return fail(PS_ERR_ALIAS, "workspace overlaps a matrix argument");
-  std::vector<double> c(m + 1);
+  double c[kMaxDegree + 1];
   if (coef) {
     for (int k = 0; k <= m; ++k) c[k] = coef[k];
   } else {
     if (m > 170) return fail(PS_ERR_ARG, "built-in Taylor coefficients need m <= 170");
-    ps_coef_taylor_exp(m, c.data());
+    ps_coef_taylor_exp(m, c);
   }
   Job J;
   J.L = &L;
   J.batch = batch;
   J.X1 = MatArg{A, lda, strideA};
   J.beta = beta;
-  J.coef = c.data();
+  J.coef = c;
   J.out = MatArg{E, lde, strideE};
   J.ws = (char*)ws;
   J.ws_stride = L.bytes;
@@ -1171,6 +1172,64 @@ ps_status ps_expm(ps_dtype dtype, int64_t n, const void* A, int64_t lda, const d
   if (sigma < 0 || sigma > kMaxSigma) return fail(PS_ERR_ARG, "sigma = %d out of range [0, %d]", sigma, kMaxSigma);
   return expm_impl(dtype, 1, n, A, lda, 0, coef, m, s, sigma, ldexp(1.0, -sigma), E, lde, 0, opts, report, ws,
                    ws_bytes, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// ps_expm_noalloc: ps_expm with its workspace in a static device array, for
+// callers that cannot allocate device memory.  Each device holds its own copy
+// of `scratch` (from the library's load until the process ends); host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// device that is current, taken once per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = PS_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+// device address of the current device's scratch array (looked up once per device)
+ps_status scratch_address(hipStream_t st, void** out) {
+  int dev = -1;
+  PS_HIP(hipGetDevice(&dev));
+  if (st) {
+    int sdev = -1;
+    PS_HIP(hipStreamGetDevice(st, &sdev));
+    if (sdev != dev) return fail(PS_ERR_ARG, "stream belongs to device %d, current device is %d", sdev, dev);
+  }
+  if (dev < 0 || dev >= kMaxDevices) return fail(PS_ERR_UNSUPPORTED, "device index %d above %d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    PS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255) != 0) return fail(PS_ERR_HIP, "scratch array address %p not usable", p);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ps_status ps_expm_noalloc(ps_dtype dtype, int64_t n, const void* A, int64_t lda, const double* coef, int m, int s,
+                          int sigma, void* E, int64_t lde, const ps_opts* opts, ps_report* report, void* stream) {
+  if (sigma < 0 || sigma > kMaxSigma) return fail(PS_ERR_ARG, "sigma = %d out of range [0, %d]", sigma, kMaxSigma);
+  if (ps_status e = check_common(dtype, n, m, &s, sigma)) return e;
+  if (opts && opts->profile) return fail(PS_ERR_UNSUPPORTED, "ps_expm_noalloc: opts.profile creates events");
+  const size_t need = make_layout(dtype, n, m, s, sigma, 0).bytes;
+  if (need > kScratchBytes)
+    return fail(PS_ERR_WORKSPACE, "ps_expm_noalloc: n = %lld, m = %d, s = %d needs %zu bytes of scratch, above the "
+                "static %zu", (long long)n, m, s, need, kScratchBytes);
+  void* ws = nullptr;
+  if (ps_status e = scratch_address((hipStream_t)stream, &ws)) return e;
+  return expm_impl(dtype, 1, n, A, lda, 0, coef, m, s, sigma, ldexp(1.0, -sigma), E, lde, 0, opts, report, ws,
+                   kScratchBytes, stream);
 }
 
 ps_status ps_expm_strided_batched(ps_dtype dtype, int batch, int64_t n, const void* A, int64_t lda, int64_t strideA,
