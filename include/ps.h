@@ -32,7 +32,8 @@
  *    caller's `ws` of at least the size returned by the matching
  *    ps_workspace_size* query (256-byte aligned pointer required).
  *  - On error, output contents are unspecified.  IEEE non-finite values in
- *    the input propagate through the arithmetic.
+ *    the input propagate through the arithmetic, unless opts->check_finite
+ *    is set (see ps_opts).
  */
 #ifndef PS_H
 #define PS_H
@@ -49,6 +50,7 @@ typedef enum {
   PS_ERR_ARG = -1,         /* invalid size, degree, block size, pointer, ld */
   PS_ERR_ALIAS = -2,       /* output overlaps an input */
   PS_ERR_WORKSPACE = -3,   /* workspace missing, too small or misaligned */
+  PS_ERR_NONFINITE = -4,   /* opts->check_finite: a NaN or infinity in an input, or in a result */
   PS_ERR_UNSUPPORTED = -5, /* valid request the library does not implement */
   PS_ERR_HIP = -6          /* a HIP runtime call failed; see ps_last_error() */
 } ps_status;
@@ -69,9 +71,11 @@ typedef enum { PS_TIER_F64 = 0, PS_TIER_F32 = 1, PS_TIER_BF16 = 2, PS_TIER_FP8 =
 #define PS_MODE_MIXED 1   /* Algorithms 2/3 (fixed s): per-step tiers from the norms.
                              With an FP64 working precision, FP32 allowed and n > 512,
                              ps_eval, ps_expm and ps_expm_strided_batched form Y = X^s by an
-                             FP32 product (eq. (cond-Y): Y needs the accuracy of the
-                             first lower-precision step) and again in FP64 when the
-                             plan keeps a Horner product in FP64. */
+                             FP32 product (eq. (cond-Y): Y needs the accuracy u_nu of
+                             the first lower-precision step) and again in FP64 (its
+                             FP32 rounding then feeds the FP32 products) when the
+                             plan keeps a Horner product in FP64 or has an FP32
+                             product with u_i < 16 * 2^-24. */
 
 #define PS_RULE_BLOCKS 0  /* tiers from the assembled blocks' 1-norms (Thm 2.1, eq. (choose-ui)) */
 #define PS_RULE_APRIORI 1 /* tiers from coefficient magnitudes times powers of ||X||_1 */
@@ -93,6 +97,15 @@ typedef struct ps_opts {
                                 PS_RULE_APRIORI (1): the denominator bounded a priori by
                                 sum_{k in block i} |c_k| ||X||^k, the numerator the
                                 block norm ||B_0|| (never overestimated) */
+  int check_finite;          /* nonzero: before any evaluation kernel the inputs are scanned
+                                (one pass per matrix, then a stream synchronisation) and a
+                                NaN or infinity returns PS_ERR_NONFINITE with nothing
+                                evaluated; after the evaluation the results are scanned the
+                                same way (an overflow returns PS_ERR_NONFINITE, the result
+                                left in place).  ps_eval, ps_expm, ps_expm_noalloc,
+                                ps_expm_strided_batched, ps_eval_multi, ps_expm_pade,
+                                ps_expm_auto, ps_expm_select and ps_expm_vars; the others
+                                return PS_ERR_UNSUPPORTED when it is set. */
 } ps_opts;
 
 typedef struct ps_report {
@@ -106,6 +119,12 @@ typedef struct ps_report {
                                 twice when it is also formed in FP64) + Horner + squarings */
   float ms_power, ms_assemble, ms_horner, ms_square;  /* profile != 0 only */
   double normX;              /* ||X||_1, X = 2^-sigma A (the first power) */
+  double cost_saving;        /* C_r of eq. (Cr) read as the saving (Table 1):
+                                1 - ((s-1) D + sum_{i=1..r} d_i) / ((s+r-1) D), D and d_i the
+                                decimal digits -log10 u of the working precision and of
+                                step i's tier (see ps_model_cost) */
+  double m_low;              /* M_low of Table 2: the fraction of the s-1+r products run in
+                                precision u^(1/2) or lower */
 } ps_report;
 
 /* Version of the ABI (major*10000 + minor*100 + patch). */
@@ -140,6 +159,17 @@ ps_status ps_coef_taylor_cos(int m, double* coef);
  * Outputs tier[0..r], u[0..r] (caller arrays of r+1) and *nu. */
 ps_status ps_plan(ps_dtype dtype, int r, const double* normB, double normY,
                   const ps_opts* opts, int* tier, double* u, int* nu);
+
+/* The modelled cost of a plan (section 3.3.1, host only, no GPU): with D the
+ * decimal digits -log10 u of the working precision dtype and d_i those of
+ * the unit roundoff of tier[i] (2^-53, 2^-24, 2^-8, 2^-4; 2^-106 for
+ * PS_DD), i = 1..r,
+ *   *cost_saving = 1 - ((s-1) D + sum_i d_i) / ((s+r-1) D)   (eq. (Cr), Table 1)
+ *   *m_low = #{i : u_tier(i) >= u^(1/2)} / (s-1+r)          (Table 2's M_low)
+ * counting the s-1 powers in the working precision and every one of the r
+ * Horner products, the trivial one of s | m included, as the paper does.
+ * tier: host array of r+1 entries (entry 0 ignored), values 0..3 or 4 (dd). */
+ps_status ps_model_cost(ps_dtype dtype, int s, int r, const int* tier, double* cost_saving, double* m_low);
 
 /* ---------------------------------------------------------------------------
  * Single matrix.

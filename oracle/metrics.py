@@ -13,6 +13,8 @@ TEST INFRASTRUCTURE ONLY (part of the oracle).
       the reading under which all four C_r entries of Table 1 reproduce.
   alpha_m(X, m)  max(||X^d||^(1/d), ||X^(d+1)||^(1/(d+1))) with
       d = floor((1 + sqrt(4m + 5)) / 2)  (section 3.2).
+  m_low(D, s, r, d)  the share of the s - 1 + r PS products run in precision
+      u^(1/2) or lower (Table 2's M_low), d_i the decimal digits of u_i.
   extra_scaling(normX, s)  l_0 = ceil(log2(e ||X||_1 / s)), the number of
       extra squarings that would force ||X||_1 <= s/e (section 3.2).
   theta_taylor(m, u)  the largest theta with sum_{k>m} theta^k / k! <= u: the
@@ -92,6 +94,13 @@ def rel_err_cols(Pcols, ref_hi, ref_lo=None) -> float:
 
 def cost_saving(D: float, s: int, r: int, d) -> float:
     return 1.0 - ((s - 1) * D + float(sum(d))) / ((s + r - 1) * D)
+
+
+def m_low(D: float, s: int, r: int, d) -> float:
+    """Table 2's M_low: the share of the s - 1 + r products performed in
+    precision u^(1/2) or lower, i.e. with d_i <= D / 2 decimal digits (the
+    s - 1 powers run in the working precision)."""
+    return sum(1 for x in d if x <= D / 2.0) / float(s - 1 + r)
 
 
 def alpha_m(X, m: int) -> float:

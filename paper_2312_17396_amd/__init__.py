@@ -34,7 +34,8 @@ class PSError(RuntimeError):
 
 class ps_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("tier_mask", ctypes.c_uint), ("delta", ctypes.c_double),
-                ("tier_override", ctypes.POINTER(ctypes.c_int)), ("profile", ctypes.c_int), ("rule", ctypes.c_int)]
+                ("tier_override", ctypes.POINTER(ctypes.c_int)), ("profile", ctypes.c_int), ("rule", ctypes.c_int),
+                ("check_finite", ctypes.c_int)]
 
 
 class ps_report(ctypes.Structure):
@@ -42,7 +43,8 @@ class ps_report(ctypes.Structure):
                 ("tier", ctypes.c_int * MAX_BLOCKS), ("u", ctypes.c_double * MAX_BLOCKS),
                 ("normB", ctypes.c_double * MAX_BLOCKS), ("normY", ctypes.c_double),
                 ("gemms", ctypes.c_int * 4), ("ms_power", ctypes.c_float), ("ms_assemble", ctypes.c_float),
-                ("ms_horner", ctypes.c_float), ("ms_square", ctypes.c_float), ("normX", ctypes.c_double)]
+                ("ms_horner", ctypes.c_float), ("ms_square", ctypes.c_float), ("normX", ctypes.c_double),
+                ("cost_saving", ctypes.c_double), ("m_low", ctypes.c_double)]
 
     def to_dict(self):
         r = self.r
@@ -50,7 +52,8 @@ class ps_report(ctypes.Structure):
                 "tier": [self.tier[i] for i in range(r + 1)], "u": [self.u[i] for i in range(r + 1)],
                 "normB": [self.normB[i] for i in range(r + 1)], "normY": self.normY, "normX": self.normX,
                 "gemms": list(self.gemms), "ms": {"power": self.ms_power, "assemble": self.ms_assemble,
-                                                  "horner": self.ms_horner, "square": self.ms_square}}
+                                                  "horner": self.ms_horner, "square": self.ms_square},
+                "cost_saving": self.cost_saving, "m_low": self.m_low}
 
 
 _lib = None
@@ -72,6 +75,7 @@ _SIGS = {
     "ps_coef_pade_exp": ([_i, _dp, _dp], _i),
     "ps_coef_taylor_cos": ([_i, _dp], _i),
     "ps_plan": ([_i, _i, _dp, _d, _op, _ip, _dp, _ip], _i),
+    "ps_model_cost": ([_i, _i, _i, _ip, _dp, _dp], _i),
     "ps_workspace_size": ([_i, _i64, _i, _i, _i, _szp], _i),
     "ps_eval": ([_i, _i64, _vp, _i64, _dp, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
     "ps_expm": ([_i, _i64, _vp, _i64, _dp, _i, _i, _i, _vp, _i64, _op, _rp, _vp, _sz, _vp], _i),
@@ -154,8 +158,10 @@ def _darr(vals):
 RULES = {"blocks": 0, "apriori": 1}
 
 
-def _opts(mode="fixed", tier_mask=0, delta=10.0, tier_override=None, profile=False, rule="blocks"):
+def _opts(mode="fixed", tier_mask=0, delta=10.0, tier_override=None, profile=False, rule="blocks",
+          check_finite=False):
     o = ps_opts()
+    o.check_finite = 1 if check_finite else 0
     o.mode = MODE_MIXED if mode in ("mixed", MODE_MIXED) else MODE_FIXED
     if rule not in RULES:
         raise PSError("rule must be one of %s" % sorted(RULES))
@@ -194,6 +200,16 @@ def _check_square(A):
 # ---------------------------------------------------------------------------
 # coefficients and planning (host)
 # ---------------------------------------------------------------------------
+def model_cost(tiers, s, dtype="f64"):
+    """(C_r as the saving, M_low) of a plan (eq. (Cr), Table 2); tiers[1..r]."""
+    r = len(tiers) - 1
+    t = (ctypes.c_int * (r + 1))(*[int(x) for x in tiers])
+    cr, ml = ctypes.c_double(), ctypes.c_double()
+    code = {"f64": PS_F64, "f32": PS_F32, "dd": 2}[dtype]
+    _check(lib().ps_model_cost(code, int(s), r, t, ctypes.byref(cr), ctypes.byref(ml)))
+    return cr.value, ml.value
+
+
 def coef_taylor_exp(m):
     out = (ctypes.c_double * (m + 1))()
     _check(lib().ps_coef_taylor_exp(int(m), out))
@@ -233,7 +249,7 @@ def default_s(m):
 # single matrix
 # ---------------------------------------------------------------------------
 def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=None, report=False, profile=False,
-            rule="blocks"):
+            rule="blocks", check_finite=False):
     """P = sum_k coef[k] A^k by Paterson--Stockmeyer (mixed mode: per-step tiers)."""
     import torch
     A = _check_square(A)
@@ -244,7 +260,7 @@ def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=N
     _check(lib().ps_workspace_size(dt, n, m, int(s), 0, ctypes.byref(nbytes)))
     ws, wsp, wsb = _workspace(nbytes.value, A.device)
     P = torch.empty_like(A)
-    o, _k = _opts(mode, tier_mask, delta, tier_override, profile, rule=rule)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile, rule=rule, check_finite=check_finite)
     rep = ps_report() if (report or profile) else None
     _check(lib().ps_eval(dt, n, A.data_ptr(), n, _darr(coef), m, int(s), P.data_ptr(), n, ctypes.byref(o),
                          ctypes.byref(rep) if rep is not None else None, wsp, wsb, _stream_ptr(A.device)))
@@ -252,7 +268,7 @@ def ps_eval(A, coef, s=0, mode="fixed", tier_mask=0, delta=10.0, tier_override=N
 
 
 def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, tier_override=None,
-            report=False, profile=False, out=None, workspace=None, rule="blocks"):
+            report=False, profile=False, out=None, workspace=None, rule="blocks", check_finite=False):
     """E = p(2^-sigma A)^(2^sigma); coef=None uses the Taylor coefficients 1/k!."""
     import torch
     A = _check_square(A)
@@ -265,7 +281,7 @@ def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
     else:
         ws, wsp, wsb = workspace
     E = torch.empty_like(A) if out is None else _check_out(out, A)
-    o, _k = _opts(mode, tier_mask, delta, tier_override, profile, rule=rule)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, profile, rule=rule, check_finite=check_finite)
     rep = ps_report() if (report or profile) else None
     c = _darr(coef) if coef is not None else None
     _check(lib().ps_expm(dt, n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n, ctypes.byref(o),
@@ -274,7 +290,7 @@ def ps_expm(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0
 
 
 def ps_expm_noalloc(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, tier_override=None,
-                    report=False, out=None, rule="blocks"):
+                    report=False, out=None, rule="blocks", check_finite=False):
     """ps_expm on the library's static device scratch array: no workspace is
     allocated (the output is, unless `out` is given)."""
     import torch
@@ -282,7 +298,7 @@ def ps_expm_noalloc(A, m, s=0, sigma=0, coef=None, mode="fixed", tier_mask=0, de
     n = A.shape[0]
     dt = _dtype_code(A)
     E = torch.empty_like(A) if out is None else _check_out(out, A)
-    o, _k = _opts(mode, tier_mask, delta, tier_override, False, rule=rule)
+    o, _k = _opts(mode, tier_mask, delta, tier_override, False, rule=rule, check_finite=check_finite)
     rep = ps_report() if report else None
     c = _darr(coef) if coef is not None else None
     _check(lib().ps_expm_noalloc(dt, n, A.data_ptr(), n, c, int(m), int(s), int(sigma), E.data_ptr(), n,

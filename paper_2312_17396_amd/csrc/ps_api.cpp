@@ -93,6 +93,7 @@ struct Opts {
   const int* override_tiers = nullptr;
   int profile = 0;
   int rule = PS_RULE_BLOCKS;
+  int check_finite = 0;
 };
 
 Opts read_opts(const ps_opts* o, int working) {
@@ -104,6 +105,7 @@ Opts read_opts(const ps_opts* o, int working) {
     r.override_tiers = o->tier_override;
     r.profile = o->profile;
     r.rule = o->rule;
+    r.check_finite = o->check_finite;
   }
   r.mask |= 1u << working;
   for (int t = 0; t < working; ++t) r.mask &= ~(1u << t);
@@ -200,10 +202,11 @@ struct Job {
 
 // Y = X_s formed by an FP32 product under an FP64 working precision.  By
 // eq. (cond-Y) Y needs the accuracy u_nu of the first lower-precision Horner
-// step; when the plan keeps every Horner product below FP64, FP32 gives it.
-// The plan is only known on the device, so each polynomial's cast launch
-// forms Y in FP64 too whenever its plan keeps a product in FP64 (and the
-// report counts it).  Only for n > 512: below that an n^3 product is bound
+// step; the FP32 product's error (~5.4 u32 measured) meets it when that step
+// is BF16 or FP8, or FP32 with u_nu >= kY32Margin u32.  The plan is only
+// known on the device, so each polynomial's cast launch forms Y in FP64 too
+// (and rounds it into the FP32 copy) whenever its plan keeps a product in
+// FP64 or has an FP32 product below that margin (the report counts it).  Only for n > 512: below that an n^3 product is bound
 // by latency, so FP32 saves nothing and a second product in FP64 would add
 // its latency.  Decided by the caller for all jobs sharing the powers.
 bool y32_allowed(const Layout& L, const Opts& o) {
@@ -217,6 +220,42 @@ MatArg ws_mat(char* ws, size_t off, int64_t n, size_t stride_bytes, int esize) {
   a.ld = n;
   a.stride = (int64_t)(stride_bytes / esize);
   return a;
+}
+
+// eq. (Cr) as the saving and Table 2's M_low from a plan's tiers (host)
+void model_cost(int working, int s, int r, const int* tier, double* saving, double* m_low) {
+  const double D = -std::log10(tier_unit_roundoff(working));
+  const double half = std::sqrt(tier_unit_roundoff(working));
+  double dsum = 0.0;
+  int low = 0;
+  for (int i = 1; i <= r; ++i) {
+    const double ut = tier_unit_roundoff(tier[i]);
+    dsum += -std::log10(ut);
+    low += ut >= half ? 1 : 0;
+  }
+  const int prods = s - 1 + r;
+  *saving = prods > 0 ? 1.0 - ((s - 1) * D + dsum) / (prods * D) : 0.0;
+  *m_low = prods > 0 ? (double)low / prods : 0.0;
+}
+
+// opts.check_finite: one counting pass over `batch` matrices, then a
+// read-back in chunks of a stack buffer (no allocation); wg: device scratch of
+// norm1_groups(n) doubles per matrix, wg_stride bytes apart
+ps_status nonfinite_or_ok(int W, int64_t n, int batch, MatArg M, char* wg, size_t wg_stride, hipStream_t st,
+                          const char* what) {
+  PS_HIP(launch_count_nonfinite(W, n, batch, M, wg, wg_stride, st));
+  const int64_t G = norm1_groups(n);
+  double h[256];
+  for (int b = 0; b < batch; ++b)
+    for (int64_t g0 = 0; g0 < G; g0 += 256) {
+      const int64_t cnt = std::min<int64_t>(256, G - g0);
+      PS_HIP(hipMemcpyAsync(h, (const double*)(wg + (size_t)b * wg_stride) + g0, cnt * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+      PS_HIP(hipStreamSynchronize(st));
+      for (int64_t k = 0; k < cnt; ++k)
+        if (h[k] != 0.0) return fail(PS_ERR_NONFINITE, "%s %d holds NaN or infinite entries", what, b);
+    }
+  return PS_OK;
 }
 
 struct Timer {
@@ -407,11 +446,13 @@ ps_status fill_report(const Layout& L, const Job& J, int b, ps_report* rep, hipS
   }
   rep->normY = P.normY;
   rep->normX = P.normX;
+  model_cost(L.working, L.s, L.r, P.tier, &rep->cost_saving, &rep->m_low);
   rep->gemms[L.working] += L.npow + L.sigma;
   for (int i = L.first_step; i >= 1; --i) rep->gemms[P.tier[i]] += 1;
   if (J.y32) {   // Y by an FP32 product, again in FP64 if a Horner product is
     bool fp64_step = false;
-    for (int i = 1; i <= L.r; ++i) fp64_step = fp64_step || P.tier[i] == L.working;
+    for (int i = 1; i <= L.r; ++i)
+      fp64_step = fp64_step || P.tier[i] == L.working || (P.tier[i] == 1 && P.u[i] < kY32Margin * 0x1p-24);
     rep->gemms[1] += 1;
     if (!fp64_step) rep->gemms[L.working] -= 1;
   }
@@ -641,6 +682,7 @@ const char* ps_strerror(int status) {
     case PS_ERR_ARG: return "invalid argument";
     case PS_ERR_ALIAS: return "output overlaps an input";
     case PS_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case PS_ERR_NONFINITE: return "non-finite values in an input or a result";
     case PS_ERR_UNSUPPORTED: return "unsupported request";
     case PS_ERR_HIP: return "HIP runtime error";
     default: return "unknown status";
@@ -711,6 +753,17 @@ ps_status ps_plan(ps_dtype dtype, int r, const double* normB, double normY, cons
   return PS_OK;
 }
 
+ps_status ps_model_cost(ps_dtype dtype, int s, int r, const int* tier, double* cost_saving, double* m_low) {
+  if (dtype != PS_F64 && dtype != PS_F32 && dtype != PS_DD)
+    return fail(PS_ERR_ARG, "dtype must be PS_F64, PS_F32 or PS_DD");
+  if (s < 1 || r < 0 || r + 1 > PS_MAX_BLOCKS) return fail(PS_ERR_ARG, "s = %d, r = %d out of range", s, r);
+  if (!tier || !cost_saving || !m_low) return fail(PS_ERR_ARG, "NULL argument");
+  for (int i = 1; i <= r; ++i)
+    if (tier[i] < 0 || tier[i] > kTierDD) return fail(PS_ERR_ARG, "tier[%d] = %d not a tier", i, tier[i]);
+  model_cost(dtype == PS_F64 ? 0 : dtype == PS_F32 ? 1 : kTierDD, s, r, tier, cost_saving, m_low);
+  return PS_OK;
+}
+
 ps_status ps_workspace_size(ps_dtype dtype, int64_t n, int m, int s, int sigma, size_t* bytes) {
   if (!bytes) return fail(PS_ERR_ARG, "bytes == NULL");
   if (ps_status e = check_common(dtype, n, m, &s, sigma)) return e;
@@ -776,11 +829,17 @@ static ps_status expm_impl(ps_dtype dtype, int batch, int64_t n, const void* A, 
   J.skip_square = false;
   J.y32 = y32_allowed(L, o);
   hipStream_t st = (hipStream_t)stream;
+  const int W = dtype == PS_F64 ? 0 : 1;
+  char* wg = (char*)ws + L.off_colsum;   // scratch of each matrix until its blocks are assembled
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, batch, J.X1, wg, L.bytes, st, "input matrix")) return e;
   float ms[4] = {0, 0, 0, 0};
   if (ps_status e = run_job(J, st, o.profile ? ms : nullptr)) return e;
   if (reports)
     for (int b = 0; b < batch; ++b)
       if (ps_status e = fill_report(L, J, b, &reports[b], st, o.profile ? ms : nullptr)) return e;
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, batch, J.out, wg, L.bytes, st, "result")) return e;
   return PS_OK;
 }
 
@@ -830,7 +889,8 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
   double nA = 0.0;
   PS_HIP(launch_norm1(W, n, X1, wg, st));
   if (ps_status e = read_norm1(wg, n, st, &nA)) return e;
-  if (!std::isfinite(nA)) return fail(PS_ERR_ARG, "input matrix has non-finite entries");
+  if (!std::isfinite(nA))
+    return fail(o.check_finite ? PS_ERR_NONFINITE : PS_ERR_ARG, "input matrix has non-finite entries");
   const int sigma0 = ceil_log2_ratio(nA, theta);
   if (sigma0 > kMaxSigma) return fail(PS_ERR_ARG, "||A||_1 = %g needs more than %d squarings", nA, kMaxSigma);
   const double beta0 = ldexp(1.0, -sigma0);
@@ -893,6 +953,8 @@ ps_status ps_expm_auto(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
   if (sigma_out) *sigma_out = sigma;
   if (report)
     if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, 1, J.out, (char*)wg, 0, st, "result")) return e;
   return PS_OK;
 }
 
@@ -938,7 +1000,8 @@ ps_status ps_expm_select(ps_dtype dtype, int64_t n, const void* A, int64_t lda, 
   double nA = 0.0;
   PS_HIP(launch_norm1(W, n, X1, wg, st));
   if (ps_status e = read_norm1(wg, n, st, &nA)) return e;
-  if (!std::isfinite(nA)) return fail(PS_ERR_ARG, "input matrix has non-finite entries");
+  if (!std::isfinite(nA))
+    return fail(o.check_finite ? PS_ERR_NONFINITE : PS_ERR_ARG, "input matrix has non-finite entries");
   const int sigma0 = ceil_log2_ratio(nA, theta_last);
   if (sigma0 > kMaxSigma) return fail(PS_ERR_ARG, "||A||_1 = %g needs more than %d squarings", nA, kMaxSigma);
   const double beta0 = ldexp(1.0, -sigma0);
@@ -1029,6 +1092,8 @@ ps_status ps_expm_select(ps_dtype dtype, int64_t n, const void* A, int64_t lda, 
   }
   if (report)
     if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, 1, J.out, (char*)wg, 0, st, "result")) return e;
   return PS_OK;
 }
 
@@ -1077,7 +1142,8 @@ ps_status ps_expm_vars(ps_dtype dtype, int64_t n, const void* A, int64_t lda, co
   double nA = 0.0;
   PS_HIP(launch_norm1(W, n, X1, wg, st));
   if (ps_status e = read_norm1(wg, n, st, &nA)) return e;
-  if (!std::isfinite(nA)) return fail(PS_ERR_ARG, "input matrix has non-finite entries");
+  if (!std::isfinite(nA))
+    return fail(o.check_finite ? PS_ERR_NONFINITE : PS_ERR_ARG, "input matrix has non-finite entries");
   const double nX = ldexp(nA, -sigma);
   int s = s0;
   bool built = false;
@@ -1157,6 +1223,8 @@ ps_status ps_expm_vars(ps_dtype dtype, int64_t n, const void* A, int64_t lda, co
   if (s_out) *s_out = s;
   if (report)
     if (ps_status e = fill_report(L, J, 0, report, st, o.profile ? ms : nullptr)) return e;
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, 1, J.out, (char*)wg, 0, st, "result")) return e;
   return PS_OK;
 }
 
@@ -1326,6 +1394,9 @@ ps_status ps_eval_multi(ps_dtype dtype, int64_t n, const void* A, int64_t lda, i
   hipStream_t st = (hipStream_t)stream;
   const int W = dtype == PS_F64 ? 0 : 1;
   MatArg X1{A, lda, 0};
+  char* wgc = (char*)ws + Ls[0].off_colsum;
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, 1, X1, wgc, 0, st, "input matrix")) return e;
   if (square_arg) {
     MatArg Z = ws_mat((char*)ws, Ls[0].off_pow, n, total, esize);
     PS_HIP(launch_gemm(W, n, 1, X1, 0, X1, 0, Z, 1.0, 0, st));
@@ -1350,6 +1421,10 @@ ps_status ps_eval_multi(ps_dtype dtype, int64_t n, const void* A, int64_t lda, i
     if (reports)
       if (ps_status e = fill_report(Ls[t], J, 0, &reports[t], st, o.profile ? ms : nullptr)) return e;
   }
+  if (o.check_finite)
+    for (int t = 0; t < k; ++t)
+      if (ps_status e = nonfinite_or_ok(W, n, 1, MatArg{P[t], ldp[t], 0}, wgc, 0, st, "result of polynomial"))
+        return e;
   return PS_OK;
 }
 
@@ -1448,6 +1523,9 @@ ps_status ps_expm_pade(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
   MatArg Wk = ws_mat(w, off_w, n, total, esize);
   MatArg Qk = ws_mat(w, off_q, n, total, esize);
   MatArg R0 = (sigma % 2 == 0) ? Eo : Wk;
+  char* wgc = w + Ls[0].off_colsum;
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, 1, MatArg{A, lda, 0}, wgc, 0, st, "input matrix")) return e;
   for (int t = 0; t < 2; ++t) {
     Job J;
     J.L = &Ls[t];
@@ -1475,6 +1553,8 @@ ps_status ps_expm_pade(ps_dtype dtype, int64_t n, const void* A, int64_t lda, in
     PS_HIP(launch_gemm(W, n, 1, cur, 0, cur, 0, dst, 1.0, 0, st));
     cur = dst;
   }
+  if (o.check_finite)
+    if (ps_status e = nonfinite_or_ok(W, n, 1, Eo, wgc, 0, st, "result")) return e;
   return PS_OK;
 }
 

@@ -127,6 +127,7 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
     return bad(PS_ERR_ARG, "batch stride smaller than one matrix");
   if (opts && opts->mode != PS_MODE_FIXED && opts->mode != PS_MODE_MIXED) return bad(PS_ERR_ARG, "opts.mode");
   if (opts && opts->rule != PS_RULE_BLOCKS && opts->rule != PS_RULE_APRIORI) return bad(PS_ERR_ARG, "opts.rule");
+  if (opts && opts->check_finite) return bad(PS_ERR_UNSUPPORTED, "check_finite is not supported by ps_expm_backward");
   const int W = dtype == PS_F64 ? 0 : 1;
   const bool mixed = opts && opts->mode == PS_MODE_MIXED;
   const int es = W == 0 ? 8 : 4;

@@ -473,6 +473,7 @@ ps_status fill_args(ps_dtype dt, const double* coef, int m, const ps_opts* opts,
   ba.mode = opts ? opts->mode : PS_MODE_FIXED;
   if (ba.mode != PS_MODE_FIXED && ba.mode != PS_MODE_MIXED) return bfail(PS_ERR_ARG, "opts.mode must be 0 or 1");
   if (opts && opts->tier_override) return bfail(PS_ERR_UNSUPPORTED, "tier_override is not supported for batches");
+  if (opts && opts->check_finite) return bfail(PS_ERR_UNSUPPORTED, "check_finite is not supported for batches");
   ba.rule = opts ? opts->rule : PS_RULE_BLOCKS;
   if (ba.rule != PS_RULE_BLOCKS && ba.rule != PS_RULE_APRIORI) return bfail(PS_ERR_ARG, "opts.rule must be 0 or 1");
   unsigned mask = (opts && opts->tier_mask) ? opts->tier_mask : 0xFu;

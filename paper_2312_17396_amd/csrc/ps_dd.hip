@@ -556,6 +556,7 @@ ps_status ps_expm_dd(int64_t n, const double* A, int64_t lda, const double* coef
   const int mode = opts ? opts->mode : PS_MODE_FIXED;
   if (mode != PS_MODE_FIXED && mode != PS_MODE_MIXED) return dfail(PS_ERR_ARG, "opts.mode must be 0 or 1");
   if (opts && opts->tier_override) return dfail(PS_ERR_UNSUPPORTED, "tier_override is not supported by ps_expm_dd");
+  if (opts && opts->check_finite) return dfail(PS_ERR_UNSUPPORTED, "check_finite is not supported by ps_expm_dd");
   if (opts && opts->rule != PS_RULE_BLOCKS) return dfail(PS_ERR_UNSUPPORTED, "ps_expm_dd plans from the block norms only");
   const unsigned mask = ((opts && opts->tier_mask) ? opts->tier_mask : 0xFu) & 0xFu;
   const double delta = (opts && opts->delta > 0) ? opts->delta : 10.0;
@@ -691,6 +692,7 @@ ps_status ps_expm_dd(int64_t n, const double* A, int64_t lda, const double* coef
     }
     report->normY = pl.normY;
     report->normX = pl.normX;
+    (void)ps_model_cost(PS_DD, L.s, L.r, pl.tier, &report->cost_saving, &report->m_low);
   }
   return PS_OK;
 }

@@ -116,8 +116,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   bool y64 = false;
   if (a.y_cond) {
     // Y was formed in FP32; a Horner product in the working precision (the
-    // folded step r included) needs it in the working precision as well
-    for (int i = 1; i <= L.r; ++i) y64 = y64 || plan->tier[i] == WT;
+    // folded step r included) needs it in the working precision as well, and
+    // so does an FP32 product whose u_i is below kY32Margin u32 (eq. (cond-Y):
+    // Y must be accurate to u_i, and the FP32 product's error is ~5 u32)
+    for (int i = 1; i <= L.r; ++i)
+      y64 = y64 || plan->tier[i] == WT || (plan->tier[i] == 1 && plan->u[i] < kY32Margin * 0x1p-24);
     if (y64)
       gemm_tile<W, false, false>((const W*)a.ya.p + b * a.ya.stride, a.ya.ld, (const W*)a.yb.p + b * a.yb.stride,
                                  a.yb.ld, (W*)a.yc.p + b * a.yc.stride, a.yc.ld, a.n, a.n, (int64_t)tm * kTileM,
@@ -147,6 +150,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.nv = a.n;
   h.nvb = a.n;
   horner_tile<W, true>(h, (int64_t)tm * kTileM, (int64_t)tn * kTileN, smem);
+  if (y64) {
+    // the FP32 copy of Y that the FP32 products read becomes the rounding of
+    // the working-precision Y (after the fold correction above has read the
+    // FP32-formed one); this workgroup wrote the tile, and horner_tile ended
+    // with a barrier
+    const int t = threadIdx.x, row = t & 63;
+    const int64_t gr = (int64_t)tm * kTileM + row;
+    const W* yc = (const W*)a.yc.p + b * a.yc.stride;
+    float* y32 = (float*)(ws + L.off_yf32);
+#pragma unroll 4
+    for (int q = 0; q < TILE_Q; ++q) {
+      const int64_t gc = (int64_t)tn * kTileN + (t >> 6) + NW * q;
+      if (gr < a.n && gc < a.n) y32[gr + gc * a.n] = (float)yc[gr + gc * a.yc.ld];
+    }
+  }
 }
 
 hipError_t launch_horner(int working, const HornerArgs& a, int batch, hipStream_t st) {
@@ -433,6 +451,38 @@ hipError_t launch_xi_norms(int working, int64_t n, const XiArgs& a, hipStream_t 
   const dim3 grid((unsigned)norm1_groups(n)), block(NT);
   if (working == 0) hipLaunchKernelGGL(k_xi_norms<double>, grid, block, 0, st, n, a);
   else hipLaunchKernelGGL(k_xi_norms<float>, grid, block, 0, st, n, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// k_count_nonfinite: NaN and infinity entries (one wave per column), count per
+// workgroup; grid.y runs over the matrices of a batch
+// ---------------------------------------------------------------------------
+template <typename W>
+__global__ __launch_bounds__(NT) void k_count_nonfinite(int64_t n, MatArg X, char* wg, size_t wg_stride) {
+  __shared__ double red[NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t col = (int64_t)blockIdx.x * NW + w;
+  const W* x = (const W*)X.p + (int64_t)blockIdx.y * X.stride;
+  double cnt = 0.0;
+  if (col < n) {
+    for (int64_t rw = lane; rw < n; rw += 64) cnt += isfinite((double)x[rw + col * X.ld]) ? 0.0 : 1.0;
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  }
+  if (lane == 0) red[w] = cnt;
+  __syncthreads();
+  if (t == 0) {
+    double c = 0.0;
+    for (int k = 0; k < NW; ++k) c += red[k];
+    ((double*)(wg + (size_t)blockIdx.y * wg_stride))[blockIdx.x] = c;
+  }
+}
+
+hipError_t launch_count_nonfinite(int working, int64_t n, int batch, MatArg X, char* wg, size_t wg_stride,
+                                  hipStream_t st) {
+  const dim3 grid((unsigned)norm1_groups(n), (unsigned)batch), block(NT);
+  if (working == 0) hipLaunchKernelGGL(k_count_nonfinite<double>, grid, block, 0, st, n, X, wg, wg_stride);
+  else hipLaunchKernelGGL(k_count_nonfinite<float>, grid, block, 0, st, n, X, wg, wg_stride);
   return hipGetLastError();
 }
 

@@ -179,3 +179,54 @@ def test_solve_and_pade_workspace_sizes(ps):
     assert L.ps_workspace_size_multi(0, 2048, 2, deg, 4, 0, ctypes.byref(multi)) == 0
     assert L.ps_workspace_size_pade(0, 2048, 13, 4, 2, ctypes.byref(pade)) == 0
     assert pade.value >= multi.value + 2 * 2048 * 2048 * 8 + sz.value
+
+
+def test_model_cost_matches_oracle(ps):
+    """ps_model_cost (the report's C_r and M_low) against the oracle's
+    cost_saving and m_low with d_i the digits of each tier's unit roundoff."""
+    from oracle import metrics
+    import math
+    rng = np.random.default_rng(3)
+    for dt, work in (("f64", 0), ("f32", 1), ("dd", 4)):
+        lowest = 1 if work == 0 else (2 if work == 1 else 0)
+        for trial in range(200):
+            s = int(rng.integers(1, 14))
+            r = int(rng.integers(0, 13))
+            tiers = [work] + [int(t) for t in rng.integers(lowest, 4, r)] if work != 4 else \
+                [4] + [int(t) for t in rng.choice([0, 1, 2, 3, 4], r)]
+            if work != 4:
+                tiers = [work] + [max(t, work) if rng.random() < 0.8 else work for t in tiers[1:]]
+            cr, ml = ps.model_cost(tiers, s, dt)
+            D = -math.log10(oplan.U_TIER[work])
+            d = [-math.log10(oplan.U_TIER[t]) for t in tiers[1:]]
+            if s - 1 + r == 0:
+                assert cr == 0.0 and ml == 0.0
+                continue
+            assert cr == pytest.approx(metrics.cost_saving(D, s, r, d), abs=1e-12)
+            assert ml == pytest.approx(metrics.m_low(D, s, r, d), abs=1e-15)
+    # every product in the working precision saves nothing
+    assert ps.model_cost([0, 0, 0, 0], 6) == (0.0, 0.0)
+    with pytest.raises(ps.PSError):
+        ps.model_cost([0, 7], 2)
+
+
+def test_nonfinite_status_and_unsupported_paths(ps):
+    L = ps.lib()
+    assert L.ps_strerror(-4).decode().startswith("non-finite")
+    o, _ = ps._opts("mixed", check_finite=True)
+    assert o.check_finite == 1
+    # check_finite is refused by the entry points that do not scan, before any device work
+    st = L.ps_expm_backward(0, 1, 8, 0x10000000, 8, 64, 0x20000000, 8, 64, None, 6, 0, 0, 0x30000000, 8, 64, 0,
+                            ctypes.byref(o), 0x40000000, 1 << 30, None)
+    assert st == -5 and b"check_finite" in L.ps_last_error()
+    n = (ctypes.c_int32 * 1)(8)
+    ptrs = (ctypes.c_void_p * 1)(0x10000000)
+    outs = (ctypes.c_void_p * 1)(0x20000000)
+    ld = (ctypes.c_int64 * 1)(8)
+    sg = (ctypes.c_int32 * 1)(0)
+    st = L.ps_expm_batched(1, 1, n, ptrs, ld, None, 6, None, sg, outs, ld, ctypes.byref(o), None, 0x40000000,
+                           1 << 30, None)
+    assert st == -5 and b"check_finite" in L.ps_last_error()
+    st = L.ps_expm_dd(8, 0x10000000, 8, None, 6, 0, 0, 0x20000000, 8, ctypes.byref(o), None, 0x40000000, 1 << 30,
+                      None)
+    assert st == -5 and b"check_finite" in L.ps_last_error()

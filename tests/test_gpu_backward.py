@@ -187,9 +187,10 @@ def test_grad_batch_512_fp32(ps):
             D = (g[b][:, cols] - gh) - gl
             errs.append(float(np.max(np.sum(np.abs(D), 0)) / np.max(np.sum(np.abs(gh), 0))))
         print("b=%d sigma=%d grad rel err fixed %.3e mixed %.3e" % (b, sigma, errs[0], errs[1]))
-        assert errs[0] <= 2 ** sigma * 512 * U32 / 8, errs
-        # equal accuracy with the tiers in both passes
-        assert errs[1] <= max(2 ** sigma * 512 * U32 / 8, 2 * errs[0]), errs
+        # the backward tolerance 1e-5 for FP32, and equal accuracy with the
+        # tiers in both passes
+        assert errs[0] <= 1e-5, errs
+        assert errs[1] <= max(1e-5, 2 * errs[0]), errs
     g = np.random.default_rng(1)
     E = g.standard_normal((512, 512))
     E /= metrics.norm1(E)

@@ -199,6 +199,28 @@ def test_forced_tier_chains_within_bound(ps, pattern):
     assert err <= bound, (err, bound)
 
 
+def test_y_reformed_when_u_nu_is_near_u32(ps):
+    """Eq. (cond-Y) asks ||Y_hat - Y|| <= u_nu ||Y||.  Here the first Horner
+    product is FP32 with u_1 ~ 7.6 u32, too close to the ~5 u32 error of the
+    FP32-formed Y: the cast launch forms Y in FP64 as well and the FP32
+    product reads its rounding.  The report counts Y in both tiers."""
+    n, m, s = 576, 30, 6
+    c = coeffs.taylor_exp(m)
+    A = _rand(n, 1.0, 31)
+    E, rep = ps.ps_expm(to_dev(A), m, s=s, sigma=0, mode="mixed", report=True)
+    steps = rep["tier"][1:rep["first_step"] + 1]
+    assert rep["tier"][1] == 1 and U32 < rep["u"][1] < 16 * U32, (rep["tier"], rep["u"][1] / U32)
+    assert rep["gemms"][0] == (s - 1) + steps.count(0) and rep["gemms"][1] == 1 + steps.count(1), rep["gemms"]
+    cols = sample_cols(n, 6, seed=4)
+    Wh, Wl = oracle.expm_apply_dd(A, c, 0, np.eye(n)[:, cols])
+    assert relerr_cols(to_np(E)[:, cols], Wh, Wl) <= TOL64
+    # with u_1 >= 16 u32 (a smaller norm) Y stays FP32 only
+    _, rep2 = ps.ps_expm(to_dev(_rand(n, 0.8, 31)), m, s=s, sigma=0, mode="mixed", report=True)
+    assert rep2["tier"][1] == 1 and rep2["u"][1] >= 16 * U32
+    steps2 = rep2["tier"][1:rep2["first_step"] + 1]
+    assert rep2["gemms"][0] == (s - 2) + steps2.count(0), rep2["gemms"]
+
+
 def test_y_formed_in_fp32_when_the_plan_allows(ps):
     """Eq. (cond-Y): Y = X^s needs the accuracy of the first lower-precision
     Horner step.  In mixed mode with FP32 allowed and n > 512 the power table

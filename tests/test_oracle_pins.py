@@ -323,6 +323,27 @@ def test_table1_cost_ratio_and_block_counts():
         assert all(d[i] >= d[i + 1] for i in range(r - 1))
 
 
+def test_m_low_from_table1_within_table2s_range():
+    # Table 2 prints M_low between 22% and 27% for every class and size, and
+    # section 3.3.1 says about a fifth of the products of Table 1's runs use
+    # precision u^(1/2) or lower: Table 1's digits give 3/12, 4/15, 5/19, 6/26
+    want = {32: (3, 12), 64: (4, 15), 128: (5, 19), 256: (6, 26)}
+    for ln in open(os.path.join(GOLD, "table1_cauchy100.txt")):
+        if not ln.strip() or ln[0] == "#":
+            continue
+        head, tail = ln.split("|")
+        D, m, s, r, _ = head.split()
+        d = [int(x) for x in tail.split()]
+        D, s, r = int(D), int(s), int(r)
+        ml = metrics.m_low(D, s, r, d)
+        k, tot = want[D]
+        assert ml == k / tot
+        assert 0.22 <= ml <= 0.27
+    # the boundary is inclusive (u_i = u^(1/2) counts) and the powers never do
+    assert metrics.m_low(32, 3, 2, [16, 17]) == 1 / 4
+    assert metrics.m_low(32, 3, 2, [1, 1]) == 2 / 4
+
+
 def test_table2_saving():
     g = dict((ln.split()[0], float(ln.split()[1])) for ln in open(os.path.join(GOLD, "table2_runtime.txt"))
              if ln.strip() and ln[0] != "#")
