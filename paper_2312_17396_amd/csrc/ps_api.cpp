@@ -226,15 +226,17 @@ MatArg ws_mat(char* ws, size_t off, int64_t n, size_t stride_bytes, int esize) {
 void model_cost(int working, int s, int r, const int* tier, double* saving, double* m_low) {
   const double D = -std::log10(tier_unit_roundoff(working));
   const double half = std::sqrt(tier_unit_roundoff(working));
-  double dsum = 0.0;
+  // 1 - ((s-1) D + sum d_i) / ((s+r-1) D) written as sum (D - d_i) / ((s+r-1) D),
+  // which is exactly 0 when every product runs in the working precision
+  double gap = 0.0;
   int low = 0;
   for (int i = 1; i <= r; ++i) {
     const double ut = tier_unit_roundoff(tier[i]);
-    dsum += -std::log10(ut);
+    gap += D + std::log10(ut);
     low += ut >= half ? 1 : 0;
   }
   const int prods = s - 1 + r;
-  *saving = prods > 0 ? 1.0 - ((s - 1) * D + dsum) / (prods * D) : 0.0;
+  *saving = prods > 0 ? gap / (prods * D) : 0.0;
   *m_low = prods > 0 ? (double)low / prods : 0.0;
 }
 

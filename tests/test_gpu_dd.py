@@ -108,6 +108,47 @@ def test_dd_inputs_with_low_parts_vs_exact_rationals(ps):
     assert float(err / scale) <= 64 * U_DD
 
 
+def _exact_expm(Aq, cq, sigma):
+    """(p(2^-sigma A))^(2^sigma) in exact rational arithmetic (object arrays of
+    Fractions), p by Horner's rule with the exact coefficients cq"""
+    n = Aq.shape[0]
+    X = Aq * F(1, 2 ** sigma)
+    I = np.array([[F(int(i == j)) for j in range(n)] for i in range(n)], dtype=object)
+    P = I * cq[-1]
+    for c in reversed(cq[:-1]):
+        P = P.dot(X) + I * c
+    for _ in range(sigma):
+        P = P.dot(P)
+    return P
+
+
+@pytest.mark.parametrize("n,sigma", [(16, 1), (24, 0)])
+@pytest.mark.parametrize("mode", ["fixed", "mixed"])
+def test_dd_dyadic_vs_exact_rationals(ps, n, sigma, mode):
+    """A reference with more digits than double-double: dyadic inputs with
+    nonzero low parts (hi + lo, lo ~ 2^-70 hi) and the Taylor coefficients as
+    double-double pairs (dyadic too), so p(2^-sigma A)^(2^sigma)
+    is an exact rational; every entry of the GPU result against it."""
+    g = np.random.default_rng(40 + n)
+    m = 18
+    hi = np.ldexp(np.round(g.standard_normal((n, n)) * 2 ** 12), -12) * (1.5 / n)
+    lo = np.ldexp(np.round(g.uniform(-1, 1, (n, n)) * 2 ** 20), -20) * np.ldexp(np.abs(hi) + 2 ** -12, -70)
+    import math
+    ch = [float(F(1, math.factorial(k))) for k in range(m + 1)]           # 1/k! as double-double pairs
+    cl = [float(F(1, math.factorial(k)) - F(h)) for k, h in enumerate(ch)]
+    Aq = np.array([[F(hi[i, j]) + F(lo[i, j]) for j in range(n)] for i in range(n)], dtype=object)
+    cq = [F(a) + F(b) for a, b in zip(ch, cl)]
+    P = _exact_expm(Aq, cq, sigma)
+    E, rep = ps.ps_expm_dd(_dd_tensor(hi, lo), m, s=5, sigma=sigma, coef=(ch, cl), mode=mode, report=True)
+    E = E.cpu().numpy()
+    diff = [[abs(F(E[0, i, j]) + F(E[1, i, j]) - P[i, j]) for j in range(n)] for i in range(n)]
+    num = max(sum(diff[i][j] for i in range(n)) for j in range(n))
+    den = max(sum(abs(P[i, j]) for i in range(n)) for j in range(n))
+    err = float(num / den)
+    print("dd n=%d sigma=%d %s: rel err %.3e (%.1f u_dd), tiers %s" % (n, sigma, mode, err, err / U_DD, rep["tier"]))
+    assert err <= 2.0 ** sigma * 64 * n * U_DD, (err, rep["tier"])
+
+
 def test_dd_rejects_bad_arguments(ps):
     import torch
     with pytest.raises(ps.PSError):

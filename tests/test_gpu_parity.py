@@ -286,6 +286,26 @@ def test_dense_1024_sampled_columns(ps, t):
             assert tiers[1:] == rep["tier"][1:]
 
 
+@pytest.mark.parametrize("t", [1.0, 64.0])
+def test_dense_1024_all_columns(ps, t):
+    """Every column of the dense n = 1024 results (||A||_1 = 1, sigma = 0 and
+    ||A||_1 = 64, sigma = 6), plain and mixed, against the oracle's PS carried
+    out in double-double followed by the sigma squarings in double-double
+    (the oracle pins PS in dd to the plain definition within 1e-28)."""
+    A = inputs.dense_1024(t)
+    sigma = inputs.squarings_for(t)
+    c = coeffs.taylor_exp(30)
+    X = np.ldexp(A, -sigma)                      # exact power-of-two scaling
+    Rh, Rl = oracle.ps_dd(X, c, 6)
+    for _ in range(sigma):
+        Rh, Rl = oracle.gemm_dd(Rh, Rl, Rh, Rl)
+    for mode in ("fixed", "mixed"):
+        E = to_np(ps.ps_expm(to_dev(A), 30, s=6, sigma=sigma, mode=mode))
+        err = metrics.rel_err_1(E, Rh, Rl)
+        print("all columns t=%g mode=%s sigma=%d err=%.3e" % (t, mode, sigma, err))
+        assert err <= TOL64, (t, mode, err)
+
+
 # ------------------------------------------------------------ batches / determinism
 def test_strided_batch_equals_single_calls_bitwise(ps):
     import torch
