@@ -579,27 +579,29 @@ __device__ __forceinline__ void pack_tile_lowp(const C* Cs, int t_out, char* pou
 #pragma unroll
     for (int e = 0; e < 8; ++e) o.h[e] = bf16_bits_rne((float)Cs[(seg + e) * CSTR + r]);
     *(uint4*)((uint16_t*)pout + (m0 + r) * Kp + n0 + seg) = o.q;
-  } else if (t < kTileM * kTileN / 32) {
-    const int r = t % kTileM, blk = t / kTileM;   // one E8M0 block = 32 columns of a row
-    float vals[32];
+  } else {
+    // one E8M0 block = 32 columns of a row, shared by four consecutive lanes
+    // (eight values each); the block maximum by two butterfly steps
+    static_assert(NT == 4 * kTileM * kTileN / 32, "four lanes per E8M0 block");
+    const int q = t >> 2, part = t & 3;
+    const int r = q % kTileM, blk = q / kTileM;
+    float vals[8];
     float amax = 0.0f;
 #pragma unroll
-    for (int e = 0; e < 32; ++e) {
-      vals[e] = (float)Cs[(32 * blk + e) * CSTR + r];
+    for (int e = 0; e < 8; ++e) {
+      vals[e] = (float)Cs[(32 * blk + 8 * part + e) * CSTR + r];
       amax = fmaxf(amax, fabsf(vals[e]));
     }
+    amax = fmaxf(amax, __shfl_xor(amax, 1, 64));
+    amax = fmaxf(amax, __shfl_xor(amax, 2, 64));
     const int sbyte = e8m0_for(amax);
     const int sexp = sbyte - 127;
-    union { uint4 q[2]; uint32_t wv[8]; } o;
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      o.wv[e] = pack4_e4m3(ldexpf(vals[4 * e], -sexp), ldexpf(vals[4 * e + 1], -sexp),
-                           ldexpf(vals[4 * e + 2], -sexp), ldexpf(vals[4 * e + 3], -sexp));
+    uint2 o;
+    o.x = pack4_e4m3(ldexpf(vals[0], -sexp), ldexpf(vals[1], -sexp), ldexpf(vals[2], -sexp), ldexpf(vals[3], -sexp));
+    o.y = pack4_e4m3(ldexpf(vals[4], -sexp), ldexpf(vals[5], -sexp), ldexpf(vals[6], -sexp), ldexpf(vals[7], -sexp));
     uint8_t* p8 = (uint8_t*)pout;
-    uint4* dst = (uint4*)(p8 + (m0 + r) * Kp + n0 + 32 * blk);
-    dst[0] = o.q[0];
-    dst[1] = o.q[1];
-    p8[Mp * Kp + (m0 + r) * (Kp / 32) + n0 / 32 + blk] = (uint8_t)sbyte;
+    *(uint2*)(p8 + (m0 + r) * Kp + n0 + 32 * blk + 8 * part) = o;
+    if (part == 0) p8[Mp * Kp + (m0 + r) * (Kp / 32) + n0 / 32 + blk] = (uint8_t)sbyte;
   }
 }
 
@@ -641,48 +643,37 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
   const int t = threadIdx.x;
   const int row = t & 63;
   const int64_t gr = m0 + row;
-  // this thread's elements of B_{i-1}, all loads in flight together: issued
-  // before the main loop for the low-precision products (short loops with
-  // free registers), after it for the FP64 / FP32 ones
+  // this thread's elements of B_{i-1}: the loads are issued first, before the
+  // tiers are known and before the main loop's loads, so their round trip
+  // overlaps everything up to the epilogue (the block is in the working
+  // precision whatever the tier)
   W bq[TILE_Q];
-  auto load_b = [&]() {
 #pragma unroll
-    for (int q = 0; q < TILE_Q; ++q) {
-      const int64_t gc = n0 + (t >> 6) + NW * q;
-      const bool in = gr < h.nvb && gc < h.nvb;
-      const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
-      bq[q] = in ? x : W(0);
-    }
-  };
+  for (int q = 0; q < TILE_Q; ++q) {
+    const int64_t gc = n0 + (t >> 6) + NW * q;
+    const bool in = gr < h.nvb && gc < h.nvb;
+    const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
+    bq[q] = in ? x : W(0);
+  }
   if (t_in == WT) {
     typename MF<W>::V acc[2];
     mainloop_lds<W, false, false>((const W*)h.pin, n, h.ysrc, h.ldy, n, m0, n0, smem, acc);
     frag_to_cs<W, W>(acc, Cs, h.yscale);
-    load_b();
   } else if (t_in == 1) {   // FP32 product below an FP64 working precision
     typename MF<float>::V acc[2];
     mainloop_lds<float, false, false>((const float*)h.pin, n, h.yf32, n, n, m0, n0, smem, acc);
     frag_to_cs<float, W>(acc, Cs, 1.0);
-    load_b();
   } else if (t_in == 2) {
-    load_b();
     f4v acc[2];
     mainloop_lowp<false>((const uint8_t*)h.pin, nullptr, (const uint8_t*)h.ybf16, nullptr, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else if (t_in == 3) {
     f4v acc[2];
     const uint8_t* p8 = (const uint8_t*)h.pin;
-    if (FP8ALL && n <= LP_ALL * 128) {
-      // every slab's registers are taken by the main loop: B_{i-1} after it
-      mainloop_fp8_all(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
-      load_b();
-    } else {
-      load_b();
-      mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
-    }
+    if (FP8ALL && n <= LP_ALL * 128) mainloop_fp8_all(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
+    else mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
-  } else {
-    load_b();   // cast only
+  } else {   // cast only
     if (h.fyc != 0.0) {
 #pragma unroll
       for (int q = 0; q < TILE_Q; ++q) {

@@ -103,7 +103,7 @@ hipError_t launch_gemm(int working, int64_t n, int batch, MatArg A, int transA, 
 // k_horner: one tile of one Horner step per workgroup
 // ---------------------------------------------------------------------------
 template <typename W>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_horner(HornerArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_horner(HornerArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   const Layout& L = a.L;
