@@ -116,7 +116,7 @@ Opts read_opts(const ps_opts* o, int working) {
 
 namespace psk {
 
-Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg, int npow_min) {
+Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg, int npow_min, int colsum_rows) {
   Layout L;
   memset(&L, 0, sizeof L);
   L.n = n;
@@ -147,7 +147,8 @@ Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_a
   L.off_ybf16 = off; off += al256((size_t)L.Mp * L.Kp * 2);
   L.off_yfp8 = off;  off += al256((size_t)L.Mp * L.Kp);
   L.off_yfp8s = off; off += al256((size_t)L.Mp * (L.Kp / 32));
-  L.off_colsum = off; off += al256((size_t)(L.nB + 2) * ((n + kRowChunk - 1) / kRowChunk) * n * 8);
+  L.colsum_rows = colsum_rows;
+  L.off_colsum = off; off += al256((size_t)(L.nB + 2) * ((n + colsum_rows - 1) / colsum_rows) * n * 8);
   L.off_plan = off;  off += al256(sizeof(Plan));
   L.bytes = al256(off);
   return L;

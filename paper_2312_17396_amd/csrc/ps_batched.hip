@@ -69,7 +69,6 @@ struct BatchArgs {
   const BatchItem* items;
   BatchRes* res;
   const int* tile_tasks;  // (matrix << 8) | tile, largest matrices first
-  const int* col_tasks;   // (matrix << 8) | group of NW columns
   int* pick;              // per matrix: 0 -> L[0], 1 -> L[1]
   int* chosen;            // per matrix: chosen block size (for reports)
   int batch;
@@ -198,15 +197,244 @@ __global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
   for (int q = 0; q < TILE_Q; ++q) X[m0 + row + (n0 + (t >> 6) + NW * q) * np] = v[q];
 }
 
-// ---- power table step j: X_j = X_a X_b (a = ceil(j/2), b = floor(j/2), X_1 = beta A)
+// Sums over the 64 lanes of a wave of eight values per lane: three exchange
+// steps that each keep half of the values (lane bits 5, 4, 3 pick the half),
+// then a butterfly over lane bits 2..0.  On return lane L holds the total of
+// v[L >> 3].  10 shuffles instead of 48 for eight separate butterflies.
+__device__ __forceinline__ double wave_sum8(const double v[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double a4[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double send = b5 ? v[k] : v[4 + k];
+    a4[k] = (b5 ? v[4 + k] : v[k]) + __shfl_xor(send, 32, 64);   // column 4 b5 + k
+  }
+  double a2[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double send = b4 ? a4[k] : a4[2 + k];
+    a2[k] = (b4 ? a4[2 + k] : a4[k]) + __shfl_xor(send, 16, 64);   // column 4 b5 + 2 b4 + k
+  }
+  const double send = b3 ? a2[0] : a2[1];
+  double c = (b3 ? a2[1] : a2[0]) + __shfl_xor(send, 8, 64);       // column 4 b5 + 2 b4 + b3
+  c += __shfl_xor(c, 4, 64);
+  c += __shfl_xor(c, 2, 64);
+  c += __shfl_xor(c, 1, 64);
+  return c;
+}
+
+// ---- block assembly of one 64 x 64 tile of the padded order, in the epilogue
+// of the launch that forms Y = X_s (or, for s = 1, on its own): Y into its
+// power slot, B_0..B_r (the same terms in the same order as the column pass
+// of the single-matrix path: c_{si} I, then c_{si+j} X_j for increasing j, the
+// trivial last step folded into B_{r-1}), the low-precision copies of Y, and
+// the 64-row partial column abs sums of B_i, Y and X_1 that the plan reads
+// (the layout's colsum_rows = 64 = the tile height).  Each wave holds 64
+// rows of one column per element q, as in the column pass, so the E8M0
+// blocks of 32 rows are half-waves.  ycs: the product tile in LDS (Y =
+// alpha ycs), or nullptr when s = 1 (Y = X_1, read from memory).
+constexpr int kAsmGather = 5;   // FP32: the powers X_1..X_{s-1} of a tile gathered at once for s <= this
+
+// X_1..X_{s-1} of the thread's elements of a tile (zero outside the order nv
+// and for j >= s), all loads in flight together
 template <typename W>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower(BatchArgs a, int j) {
-  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
+__device__ __forceinline__ void gather_powers(const BatchRes& it, int64_t m0, int64_t n0,
+                                              W x[kAsmGather - 1][TILE_Q]) {
+  const Layout& L = it.L;
+  const int64_t n = L.n, nv = it.nv, se = (int64_t)(L.slot / sizeof(W));
+  const W* pw = (const W*)(it.ws + L.off_pow);
+  const W* X1 = (const W*)it.X1;
+  const double x1s = ldexp(1.0, -it.sigma);
+  const int t = threadIdx.x;
+  const int64_t gr = m0 + (t & 63);
+#pragma unroll
+  for (int jj = 0; jj < kAsmGather - 1; ++jj)
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) {
+      const int64_t gc = n0 + (t >> 6) + NW * q;
+      const bool in = jj + 1 < L.s && gr < nv && gc < nv;
+      const int64_t rr = in ? gr : 0, cc = in ? gc : 0;
+      const W v = (jj == 0) ? (W)(x1s * (double)X1[rr + cc * n]) : pw[(int64_t)(jj - 1) * se + rr + cc * n];
+      x[jj][q] = in ? v : W(0);
+    }
+}
+
+// HAVE_X: x already holds gather_powers' values (FP32, s <= kAsmGather)
+template <typename W, bool HAVE_X>
+__device__ __forceinline__ void assemble_tile(const BatchArgs& a, const BatchRes& it, const W* ycs, double alpha,
+                                              int64_t m0, int64_t n0, W (&x)[kAsmGather - 1][TILE_Q]) {
+  const Layout& L = it.L;
+  const int64_t n = L.n, nv = it.nv;
+  const int s = L.s, r = L.r, m = L.m, nB = L.nB;
+  const int64_t se = (int64_t)(L.slot / sizeof(W));
+  char* ws = it.ws;
+  W* pw = (W*)(ws + L.off_pow);
+  W* Bm = (W*)(ws + L.off_B);
+  double* colsum = (double*)(ws + L.off_colsum);
+  const int64_t nch = (n + L.colsum_rows - 1) / L.colsum_rows, chunk = m0 / L.colsum_rows;
+  const double x1s = ldexp(1.0, -it.sigma);
+  const W* X1 = (const W*)it.X1;
+  const unsigned mask = a.mode == PS_MODE_MIXED ? a.mask : 0u;
+  const bool want32 = std::is_same<W, double>::value && ((mask >> 1) & 1u);
+  const bool want16 = (mask >> 2) & 1u, want8 = (mask >> 3) & 1u;
+  const int64_t Kp = L.Kp, Ks = Kp / 32;
+  float* yf32 = (float*)(ws + L.off_yf32);
+  uint16_t* ybf = (uint16_t*)(ws + L.off_ybf16);
+  uint8_t* y8 = (uint8_t*)(ws + L.off_yfp8);
+  uint8_t* y8s = (uint8_t*)(ws + L.off_yfp8s);
+  const int t = threadIdx.x, lane = t & 63;
+  const int64_t gr = m0 + lane;
+  if (m0 == 0 && n0 == 0 && t < 64) {   // |c_k| for the a-priori planning rule
+    Plan* P = (Plan*)(ws + L.off_plan);
+    for (int k = lane; k <= m; k += 64) P->abs_coef[k] = fabs(a.cf.c[k]);
+  }
+  // the thread's TILE_Q elements: row gr, columns n0 + (t >> 6) + NW q
+  auto col_q = [&](int q) { return n0 + (t >> 6) + NW * q; };
+  auto inner_q = [&](int q) { return gr < nv && col_q(q) < nv; };
+  // X_j (j < s) of these elements, zero outside the matrix's order
+  auto load_x = [&](int j, W xv[TILE_Q]) {
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) {
+      const bool in = inner_q(q);
+      const int64_t gc = in ? col_q(q) : 0, rr = in ? gr : 0;
+      const W v = (j == 1) ? (W)(x1s * (double)X1[rr + gc * n]) : pw[(int64_t)(j - 2) * se + rr + gc * n];
+      xv[q] = in ? v : W(0);
+    }
+  };
+  // column abs sums over this tile's 64 rows (lane = row): lane 8c holds the
+  // sum of column c of the wave's eight
+  auto put_sums = [&](int qty, double v[TILE_Q]) {
+    const double tot = wave_sum8(v);
+    if ((lane & 7) == 0) colsum[((int64_t)qty * nch + chunk) * n + col_q(lane >> 3)] = tot;
+  };
+  // Y, its copies and column sums
+  W y[TILE_Q];
+  if (ycs) {
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) {
+      const W v = (W)(alpha * (double)ycs[((t >> 6) + NW * q) * CSTR + lane]);
+      y[q] = inner_q(q) ? v : W(0);
+      pw[(int64_t)(s - 2) * se + gr + col_q(q) * n] = y[q];
+    }
+  } else {
+    load_x(1, y);
+  }
+  {
+    double sv[TILE_Q];
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) {
+      const int64_t gc = col_q(q);
+      sv[q] = fabs((double)y[q]);
+      if (want32) yf32[gr + gc * n] = (float)y[q];
+      if (want16) ybf[gc * Kp + gr] = bf16_bits_rne((float)y[q]);
+      if (want8) {
+        float av = fabsf((float)y[q]);
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) av = fmaxf(av, __shfl_xor(av, off, 64));
+        const int sbyte = e8m0_for(av);
+        float qv = ldexpf((float)y[q], -(sbyte - 127));
+        qv = fminf(fmaxf(qv, -448.0f), 448.0f);
+        const int wv = __builtin_amdgcn_cvt_pk_fp8_f32(qv, 0.0f, 0, false);
+        y8[gc * Kp + gr] = (uint8_t)(wv & 0xff);
+        if ((gr & 31) == 0) y8s[gc * Ks + gr / 32] = (uint8_t)sbyte;
+      }
+    }
+    if (s == 1) {   // X_1 is Y
+      double sx[TILE_Q];
+#pragma unroll
+      for (int q = 0; q < TILE_Q; ++q) sx[q] = sv[q];
+      put_sums(nB + 1, sx);
+    }
+    put_sums(nB, sv);
+  }
+  // block i: c_{si} I, then c_{si+j} X_j for increasing j; stored with the
+  // trivial last step folded in, its column sums from the unfolded values
+  auto finish_block = [&](int i, const W bv[TILE_Q]) {
+    double v[TILE_Q];
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) {
+      v[q] = fabs((double)bv[q]);
+      W outv = bv[q];
+      if (L.trivial_last && i == r - 1) outv += (W)a.cf.c[m] * y[q];   // step r: c_m I * Y
+      if (inner_q(q)) Bm[(int64_t)i * se + gr + col_q(q) * n] = outv;
+    }
+    put_sums(i, v);
+  };
+  auto init_block = [&](int i, W bv[TILE_Q]) {
+    const W c0 = (i < nB && s * i <= m) ? (W)a.cf.c[s * i] : W(0);
+#pragma unroll
+    for (int q = 0; q < TILE_Q; ++q) bv[q] = (gr == col_q(q) && gr < nv) ? c0 : W(0);
+  };
+  // FP32: every power X_1..X_{s-1} of the elements loaded at once (s <= PG),
+  // before the GEMM main loop when the caller passes them in xpre
+  constexpr int PG = std::is_same<W, float>::value ? kAsmGather : 1;
+  if (PG > 1 && s <= PG) {
+    if (!HAVE_X) gather_powers<W>(it, m0, n0, x);
+    if (s > 1) {
+      double sx[TILE_Q];
+#pragma unroll
+      for (int q = 0; q < TILE_Q; ++q) sx[q] = fabs((double)x[0][q]);
+      put_sums(nB + 1, sx);
+    }
+    for (int i = 0; i < nB; ++i) {
+      W bv[TILE_Q];
+      init_block(i, bv);
+#pragma unroll
+      for (int jj = 0; jj < PG - 1; ++jj) {
+        const int k = s * i + jj + 1;
+        if (jj + 1 < s && k <= m) {
+          const W ck = (W)a.cf.c[k];
+#pragma unroll
+          for (int q = 0; q < TILE_Q; ++q) bv[q] += ck * x[jj][q];
+        }
+      }
+      finish_block(i, bv);
+    }
+    return;
+  }
+  // otherwise blocks in chunks of BC, the powers read once per chunk
+  constexpr int BC = sizeof(W) == 8 ? 1 : 2;
+  for (int i0 = 0; i0 < nB; i0 += BC) {
+    W bv[BC][TILE_Q];
+#pragma unroll
+    for (int ii = 0; ii < BC; ++ii) init_block(i0 + ii, bv[ii]);
+    for (int j = 1; j < s; ++j) {
+      W xj[TILE_Q];
+      load_x(j, xj);
+      if (j == 1 && i0 == 0) {
+        double sx[TILE_Q];
+#pragma unroll
+        for (int q = 0; q < TILE_Q; ++q) sx[q] = fabs((double)xj[q]);
+        put_sums(nB + 1, sx);
+      }
+#pragma unroll
+      for (int ii = 0; ii < BC; ++ii) {
+        const int k = s * (i0 + ii) + j;
+        if (i0 + ii < nB && k <= m) {
+          const W ck = (W)a.cf.c[k];
+#pragma unroll
+          for (int q = 0; q < TILE_Q; ++q) bv[ii][q] += ck * xj[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < BC; ++ii)
+      if (i0 + ii < nB) finish_block(i0 + ii, bv[ii]);
+  }
+}
+
+// ---- power table step j: X_j = X_a X_b (a = ceil(j/2), b = floor(j/2), X_1 = beta A).
+// ASM = false: the tiles of matrices with j < s; ASM = true: those with j = s
+// (Y), whose block assembly follows in the same workgroup.  Two kernels, so
+// that the plain products keep the register count (and occupancy) of a GEMM.
+template <typename W, bool ASM>
+__device__ __forceinline__ void bpower_tile(const BatchArgs& a, int j, char* smem) {
   const int task = a.tile_tasks[blockIdx.x];
   const int b = task >> 8, tile = task & 255;
   const BatchRes& it = a.res[b];
   const Layout& L = it.L;
-  if (j > L.s) return;   // uniform: the whole workgroup leaves
+  if (ASM ? (j != L.s) : (j >= L.s)) return;   // uniform: the whole workgroup leaves
   const int64_t n = L.n;
   const int ntm = tiles_m(n);
   const W* X1 = (const W*)it.X1;
@@ -219,36 +447,45 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const W* xa = (pa == 1) ? X1 : pw + (int64_t)(pa - 2) * se;
   const W* xb = (pb == 1) ? X1 : pw + (int64_t)(pb - 2) * se;
   const double alpha = (pa == 1 ? beta : 1.0) * (pb == 1 ? beta : 1.0);
-  gemm_tile<W, false, false>(xa, n, xb, n, pw + (int64_t)(j - 2) * se, n, n, n, (int64_t)(tile % ntm) * kTileM,
-                             (int64_t)(tile / ntm) * kTileN, alpha, 0, smem);
+  const int64_t m0 = (int64_t)(tile % ntm) * kTileM, n0 = (int64_t)(tile / ntm) * kTileN;
+  if (!ASM) {
+    gemm_tile<W, false, false>(xa, n, xb, n, pw + (int64_t)(j - 2) * se, n, n, n, m0, n0, alpha, 0, smem);
+    return;
+  }
+  typename MF<W>::V acc[2];
+  mainloop_lds<W, false, false>(xa, n, xb, n, n, m0, n0, smem, acc);
+  W* Cs = (W*)smem;
+  frag_to_cs<W, W>(acc, Cs, 1.0);
+  __syncthreads();
+  // the assembly's power loads are issued after the main loop: loaded before
+  // it, they held enough registers to halve the GEMM's occupancy (slower)
+  W x[kAsmGather - 1][TILE_Q];
+  assemble_tile<W, false>(a, it, Cs, alpha, m0, n0, x);
 }
 
-// ---- blocks, norms, low-precision copies of Y: one wave per column
 template <typename W>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(W) == 4 ? 6 : 4))) void k_bassemble(BatchArgs a) {
-  const int task = a.col_tasks[blockIdx.x];
-  const int b = task >> 8, grp = task & 255;
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower(BatchArgs a, int j) {
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
+  bpower_tile<W, false>(a, j, smem);
+}
+
+template <typename W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower_asm(BatchArgs a, int j) {
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
+  bpower_tile<W, true>(a, j, smem);
+}
+
+// ---- block assembly of the matrices with s = 1 (no power products: Y = X_1)
+template <typename W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bassemble1(BatchArgs a) {
+  const int task = a.tile_tasks[blockIdx.x];
+  const int b = task >> 8, tile = task & 255;
   const BatchRes& it = a.res[b];
-  const Layout& L = it.L;
-  const int64_t col = (int64_t)grp * NW + (threadIdx.x >> 6);
-  if (col >= L.n) return;   // no workgroup barrier below
-  AssembleArgs aa;
-  aa.n = L.n;
-  aa.nv = it.nv;
-  aa.m = L.m;
-  aa.s = L.s;
-  aa.r = L.r;
-  aa.nB = L.nB;
-  aa.trivial_last = L.trivial_last;
-  aa.X1 = MatArg{it.X1, L.n, 0};
-  aa.x1_scale = ldexp(1.0, -it.sigma);
-  aa.pow_shift = 0;
-  aa.ws = it.ws;
-  aa.ws_stride = 0;
-  aa.L = L;
-  aa.tier_mask = a.mode == PS_MODE_MIXED ? a.mask : 0u;
-  aa.y_f32 = 0;   // Y in FP64: the grid path forms it in FP32 only above order 512
-  assemble_column<W, false>(aa, a.cf, aa.ws, (const W*)it.X1, col, 0);
+  if (it.L.s != 1) return;   // uniform
+  const int ntm = tiles_m(it.L.n);
+  W x[kAsmGather - 1][TILE_Q];
+  assemble_tile<W, false>(a, it, (const W*)nullptr, 1.0, (int64_t)(tile % ntm) * kTileM,
+                          (int64_t)(tile / ntm) * kTileN, x);
 }
 
 // ---- precision plan: one workgroup per matrix
@@ -378,9 +615,10 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan2 {
   std::vector<BatchItem> items;
-  std::vector<int> tile_tasks, col_tasks;
+  std::vector<int> tile_tasks;
   int smax = 1, kmax = 0, sigmax = 0;
-  size_t off_items, off_res, off_tiles, off_cols, off_pick, off_chosen, total;
+  std::vector<char> s_possible;   // s_possible[s]: some matrix may take block size s
+  size_t off_items, off_res, off_tiles, off_pick, off_chosen, total;
 };
 
 int s_floor(int m) {
@@ -404,6 +642,7 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
   if (m < 0 || m > kMaxDegree) return bfail(PS_ERR_ARG, "degree m = %d out of range", m);
   const int esize = dt == PS_F64 ? 8 : 4;
   P.items.resize(batch);
+  P.s_possible.assign(2, 0);
   std::vector<double> cost(batch);
   size_t off = 0;
   for (int b = 0; b < batch; ++b) {
@@ -418,8 +657,8 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
     const int s0 = sb ? sb : s_floor(m), s1 = sb ? sb : s_ceil(m);
     if (m / s0 + 1 > PS_MAX_BLOCKS || m / s1 + 1 > PS_MAX_BLOCKS) return bfail(PS_ERR_ARG, "too many blocks");
     const int64_t np = (nb + kTileM - 1) / kTileM * kTileM;   // padded order
-    it.L[0] = make_layout(dt, np, m, s0, 1, 0);
-    it.L[1] = make_layout(dt, np, m, s1, 1, 0);
+    it.L[0] = make_layout(dt, np, m, s0, 1, 0, 0, kTileM);   // partial column sums per 64-row tile
+    it.L[1] = make_layout(dt, np, m, s1, 1, 0, 0, kTileM);
     it.s_fixed = sb != 0;
     it.sigma = sg;
     it.nv = nb;
@@ -441,6 +680,8 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
     const int gem = (std::max(s0, s1) - 1) + (m / s0) + sg;
     cost[b] = (double)nb * nb * nb * gem;
     P.smax = std::max(P.smax, std::max(s0, s1));
+    if ((int)P.s_possible.size() <= std::max(s0, s1)) P.s_possible.resize(std::max(s0, s1) + 1, 0);
+    P.s_possible[s0] = P.s_possible[s1] = 1;
     P.kmax = std::max(P.kmax, std::max(it.L[0].first_step, it.L[1].first_step));
     P.sigmax = std::max(P.sigmax, sg);
   }
@@ -449,19 +690,15 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
   P.tile_tasks.clear();
-  P.col_tasks.clear();
   for (int b : order) {
     const int64_t nb = n[b];
     const int nt = (int)(((nb + kTileM - 1) / kTileM) * ((nb + kTileN - 1) / kTileN));   // tiles of the padded square
     for (int t = 0; t < nt; ++t) P.tile_tasks.push_back((b << 8) | t);
-    const int ng = (int)((P.items[b].L[0].n + NW - 1) / NW);   // columns of the padded square
-    for (int g = 0; g < ng; ++g) P.col_tasks.push_back((b << 8) | g);
   }
   P.off_items = al256(off);
   P.off_res = al256(P.off_items + sizeof(BatchItem) * (size_t)batch);
   P.off_tiles = al256(P.off_res + sizeof(BatchRes) * (size_t)batch);
-  P.off_cols = al256(P.off_tiles + sizeof(int) * P.tile_tasks.size());
-  P.off_pick = al256(P.off_cols + sizeof(int) * P.col_tasks.size());
+  P.off_pick = al256(P.off_tiles + sizeof(int) * P.tile_tasks.size());
   P.off_chosen = al256(P.off_pick + sizeof(int) * (size_t)batch);
   P.total = al256(P.off_chosen + sizeof(int) * (size_t)batch);
   return PS_OK;
@@ -498,15 +735,11 @@ ps_status upload_and_args(const Plan2& P, char* ws, hipStream_t st, BatchArgs& b
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws + P.off_tiles, P.tile_tasks.data(), sizeof(int) * P.tile_tasks.size(),
                        hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + P.off_cols, P.col_tasks.data(), sizeof(int) * P.col_tasks.size(), hipMemcpyHostToDevice,
-                       st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors are released on return
   if (e != hipSuccess) return bfail(PS_ERR_HIP, "descriptor upload: %s", hipGetErrorString(e));
   ba.items = (const BatchItem*)(ws + P.off_items);
   ba.res = (BatchRes*)(ws + P.off_res);
   ba.tile_tasks = (const int*)(ws + P.off_tiles);
-  ba.col_tasks = (const int*)(ws + P.off_cols);
   ba.pick = (int*)(ws + P.off_pick);
   ba.chosen = (int*)(ws + P.off_chosen);
   ba.batch = (int)P.items.size();
@@ -517,7 +750,7 @@ ps_status upload_and_args(const Plan2& P, char* ws, hipStream_t st, BatchArgs& b
 // the fixed launch sequence of a batch (stream-ordered; captured by ps_batched_prepare)
 ps_status launch_batch(int W, const BatchArgs& ba, const Plan2& P, hipStream_t st) {
   const dim3 blk(NT);
-  const unsigned nmat = (unsigned)ba.batch, ntile = (unsigned)P.tile_tasks.size(), ncol = (unsigned)P.col_tasks.size();
+  const unsigned nmat = (unsigned)ba.batch, ntile = (unsigned)P.tile_tasks.size();
 #define PS_BLAUNCH(KER, GRID, ...)                                                          \
   do {                                                                                       \
     if (W == 0) hipLaunchKernelGGL(KER<double>, dim3(GRID), blk, 0, st, ba, ##__VA_ARGS__); \
@@ -525,8 +758,14 @@ ps_status launch_batch(int W, const BatchArgs& ba, const Plan2& P, hipStream_t s
   } while (0)
   PS_BLAUNCH(k_bchoose, nmat);
   PS_BLAUNCH(k_bpad, ntile);
-  for (int j = 2; j <= P.smax; ++j) PS_BLAUNCH(k_bpower, ntile, j);
-  PS_BLAUNCH(k_bassemble, ncol);
+  // powers: for each j, the products of the matrices with j < s, then those
+  // with j = s (Y) together with their block assembly (only for the block
+  // sizes some matrix can take)
+  for (int j = 2; j <= P.smax; ++j) {
+    if (j < P.smax) PS_BLAUNCH(k_bpower, ntile, j);
+    if (P.s_possible[j]) PS_BLAUNCH(k_bpower_asm, ntile, j);
+  }
+  if (P.s_possible[1]) PS_BLAUNCH(k_bassemble1, ntile);
   PS_BLAUNCH(k_bplan, nmat);
   for (int k = -1; k < P.kmax; ++k) PS_BLAUNCH(k_bhorner, ntile, k);
   for (int q = 1; q <= P.sigmax; ++q) PS_BLAUNCH(k_bsquare, ntile, q);

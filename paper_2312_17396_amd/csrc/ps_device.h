@@ -939,7 +939,7 @@ __device__ __forceinline__ void plan_matrix(const PlanArgs& a, const Layout& L, 
   const int64_t n = L.n;
   const double* colsum = (const double*)(ws + L.off_colsum);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t nch = (n + kRowChunk - 1) / kRowChunk;
+  const int64_t nch = (n + L.colsum_rows - 1) / L.colsum_rows;
   // each thread: running max over its columns of every block's column sum
   // (partial sums of the row chunks added in chunk order); the loads of
   // different blocks and chunks are independent, so their latencies overlap

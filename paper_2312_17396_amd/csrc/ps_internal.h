@@ -61,12 +61,14 @@ struct Layout {
   size_t off_P0, off_P1, off_R;
   size_t off_yf32, off_ybf16, off_yfp8, off_yfp8s;
   size_t off_colsum;   // (nB + 2) * nchunks * n doubles: partial column abs sums of B_i, Y and X
+  int colsum_rows;     // rows per partial column sum (nchunks = ceil(n / colsum_rows))
   size_t off_plan;
   size_t off_coef;     // double-double coefficients (hi[m+1], lo[m+1]); double-double path only
   size_t bytes;        // total per matrix
 };
 
-Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg, int npow_min = 0);
+Layout make_layout(ps_dtype dt, int64_t n, int m, int s, int sigma, int square_arg, int npow_min = 0,
+                   int colsum_rows = kRowChunk);
 
 }  // namespace psk
 
