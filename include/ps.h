@@ -390,6 +390,18 @@ ps_status ps_expm_batched(ps_dtype dtype, int batch, const int32_t* n,
                           const ps_opts* opts, int32_t* tiers_out,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* P_b = p(A_b) = sum_k coef[k] A_b^k for a batch of uneven orders (Algorithm
+ * 1 / Algorithm 3 with fixed s per matrix, as ps_eval): ps_expm_batched with
+ * every sigma = 0 and the caller's coefficients (coef required, host array of
+ * m+1).  Workspace: ps_workspace_size_batched.  Same launches, plans and
+ * errors as ps_expm_batched. */
+ps_status ps_eval_batched(ps_dtype dtype, int batch, const int32_t* n,
+                          const void* const* A, const int64_t* lda,
+                          const double* coef, int m, const int32_t* s,
+                          void* const* P, const int64_t* ldp,
+                          const ps_opts* opts, int32_t* tiers_out,
+                          void* ws, size_t ws_bytes, void* stream);
+
 /* Graph form of ps_expm_batched for repeated evaluation of the same batch
  * layout: ps_batched_prepare validates, uploads the work descriptors into the
  * workspace (synchronously) and captures the launch sequence into a
@@ -433,6 +445,28 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n,
                            void* gradA, int64_t ldga, int64_t strideGA,
                            int recompute, const ps_opts* opts,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoints of a batch of uneven orders: gradA_b = L_r(A_b^T, G_b) as
+ * ps_expm_backward for each matrix b (order n[b] <= 2^20, block size s[b],
+ * 0 = ceil(sqrt m); scaling sigma[b]; s and sigma may be NULL = 0 / auto).
+ * Host arrays of `batch` device pointers and leading dimensions.  Matrices
+ * that follow each other with the same order, block size, scaling and
+ * leading dimensions, and whose A, G and gradA pointers each advance by one
+ * constant stride, run as one strided batch of ps_expm_backward; every other
+ * matrix as a batch of one, in order on `stream`.  Workspace: the sum over
+ * the matrices of their single-matrix ps_workspace_size_backward, 256-byte
+ * rounded (ps_workspace_size_backward_batched).  Every matrix's arguments
+ * are checked before any device work; errors as ps_expm_backward. */
+ps_status ps_workspace_size_backward_batched(ps_dtype dtype, int batch, const int32_t* n, int m,
+                                             const int32_t* s, const int32_t* sigma, int recompute,
+                                             size_t* bytes);
+ps_status ps_expm_backward_batched(ps_dtype dtype, int batch, const int32_t* n,
+                                   const void* const* A, const int64_t* lda,
+                                   const void* const* G, const int64_t* ldg,
+                                   const double* coef, int m, const int32_t* s, const int32_t* sigma,
+                                   void* const* gradA, const int64_t* ldga,
+                                   int recompute, const ps_opts* opts,
+                                   void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Linear solve Q X = P (the quotient r_km = q_km^{-1} p_km of the Pade

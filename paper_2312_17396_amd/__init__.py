@@ -100,6 +100,16 @@ _SIGS = {
     "ps_expm_batched": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _dp, _i,
                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp),
                          _i64p, _op, ctypes.POINTER(ctypes.c_int32), _vp, _sz, _vp], _i),
+    "ps_eval_batched": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _dp, _i,
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _op,
+                         ctypes.POINTER(ctypes.c_int32), _vp, _sz, _vp], _i),
+    "ps_workspace_size_backward_batched": ([_i, _i, ctypes.POINTER(ctypes.c_int32), _i,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _i,
+                                            _szp], _i),
+    "ps_expm_backward_batched": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p,
+                                  ctypes.POINTER(_vp), _i64p, _dp, _i, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _i, _op, _vp, _sz,
+                                  _vp], _i),
     "ps_batched_prepare": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _dp, _i,
                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp),
                             _i64p, _op, _vp, _sz, _vp, ctypes.POINTER(_vp)], _i),
@@ -620,6 +630,69 @@ def ps_expm_batched(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask
             row = list(tiers[b * MAX_BLOCKS:(b + 1) * MAX_BLOCKS])
             reps.append({"s": row[-1], "tier": [t for t in row[:-1] if t >= 0]})
         return outs, reps
+    return outs
+
+
+def ps_eval_batched(mats, coef, s=None, mode="fixed", tier_mask=0, delta=10.0, report=False, outs=None,
+                    workspace=None, rule="blocks"):
+    """P_b = sum_k coef[k] A_b^k for a list of square matrices of uneven order
+    (1..256), one launch per phase for the whole batch (ps_eval_batched)."""
+    import torch
+    mats = [_check_square(a) for a in mats]
+    k = len(mats)
+    dt = _dtype_code(mats[0])
+    if any(_dtype_code(a) != dt for a in mats):
+        raise PSError("all matrices of a batch must share one dtype")
+    m = len(coef) - 1
+    n, sv, _ = _batch_arrays(mats, s, 0)
+    if workspace is None:
+        ws, wsp, wsb = _workspace(batched_workspace_bytes(mats, m, s), mats[0].device)
+    else:
+        ws, wsp, wsb = workspace
+    outs = [torch.empty_like(a) for a in mats] if outs is None else outs
+    aptr = (_vp * k)(*[a.data_ptr() for a in mats])
+    pptr = (_vp * k)(*[o.data_ptr() for o in outs])
+    lda = (ctypes.c_int64 * k)(*[a.shape[0] for a in mats])
+    o, _k = _opts(mode, tier_mask, delta, rule=rule)
+    tiers = (ctypes.c_int32 * (k * MAX_BLOCKS))() if report else None
+    _check(lib().ps_eval_batched(dt, k, n, aptr, lda, _darr(coef), m, sv, pptr, lda, ctypes.byref(o), tiers,
+                                 wsp, wsb, _stream_ptr(mats[0].device)))
+    if report:
+        reps = []
+        for b in range(k):
+            row = list(tiers[b * MAX_BLOCKS:(b + 1) * MAX_BLOCKS])
+            reps.append({"s": row[-1], "tier": [t for t in row[:-1] if t >= 0]})
+        return outs, reps
+    return outs
+
+
+def ps_expm_backward_batched(mats, grads, m, s=None, sigma=0, coef=None, recompute=False, mode="fixed",
+                             tier_mask=0, delta=10.0, rule="blocks", outs=None):
+    """gradA_b = d<G_b, r(A_b)>/dA_b for lists of square matrices of uneven order
+    (ps_expm_backward_batched); s and sigma: int or per-matrix lists."""
+    import torch
+    mats = [_check_square(a) for a in mats]
+    grads = [g.contiguous().to(a.dtype) for g, a in zip(grads, mats)]
+    k = len(mats)
+    if len(grads) != k or any(g.shape != a.shape for g, a in zip(grads, mats)):
+        raise PSError("one upstream gradient of the same shape per matrix")
+    dt = _dtype_code(mats[0])
+    if any(_dtype_code(a) != dt for a in mats):
+        raise PSError("all matrices of a batch must share one dtype")
+    n, sv, sgv = _batch_arrays(mats, 0 if s is None else s, sigma)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ps_workspace_size_backward_batched(dt, k, n, int(m), sv, sgv, int(bool(recompute)),
+                                                    ctypes.byref(nbytes)))
+    ws, wsp, wsb = _workspace(nbytes.value, mats[0].device)
+    outs = [torch.empty_like(a) for a in mats] if outs is None else outs
+    ld = (ctypes.c_int64 * k)(*[a.shape[0] for a in mats])
+    o, keep = _opts(mode, tier_mask, delta, rule=rule)
+    c = _darr(coef) if coef is not None else None
+    _check(lib().ps_expm_backward_batched(dt, k, n, (_vp * k)(*[a.data_ptr() for a in mats]), ld,
+                                          (_vp * k)(*[g.data_ptr() for g in grads]), ld, c, int(m), sv, sgv,
+                                          (_vp * k)(*[g.data_ptr() for g in outs]), ld, int(bool(recompute)),
+                                          ctypes.byref(o), wsp, wsb, _stream_ptr(mats[0].device)))
+    del keep
     return outs
 
 

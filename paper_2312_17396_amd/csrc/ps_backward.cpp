@@ -374,4 +374,112 @@ ps_status ps_expm_backward(ps_dtype dtype, int batch, int64_t n, const void* A, 
   return PS_OK;
 }
 
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// uneven batch of adjoints: matrix b has order n[b], block size s[b] and
+// scaling sigma[b].  Consecutive matrices with the same order, block size,
+// scaling and leading dimensions whose pointers advance by one constant
+// stride each (for A, G and gradA) form a run, evaluated as one strided
+// batch; every matrix owns the workspace slice of its single-matrix size.
+// ---------------------------------------------------------------------------
+namespace {
+ps_status backward_batch_sizes(ps_dtype dtype, int batch, const int32_t* n, int m, const int32_t* s,
+                               const int32_t* sigma, int recompute, std::vector<size_t>* each, size_t* total) {
+  if (batch < 1 || batch > (1 << 22)) return bad(PS_ERR_ARG, "batch out of range");
+  if (!n) return bad(PS_ERR_ARG, "n == NULL");
+  size_t t = 0;
+  for (int b = 0; b < batch; ++b) {
+    size_t one = 0;
+    if (ps_status e = ps_workspace_size_backward(dtype, 1, n[b], m, s ? s[b] : 0, sigma ? sigma[b] : 0, recompute,
+                                                 &one))
+      return e;
+    if (each) each->push_back(al256b(one));
+    t += al256b(one);
+  }
+  *total = t;
+  return PS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ps_status ps_workspace_size_backward_batched(ps_dtype dtype, int batch, const int32_t* n, int m, const int32_t* s,
+                                             const int32_t* sigma, int recompute, size_t* bytes) {
+  if (!bytes) return bad(PS_ERR_ARG, "bytes == NULL");
+  return backward_batch_sizes(dtype, batch, n, m, s, sigma, recompute, nullptr, bytes);
+}
+
+ps_status ps_expm_backward_batched(ps_dtype dtype, int batch, const int32_t* n, const void* const* A,
+                                   const int64_t* lda, const void* const* G, const int64_t* ldg, const double* coef,
+                                   int m, const int32_t* s, const int32_t* sigma, void* const* gradA,
+                                   const int64_t* ldga, int recompute, const ps_opts* opts, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  std::vector<size_t> each;
+  size_t total = 0;
+  if (ps_status e = backward_batch_sizes(dtype, batch, n, m, s, sigma, recompute, &each, &total)) return e;
+  if (!A || !lda || !G || !ldg || !gradA || !ldga) return bad(PS_ERR_ARG, "NULL array argument");
+  if (ws_bytes < total) return bad(PS_ERR_WORKSPACE, "workspace too small for ps_expm_backward_batched");
+  if (!ws || ((uintptr_t)ws & 255)) return bad(PS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+  if (opts && opts->check_finite) return bad(PS_ERR_UNSUPPORTED, "check_finite is not supported by ps_expm_backward");
+  const int es = dtype == PS_F64 ? 8 : 4;
+  auto ov = [](const void* a, size_t as, const void* b, size_t bs) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + bs && y < x + as;
+  };
+  // every matrix checked before any device work
+  for (int b = 0; b < batch; ++b) {
+    const int64_t nb = n[b];
+    if (!A[b] || !G[b] || !gradA[b]) return bad(PS_ERR_ARG, "NULL matrix pointer");
+    if (lda[b] < nb || ldg[b] < nb || ldga[b] < nb) return bad(PS_ERR_ARG, "leading dimension smaller than n");
+    const size_t so = (size_t)((nb - 1) * ldga[b] + nb) * es;
+    if (ov(gradA[b], so, A[b], (size_t)((nb - 1) * lda[b] + nb) * es) ||
+        ov(gradA[b], so, G[b], (size_t)((nb - 1) * ldg[b] + nb) * es))
+      return bad(PS_ERR_ALIAS, "gradA overlaps A or G");
+    if (ov(gradA[b], so, ws, total)) return bad(PS_ERR_ALIAS, "workspace overlaps gradA");
+  }
+  if (opts && opts->mode != PS_MODE_FIXED && opts->mode != PS_MODE_MIXED) return bad(PS_ERR_ARG, "opts.mode");
+  if (opts && opts->rule != PS_RULE_BLOCKS && opts->rule != PS_RULE_APRIORI) return bad(PS_ERR_ARG, "opts.rule");
+  char* wsc = (char*)ws;
+  size_t off = 0;
+  for (int b0 = 0; b0 < batch;) {
+    // extend the run b0 .. b1-1 while shapes match and the strides stay constant
+    auto same = [&](int x, int y) {
+      return n[x] == n[y] && (s ? s[x] : 0) == (s ? s[y] : 0) && (sigma ? sigma[x] : 0) == (sigma ? sigma[y] : 0) &&
+             lda[x] == lda[y] && ldg[x] == ldg[y] && ldga[x] == ldga[y];
+    };
+    const int64_t nb = n[b0];
+    int b1 = b0 + 1;
+    int64_t sA = 0, sG = 0, sO = 0;
+    if (b1 < batch && same(b0, b1)) {
+      sA = ((const char*)A[b1] - (const char*)A[b0]) / es;
+      sG = ((const char*)G[b1] - (const char*)G[b0]) / es;
+      sO = ((const char*)gradA[b1] - (const char*)gradA[b0]) / es;
+      const bool ok = sA >= (nb - 1) * lda[b0] + nb && sG >= (nb - 1) * ldg[b0] + nb &&
+                      sO >= (nb - 1) * ldga[b0] + nb &&
+                      (const char*)A[b0] + sA * es == (const char*)A[b1] &&
+                      (const char*)G[b0] + sG * es == (const char*)G[b1] &&
+                      (const char*)gradA[b0] + sO * es == (const char*)gradA[b1];
+      if (ok) {
+        b1 = b0 + 2;
+        while (b1 < batch && same(b0, b1) && (const char*)A[b1] == (const char*)A[b1 - 1] + sA * es &&
+               (const char*)G[b1] == (const char*)G[b1 - 1] + sG * es &&
+               (const char*)gradA[b1] == (const char*)gradA[b1 - 1] + sO * es)
+          ++b1;
+      }
+    }
+    const int cnt = b1 - b0;
+    const size_t bytes = each[b0] * (size_t)cnt;   // equal shapes: equal per-matrix sizes
+    if (ps_status e = ps_expm_backward(dtype, cnt, nb, A[b0], lda[b0], sA, G[b0], ldg[b0], sG, coef, m,
+                                       s ? s[b0] : 0, sigma ? sigma[b0] : 0, gradA[b0], ldga[b0], sO, recompute,
+                                       opts, wsc + off, bytes, stream))
+      return e;
+    off += bytes;
+    b0 = b1;
+  }
+  return PS_OK;
+}
+
 }  // extern "C"

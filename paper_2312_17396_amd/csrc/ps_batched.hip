@@ -842,6 +842,13 @@ ps_status ps_expm_batched(ps_dtype dtype, int batch, const int32_t* n, const voi
   return PS_OK;
 }
 
+ps_status ps_eval_batched(ps_dtype dtype, int batch, const int32_t* n, const void* const* A, const int64_t* lda,
+                          const double* coef, int m, const int32_t* s, void* const* P, const int64_t* ldp,
+                          const ps_opts* opts, int32_t* tiers_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!coef) return ps_set_error(bfail(PS_ERR_ARG, "coef == NULL"), g_batch_err.c_str());
+  return ps_expm_batched(dtype, batch, n, A, lda, coef, m, s, nullptr, P, ldp, opts, tiers_out, ws, ws_bytes, stream);
+}
+
 ps_status ps_batched_prepare(ps_dtype dtype, int batch, const int32_t* n, const void* const* A, const int64_t* lda,
                              const double* coef, int m, const int32_t* s, const int32_t* sigma, void* const* E,
                              const int64_t* lde, const ps_opts* opts, void* ws, size_t ws_bytes, void* stream,

@@ -230,3 +230,37 @@ def test_nonfinite_status_and_unsupported_paths(ps):
     st = L.ps_expm_dd(8, 0x10000000, 8, None, 6, 0, 0, 0x20000000, 8, ctypes.byref(o), None, 0x40000000, 1 << 30,
                       None)
     assert st == -5 and b"check_finite" in L.ps_last_error()
+
+
+def test_backward_batched_validation(ps):
+    L = ps.lib()
+    k = 2
+    n = (ctypes.c_int32 * k)(8, 16)
+    ld = (ctypes.c_int64 * k)(8, 16)
+    A = (ctypes.c_void_p * k)(0x10000000, 0x10100000)
+    G = (ctypes.c_void_p * k)(0x20000000, 0x20100000)
+    O = (ctypes.c_void_p * k)(0x30000000, 0x10100000)        # the second output is the second input
+    sz = ctypes.c_size_t()
+    assert L.ps_workspace_size_backward_batched(0, k, n, 18, None, None, 0, ctypes.byref(sz)) == 0
+    one = [ctypes.c_size_t(), ctypes.c_size_t()]
+    for b, nb in enumerate((8, 16)):
+        assert L.ps_workspace_size_backward(0, 1, nb, 18, 0, 0, 0, ctypes.byref(one[b])) == 0
+    assert sz.value == sum((x.value + 255) // 256 * 256 for x in one)
+    st = L.ps_expm_backward_batched(0, k, n, A, ld, G, ld, None, 18, None, None, O, ld, 0, None, 0x40000000,
+                                    sz.value, None)
+    assert st == -2, L.ps_last_error()
+    O2 = (ctypes.c_void_p * k)(0x30000000, 0x30100000)
+    assert L.ps_expm_backward_batched(0, k, n, A, ld, G, ld, None, 18, None, None, O2, ld, 0, None, 0x40000000,
+                                      16, None) == -3
+    bad = (ctypes.c_int64 * k)(8, 15)
+    assert L.ps_expm_backward_batched(0, k, n, A, bad, G, ld, None, 18, None, None, O2, ld, 0, None, 0x40000000,
+                                      sz.value, None) == -1
+
+
+def test_eval_batched_requires_coefficients(ps):
+    L = ps.lib()
+    n = (ctypes.c_int32 * 1)(4)
+    st = L.ps_eval_batched(0, 1, n, (ctypes.c_void_p * 1)(0x1000), (ctypes.c_int64 * 1)(4), None, 4, None,
+                           (ctypes.c_void_p * 1)(0x2000), (ctypes.c_int64 * 1)(4), None, None, 0x40000000, 1 << 30,
+                           None)
+    assert st == -1 and b"coef" in L.ps_last_error()
