@@ -10,17 +10,18 @@ resident in HBM.  `value` = evals/s of the mixed-precision path.
 Also reported:
   plain       the same workload with every product in FP64 (Algorithm 1)
   accuracy    relative 1-norm distance mixed vs plain (full matrices, GPU)
-  roofline    the dominant kernel, the FP64 MFMA GEMM tile kernel of the power
-              table (k_gemm_group: one launch per level of ceil(log2 j), one or
-              two n^3 products) and of the squarings (k_gemm): algorithmic
-              2 n^3 flops per product over the average time per product, from
-              hipEvent pairs around the power-table and squaring phases
-              (library profile mode, same stream), for K steps of the plain
-              evaluation run after the timed region (all its power products
-              are FP64; the mixed one may form Y = X^s by an FP32 product)
+  roofline    the dominant kernel, k_gemm<double>, the FP64 MFMA tile kernel of
+              the squarings (one n^3 product per launch): algorithmic 2 n^3
+              flops over its average launch duration, from hipEvent pairs around
+              the squaring phase (library profile mode, on the launch stream),
+              for K steps of the plain evaluation run right after the timed
+              region; roofline_power_levels gives the same per product for the
+              power-table launches (k_gemm_group, the same tile routine)
   cpu_baseline  the CPU oracle's plain FP64 Algorithm 1 + squarings
-              (OpenMP, all host cores) on one evaluation of each matrix, plus
-              the GPU result's error against the dd oracle on sampled columns
+              (OpenMP, all host cores, median of three runs, CPU model stated)
+              on one evaluation of each matrix, plus the GPU result's error
+              against the dd oracle on sampled columns; the batched extra's
+              accuracy gate is computed in this leg too
 """
 from __future__ import annotations
 
@@ -258,18 +259,26 @@ def main():
     # timed on the plain evaluation, whose power products are all FP64 (the
     # mixed one forms Y = X^s by an FP32 product when its plan allows)
     prof_mode = "fixed"
-    gemm_ms, gemm_n = 0.0, 0
+    sq_ms, sq_n, pw_ms, pw_n = 0.0, 0, 0.0, 0
     for _ in range(args.steps):
         for r, sg in zip(step(prof_mode, profile=True), sigmas):
-            gemm_ms += r["ms"]["power"] + r["ms"]["square"]
-            gemm_n += (S - 1) + sg
-    avg_ms = gemm_ms / max(gemm_n, 1)
-    achieved = 2.0 * N ** 3 / (avg_ms * 1e-3) / 1e12
-    roofline = {"kernel": "FP64 GEMM tile kernel (k_gemm_group power levels, k_gemm squarings; "
-                          "MFMA 16x16x4, 64x64 tiles)", "bound": "mfma",
+            pw_ms += r["ms"]["power"]
+            pw_n += S - 1
+            sq_ms += r["ms"]["square"]
+            sq_n += sg
+    sq_avg = sq_ms / max(sq_n, 1)            # ms per k_gemm launch (one product each)
+    achieved = 2.0 * N ** 3 / (sq_avg * 1e-3) / 1e12
+    roofline = {"kernel": "k_gemm<double> (the squarings: one n^3 FP64 product per launch; 64x64 tiles, "
+                          "MFMA 16x16x4)", "bound": "mfma",
                 "achieved": round(achieved, 2), "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_MFMA, 4), "avg_us_per_product": round(avg_ms * 1e3, 2),
-                "traffic": load_traffic()}
+                "frac": round(achieved / PEAK_FP64_MFMA, 4), "avg_us_per_launch": round(sq_avg * 1e3, 2),
+                "launches_timed": sq_n, "traffic": load_traffic()}
+    pw_avg = pw_ms / max(pw_n, 1)            # ms per product of the power-table levels
+    roofline_power = {"kernel": "k_gemm_group<double> (power table X^2..X^6: one launch per level of "
+                                "ceil(log2 j), one or two products; same tile routine)",
+                      "achieved": round(2.0 * N ** 3 / (pw_avg * 1e-3) / 1e12, 2), "peak": PEAK_FP64_MFMA,
+                      "unit": "TFLOP/s", "frac": round(2.0 * N ** 3 / (pw_avg * 1e-3) / 1e12 / PEAK_FP64_MFMA, 4),
+                      "avg_us_per_product": round(pw_avg * 1e3, 2)}
 
     main_mode = "mixed" if "mixed" in res else "plain"
     t_step = res[main_mode]
@@ -293,6 +302,7 @@ def main():
         "tiers": plans,
         "rel_diff_mixed_vs_plain": [float("%.3e" % e) for e in errs],
         "roofline": roofline,
+        "roofline_power_levels": roofline_power,
         "step_roofline": {mode: {"ideal_ms": round(ideal[mode] * 1e3, 4), "measured_ms": round(res[mode] * 1e3, 4),
                                  "frac": round(ideal[mode] / res[mode], 4),
                                  "mfma_only_frac": round(mfma_only[mode] / res[mode], 4)} for mode in res},
@@ -323,6 +333,16 @@ def main():
         worst = max(out["cpu_baseline"]["gpu_mixed_rel_err_vs_dd_oracle_sampled_cols"])
         out["accuracy_gate"] = {"tol": 1e-13, "max_rel_err_vs_dd_oracle": worst, "ok": worst <= 1e-13,
                                 "note": "mixed results, sampled columns, 1-norm relative error"}
+        bx = out.get("extra", {}).get("batched_uneven_4096")
+        if bx is not None and "_gate_samples" in bx:
+            bx["accuracy_gate"] = batched_gate(bx.pop("_gate_samples"))
+            if not bx["accuracy_gate"]["ok"]:
+                bx.pop("speedup_graph_vs_loop", None)
+                bx.pop("speedup_mixed_vs_fixed", None)
+    bx = out.get("extra", {}).get("batched_uneven_4096")
+    if bx is not None and "_gate_samples" in bx:
+        bx.pop("_gate_samples")
+        bx["accuracy_gate"] = {"ok": None, "note": "not computed: the oracle leg was skipped (--no-cpu-baseline)"}
     print(json.dumps(out))
 
 
@@ -347,7 +367,9 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
               GEMM tile kernel's TFLOP/s (library profile mode, hipEvents);
     batched   4096 matrices, n uniform in {8..256}, ||A||_1 ~ U[0.05, 4], Taylor
               m = 18, s chosen per matrix, FP32: the per-phase launches of the whole
-              batch replayed from one hipGraph vs a loop of single-matrix calls;
+              batch replayed from one hipGraph (one branch, then the size-class
+              schedule chosen by ps_batched_tune), each size class alone, and a
+              loop of single-matrix calls; accuracy gate in the oracle leg;
     pade_cos  n = 2048 FP64, A = Q diag(lambda) Q^T: Pade [13/13] p and q from one
               power table (s = 4), exp as q^-1 p (the LU solve on the device;
               its time is the difference to the pair), and Taylor cos of degree
@@ -406,14 +428,39 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
         mats, ts = inputs.batch_uneven()
         sig = [inputs.squarings_for(t) for t in ts]
         A = [torch.tensor(a, dtype=torch.float32, device=dev) for a in mats]
-        flops = sum(2.0 * a.shape[0] ** 3 * (3 + 4 + sg) for a, sg in zip(mats, sig))   # s=4/5: 7 GEMMs + squarings
+        gemms = lambda n, sg: 2.0 * n ** 3 * (3 + 4 + sg)   # s = 4/5: 7 products + squarings
+        flops = sum(gemms(a.shape[0], sg) for a, sg in zip(mats, sig))
         out = {"matrices": len(A), "m": 18, "dtype": "f32"}
+        ps.autotune_clear()
         for mode in ("fixed", "mixed"):
             g = ps.BatchedGraph(A, 18, sigma=sig, mode=mode)
             t = _time(g.launch, 5, torch)
             g.close()
-            out[mode] = {"ms": round(t * 1e3, 3), "evals_per_s": round(len(A) / t, 1),
-                         "tflops_credited": round(flops / t / 1e12, 2)}
+            tune = ps.batched_tune(A, 18, sigma=sig, mode=mode, reps=3)
+            g = ps.BatchedGraph(A, 18, sigma=sig, mode=mode)      # the tuned schedule, from the cache
+            tt = _time(g.launch, 5, torch)
+            g.close()
+            out[mode] = {"ms": round(tt * 1e3, 3), "evals_per_s": round(len(A) / tt, 1),
+                         "tflops_credited": round(flops / tt / 1e12, 2),
+                         "frac_fp32_mfma_credited": round(flops / tt / 157.3e12, 4),
+                         "one_branch_ms": round(t * 1e3, 3),
+                         "tuned_schedule": {"branch_of_class": tune["groups"], "candidate_ms": tune["ms"]}}
+        out["speedup_mixed_vs_fixed"] = round(out["fixed"]["ms"] / out["mixed"]["ms"], 3)
+        # per size class (padded order 64 k): the class alone as a batch, mixed
+        classes = {}
+        for i, a in enumerate(mats):
+            classes.setdefault(64 * ((a.shape[0] + 63) // 64), []).append(i)
+        per = {}
+        for npad in sorted(classes):
+            idx = classes[npad]
+            g = ps.BatchedGraph([A[i] for i in idx], 18, sigma=[sig[i] for i in idx], mode="mixed")
+            tc = _time(g.launch, 5, torch)
+            g.close()
+            fc = sum(gemms(mats[i].shape[0], sig[i]) for i in idx)
+            per["n<=%d" % npad] = {"matrices": len(idx), "ms": round(tc * 1e3, 3),
+                                   "tflops_credited": round(fc / tc / 1e12, 2),
+                                   "frac_fp32_mfma_credited": round(fc / tc / 157.3e12, 4)}
+        out["per_class_mixed"] = per
         sub = list(range(0, len(A), 8))          # per-matrix loop on every 8th matrix, scaled
         wsl = [ps.expm_workspace(A[i], 18, 0, sig[i]) for i in sub]
         outs = [torch.empty_like(A[i]) for i in sub]
@@ -425,8 +472,20 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
         out["per_matrix_loop_mixed"] = {"ms": round(t * 1e3, 2), "evals_per_s": round(len(A) / t, 1),
                                         "note": "loop of ps_expm calls timed on every 8th matrix, scaled"}
         out["speedup_graph_vs_loop"] = round(t / (out["mixed"]["ms"] * 1e-3), 2)
+        # results kept for the accuracy gate (computed in the oracle leg):
+        # every 128th matrix, mixed and plain, two columns each
+        gs = []
+        Ef = ps.ps_expm_batched(A, 18, sigma=sig, mode="fixed")
+        Em = ps.ps_expm_batched(A, 18, sigma=sig, mode="mixed")
+        for i in range(0, len(A), 128):
+            n = A[i].shape[0]
+            cols = [0, n // 2]
+            gs.append((mats[i], sig[i], cols, Em[i][:, cols].double().cpu().numpy(),
+                       Ef[i][:, cols].double().cpu().numpy()))
+        out["_gate_samples"] = gs
+        ps.autotune_clear()
         res["batched_uneven_4096"] = out
-        del A, outs, wsl
+        del A, outs, wsl, Ef, Em
     # ---- Pade pair and cos at n = 2048
     if "pade_cos" in which:
         Aq = torch.tensor(inputs.orthosim_2048(), dtype=torch.float64, device=dev)
@@ -534,6 +593,28 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
     return res
 
 
+def batched_gate(samples):
+    """Accuracy gate of the uneven FP32 batch (part of the oracle leg): on the
+    sampled matrices and columns, the mixed results within max(1e-6, 2 err_plain)
+    of the oracle (the equal-accuracy rule of the FP32 target)."""
+    import numpy as np
+
+    import oracle
+    from oracle import coeffs
+    c32 = [float(np.float32(x)) for x in coeffs.taylor_exp(18)]
+    worst, ok = 0.0, True
+    for A, sg, cols, em, ef in samples:
+        A = A.astype(np.float32).astype(np.float64)
+        wh, wl = oracle.expm_apply_dd(A, c32, sg, np.eye(A.shape[0])[:, cols])
+        err = lambda e: float(np.max(np.sum(np.abs((e - wh) - wl), 0)) / np.max(np.sum(np.abs(wh), 0)))
+        e_m, e_f = err(em), err(ef)
+        worst = max(worst, e_m)
+        ok = ok and e_m <= max(1e-6, 2 * e_f)
+    return {"rule": "err_mixed <= max(1e-6, 2 err_plain) per matrix", "matrices": len(samples),
+            "max_rel_err_mixed": float("%.3e" % worst), "ok": ok,
+            "note": "every 128th matrix, two columns each, against the oracle's dd evaluation"}
+
+
 def cpu_baseline(mats, outs_mixed, norms, sigmas):
     """The oracle's plain FP64 Algorithm 1 + squarings on the host cores (one
     evaluation of each matrix), and the GPU result against the dd oracle on
@@ -547,10 +628,13 @@ def cpu_baseline(mats, outs_mixed, norms, sigmas):
     oracle.set_threads(threads)
     c = coeffs.taylor_exp(M)
     A_np = [a.cpu().numpy() for a in mats]
-    t0 = time.perf_counter()
-    for A, sg in zip(A_np, sigmas):
-        oracle.expm_ps_f64(A, c, S, sg)
-    dt = time.perf_counter() - t0
+    runs = []
+    for _ in range(3):                       # median of three runs
+        t0 = time.perf_counter()
+        for A, sg in zip(A_np, sigmas):
+            oracle.expm_ps_f64(A, c, S, sg)
+        runs.append(time.perf_counter() - t0)
+    dt = sorted(runs)[1]
     errs = []
     for A, sg, e in zip(A_np, sigmas, outs_mixed):
         cols = [0, N // 2 + 1]
@@ -565,9 +649,18 @@ def cpu_baseline(mats, outs_mixed, norms, sigmas):
     oracle.expm_ps_f64(A_np[1], c, S, sigmas[1])
     d1 = time.perf_counter() - t1
     oracle.set_threads(threads)
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(len(A_np) / dt, 4), "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu,
             "sample": "one evaluation of each of the 4 dense n=1024 matrices by the oracle's FP64 "
-                      "Algorithm 1 + squarings (%.1f s)" % dt,
+                      "Algorithm 1 + squarings; median of 3 runs (%s s)" % ", ".join("%.2f" % r for r in runs),
             "single_core": {"value": round(1.0 / d1, 4), "unit": "evals/s",
                             "sample": "the ||A||_1 = 1 matrix (sigma = 0) once on one thread (%.1f s)" % d1},
             "gpu_mixed_rel_err_vs_dd_oracle_sampled_cols": [float("%.3e" % e) for e in errs]}

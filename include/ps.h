@@ -418,6 +418,48 @@ ps_status ps_batched_launch(ps_batched_handle h, void* stream);
 ps_status ps_batched_destroy(ps_batched_handle h);
 
 /* ---------------------------------------------------------------------------
+ * Autotuning of the uneven batch's size-class schedule (the batching
+ * pattern's tuner).  A matrix's size class is its padded order / 64 (1..4 for
+ * orders up to 256).  A schedule assigns each class to one of up to four
+ * branches; each branch is a launch sequence of its own over its matrices'
+ * tiles, and the branches run concurrently (forked from the caller's stream
+ * and joined back by events; graph edges under capture).  A schedule changes
+ * which launch processes a tile, never a tile's arithmetic: every schedule
+ * gives the same bits.
+ *   ps_batched_tune: times every contiguous grouping of the batch's classes
+ *     (in increasing order) into at most four branches on this batch (one
+ *     captured graph per candidate, one warm-up replay, median of `reps`
+ *     replays timed with events on `stream`, which the call synchronises),
+ *     keeps the fastest in the process-wide cache under a key of device
+ *     architecture, dtype, degree m and the order of magnitude of each
+ *     class's matrix count, and returns it: groups_out[c-1] = branch of
+ *     class c (host array of 4; may be NULL), ms_out[k] = candidate k's
+ *     median (host array of 8; may be NULL), *ncand_out = candidates (may be
+ *     NULL).  Arguments and workspace as ps_batched_prepare.  ps_expm_batched,
+ *     ps_eval_batched and ps_batched_prepare use the cached schedule of a
+ *     matching key, otherwise one branch.
+ *   ps_autotune_lookup: the schedule the cache holds for such a batch
+ *     (*found = 0: none; groups_out then the one-branch default).
+ *   ps_autotune_save / ps_autotune_load: the cache as a JSON file
+ *     ({"ps_autotune": 1, "entries": [{"key": ..., "groups": [g1,g2,g3,g4]}]});
+ *     load adds the file's entries to the cache (PS_ERR_ARG for a file that is
+ *     missing or not such a cache).  ps_autotune_clear empties the cache.
+ * The cache is guarded by a mutex; multi-branch batches are queued (or
+ * captured) under a second mutex, since their side streams are a per-device
+ * pool created on first use and kept until the process ends.
+ * ------------------------------------------------------------------------- */
+ps_status ps_batched_tune(ps_dtype dtype, int batch, const int32_t* n,
+                          const void* const* A, const int64_t* lda,
+                          const double* coef, int m, const int32_t* s, const int32_t* sigma,
+                          void* const* E, const int64_t* lde, const ps_opts* opts,
+                          void* ws, size_t ws_bytes, void* stream, int reps,
+                          int32_t* groups_out, float* ms_out, int* ncand_out);
+ps_status ps_autotune_lookup(ps_dtype dtype, int batch, const int32_t* n, int m, int32_t* groups_out, int* found);
+ps_status ps_autotune_save(const char* path);
+ps_status ps_autotune_load(const char* path);
+ps_status ps_autotune_clear(void);
+
+/* ---------------------------------------------------------------------------
  * Adjoint.  gradA = d<G, r(A)>/dA for r(A) = p(2^-sigma A)^(2^sigma), i.e. the
  * Frechet derivative L_r(A^T, G), by reverse-mode differentiation of the
  * squarings, the Horner recurrence, the block assembly and the power table.

@@ -110,6 +110,14 @@ _SIGS = {
                                   ctypes.POINTER(_vp), _i64p, _dp, _i, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _i, _op, _vp, _sz,
                                   _vp], _i),
+    "ps_batched_tune": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _dp, _i,
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp),
+                         _i64p, _op, _vp, _sz, _vp, _i, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_float), _ip], _i),
+    "ps_autotune_lookup": ([_i, _i, ctypes.POINTER(ctypes.c_int32), _i, ctypes.POINTER(ctypes.c_int32), _ip], _i),
+    "ps_autotune_save": ([ctypes.c_char_p], _i),
+    "ps_autotune_load": ([ctypes.c_char_p], _i),
+    "ps_autotune_clear": ([], _i),
     "ps_batched_prepare": ([_i, _i, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp), _i64p, _dp, _i,
                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_vp),
                             _i64p, _op, _vp, _sz, _vp, ctypes.POINTER(_vp)], _i),
@@ -694,6 +702,52 @@ def ps_expm_backward_batched(mats, grads, m, s=None, sigma=0, coef=None, recompu
                                           ctypes.byref(o), wsp, wsb, _stream_ptr(mats[0].device)))
     del keep
     return outs
+
+
+def batched_tune(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, rule="blocks",
+                 reps=3):
+    """Time the size-class schedules of this batch (ps_batched_tune) and keep
+    the fastest in the library's cache; returns {"groups": [...4], "ms": [...]}."""
+    import torch
+    mats = [_check_square(a) for a in mats]
+    k = len(mats)
+    dt = _dtype_code(mats[0])
+    n, sv, sgv = _batch_arrays(mats, s, sigma)
+    ws, wsp, wsb = _workspace(batched_workspace_bytes(mats, m, s), mats[0].device)
+    outs = [torch.empty_like(a) for a in mats]
+    aptr = (_vp * k)(*[a.data_ptr() for a in mats])
+    eptr = (_vp * k)(*[o.data_ptr() for o in outs])
+    lda = (ctypes.c_int64 * k)(*[a.shape[0] for a in mats])
+    o, _k = _opts(mode, tier_mask, delta, rule=rule)
+    c = _darr(coef) if coef is not None else None
+    groups = (ctypes.c_int32 * 4)()
+    ms = (ctypes.c_float * 8)()
+    ncand = ctypes.c_int()
+    _check(lib().ps_batched_tune(dt, k, n, aptr, lda, c, int(m), sv, sgv, eptr, lda, ctypes.byref(o), wsp, wsb,
+                                 _stream_ptr(mats[0].device), int(reps), groups, ms, ctypes.byref(ncand)))
+    return {"groups": list(groups), "ms": [round(ms[i], 4) for i in range(min(ncand.value, 8))]}
+
+
+def autotune_lookup(mats, m):
+    """(found, groups) of the cached size-class schedule for such a batch."""
+    k = len(mats)
+    n = (ctypes.c_int32 * k)(*[int(a.shape[0]) for a in mats])
+    groups = (ctypes.c_int32 * 4)()
+    found = ctypes.c_int()
+    _check(lib().ps_autotune_lookup(_dtype_code(mats[0]), k, n, int(m), groups, ctypes.byref(found)))
+    return bool(found.value), list(groups)
+
+
+def autotune_save(path):
+    _check(lib().ps_autotune_save(str(path).encode()))
+
+
+def autotune_load(path):
+    _check(lib().ps_autotune_load(str(path).encode()))
+
+
+def autotune_clear():
+    _check(lib().ps_autotune_clear())
 
 
 class BatchedGraph:

@@ -20,6 +20,20 @@
 // ps_batched_prepare captures into one hipGraph; the plan and the block-size
 // choice are made on the device, so nothing returns to the host in between.
 //
+// Size classes and branches: a matrix's class is its padded order / 64.  A
+// schedule assigns each class to a branch; every branch is a launch sequence
+// of its own over its matrices' tasks, and the branches run concurrently
+// (forked from the caller's stream by events and joined at the end), so the
+// latency-bound phases of one class overlap the products of another.  The
+// schedule changes only which launch processes a tile, never a tile's
+// arithmetic, so every schedule gives the same bits.  ps_batched_tune times
+// the candidate schedules (the groupings of the classes, in order of order,
+// into up to four branches) on the caller's batch and keeps the fastest in a
+// process-wide cache keyed by device architecture, dtype, degree and the
+// batch's classes; ps_expm_batched and ps_batched_prepare use a cached
+// schedule when one matches (otherwise one branch), and ps_autotune_save /
+// ps_autotune_load keep the cache in a JSON file.
+//
 // The block size is chosen per matrix among floor(sqrt m) and ceil(sqrt m)
 // (the two equally cheap choices of the paper's section 1) by the modelled
 // cost sum over products of 1 / rate(tier) under an a-priori plan from
@@ -33,6 +47,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -68,7 +84,8 @@ struct BatchRes {
 struct BatchArgs {
   const BatchItem* items;
   BatchRes* res;
-  const int* tile_tasks;  // (matrix << 8) | tile, largest matrices first
+  const int* tile_tasks;  // (matrix << 8) | tile, largest matrices first (this branch's)
+  const int* mat_tasks;   // matrices of this branch (per-matrix kernels)
   int* pick;              // per matrix: 0 -> L[0], 1 -> L[1]
   int* chosen;            // per matrix: chosen block size (for reports)
   int batch;
@@ -115,7 +132,7 @@ template <typename W>
 __global__ __launch_bounds__(NT) void k_bchoose(BatchArgs a) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   __shared__ double red[NW + 1];
-  const int b = blockIdx.x;
+  const int b = a.mat_tasks[blockIdx.x];
   const BatchItem& it = a.items[b];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   int pick = 1;
@@ -494,7 +511,7 @@ __global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
   __shared__ double red[8 * NW];
   __shared__ double norms[PS_MAX_BLOCKS + 2];
-  const int b = blockIdx.x;
+  const int b = a.mat_tasks[blockIdx.x];
   const BatchRes& it = a.res[b];
   const Layout& L = it.L;
   PlanArgs pa;
@@ -613,12 +630,28 @@ ps_status bfail(ps_status st, const char* fmt, ...) {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int kMaxClass = 4;     // padded orders 64, 128, 192, 256
+constexpr int kMaxBranch = 4;
+
+// one branch of a batch: its matrices, their tiles and the bounds of its
+// launch loops
+struct Branch {
+  std::vector<int> mats, tiles;
+  int smax = 1, kmax = 0, sigmax = 0;
+  std::vector<char> s_possible;   // s_possible[s]: some matrix of the branch may take block size s
+  size_t off_mats = 0, off_tiles = 0;
+};
+
 struct Plan2 {
   std::vector<BatchItem> items;
-  std::vector<int> tile_tasks;
-  int smax = 1, kmax = 0, sigmax = 0;
-  std::vector<char> s_possible;   // s_possible[s]: some matrix may take block size s
-  size_t off_items, off_res, off_tiles, off_pick, off_chosen, total;
+  std::vector<Branch> br;
+  int cls_count[kMaxClass + 1] = {0, 0, 0, 0, 0};   // matrices per class (index = padded order / 64)
+  size_t off_items, off_res, off_pick, off_chosen, total;
+};
+
+// schedule: group[c - 1] = branch of class c (c = 1..kMaxClass)
+struct Schedule {
+  int group[kMaxClass] = {0, 0, 0, 0};
 };
 
 int s_floor(int m) {
@@ -635,14 +668,17 @@ int s_ceil(int m) {
 
 ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int32_t* s, const int32_t* sigma,
                      const void* const* A, const int64_t* lda, void* const* E, const int64_t* lde, Plan2& P,
-                     bool need_ptrs) {
+                     bool need_ptrs, const Schedule& sch) {
   if (dt != PS_F64 && dt != PS_F32) return bfail(PS_ERR_ARG, "dtype must be PS_F64 or PS_F32");
   if (batch < 1 || batch > (1 << 22)) return bfail(PS_ERR_ARG, "batch = %d out of range", batch);
   if (!n) return bfail(PS_ERR_ARG, "n == NULL");
   if (m < 0 || m > kMaxDegree) return bfail(PS_ERR_ARG, "degree m = %d out of range", m);
   const int esize = dt == PS_F64 ? 8 : 4;
   P.items.resize(batch);
-  P.s_possible.assign(2, 0);
+  int nbr = 1;
+  for (int c = 0; c < kMaxClass; ++c) nbr = std::max(nbr, sch.group[c] + 1);
+  P.br.assign(nbr, Branch());
+  for (Branch& B : P.br) B.s_possible.assign(2, 0);
   std::vector<double> cost(batch);
   size_t off = 0;
   for (int b = 0; b < batch; ++b) {
@@ -679,29 +715,85 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
     }
     const int gem = (std::max(s0, s1) - 1) + (m / s0) + sg;
     cost[b] = (double)nb * nb * nb * gem;
-    P.smax = std::max(P.smax, std::max(s0, s1));
-    if ((int)P.s_possible.size() <= std::max(s0, s1)) P.s_possible.resize(std::max(s0, s1) + 1, 0);
-    P.s_possible[s0] = P.s_possible[s1] = 1;
-    P.kmax = std::max(P.kmax, std::max(it.L[0].first_step, it.L[1].first_step));
-    P.sigmax = std::max(P.sigmax, sg);
+    const int cls = (int)(np / kTileM);
+    P.cls_count[cls] += 1;
+    Branch& B = P.br[sch.group[cls - 1]];
+    B.mats.push_back(b);
+    B.smax = std::max(B.smax, std::max(s0, s1));
+    if ((int)B.s_possible.size() <= std::max(s0, s1)) B.s_possible.resize(std::max(s0, s1) + 1, 0);
+    B.s_possible[s0] = B.s_possible[s1] = 1;
+    B.kmax = std::max(B.kmax, std::max(it.L[0].first_step, it.L[1].first_step));
+    B.sigmax = std::max(B.sigmax, sg);
   }
-  // task tables, largest matrices first so the long tiles start early
-  std::vector<int> order(batch);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-  P.tile_tasks.clear();
-  for (int b : order) {
-    const int64_t nb = n[b];
-    const int nt = (int)(((nb + kTileM - 1) / kTileM) * ((nb + kTileN - 1) / kTileN));   // tiles of the padded square
-    for (int t = 0; t < nt; ++t) P.tile_tasks.push_back((b << 8) | t);
-  }
+  // per branch: matrices and their tiles, largest matrices first so the long
+  // tiles start early
   P.off_items = al256(off);
   P.off_res = al256(P.off_items + sizeof(BatchItem) * (size_t)batch);
-  P.off_tiles = al256(P.off_res + sizeof(BatchRes) * (size_t)batch);
-  P.off_pick = al256(P.off_tiles + sizeof(int) * P.tile_tasks.size());
+  const size_t tasks0 = al256(P.off_res + sizeof(BatchRes) * (size_t)batch);
+  size_t o = tasks0;
+  size_t ntiles = 0;
+  for (Branch& B : P.br) {
+    std::stable_sort(B.mats.begin(), B.mats.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    for (int b : B.mats) {
+      const int64_t nb = n[b];
+      const int nt = (int)(((nb + kTileM - 1) / kTileM) * ((nb + kTileN - 1) / kTileN));   // tiles of the padded square
+      for (int t = 0; t < nt; ++t) B.tiles.push_back((b << 8) | t);
+    }
+    B.off_mats = o;
+    o = al256(o + sizeof(int) * B.mats.size());
+    B.off_tiles = o;
+    o = al256(o + sizeof(int) * B.tiles.size());
+    ntiles += B.tiles.size();
+  }
+  // the task arrays get a region sized for any schedule (every branch's two
+  // arrays 256-byte rounded), so one workspace size covers all schedules
+  P.off_pick = al256(tasks0 + sizeof(int) * ((size_t)batch + ntiles) + (size_t)(2 * 256 * kMaxBranch));
+  if (o > P.off_pick) return bfail(PS_ERR_UNSUPPORTED, "task arrays exceed their region");
   P.off_chosen = al256(P.off_pick + sizeof(int) * (size_t)batch);
   P.total = al256(P.off_chosen + sizeof(int) * (size_t)batch);
   return PS_OK;
+}
+
+// ---- the schedule cache (process-wide) ----
+std::mutex g_cache_mu;
+std::map<std::string, Schedule> g_cache;
+
+// key of a batch: device architecture, dtype, degree and, per class, the
+// order of magnitude of its matrix count (0 = absent, k = [2^(k-1), 2^k))
+std::string schedule_key(ps_dtype dt, int m, const int cls_count[kMaxClass + 1]) {
+  std::string arch = "unknown";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  char buf[160];
+  int mag[kMaxClass];
+  for (int c = 1; c <= kMaxClass; ++c) {
+    int k = 0;
+    while (k < 30 && (cls_count[c] >> k) > 0) ++k;
+    mag[c - 1] = k;
+  }
+  snprintf(buf, sizeof buf, "%s|%s|m%d|%d,%d,%d,%d", arch.c_str(), dt == PS_F64 ? "f64" : "f32", m, mag[0], mag[1],
+           mag[2], mag[3]);
+  return buf;
+}
+
+void count_classes(int batch, const int32_t* n, int cls_count[kMaxClass + 1]) {
+  for (int c = 0; c <= kMaxClass; ++c) cls_count[c] = 0;
+  for (int b = 0; b < batch; ++b)
+    if (n[b] >= 1 && n[b] <= 256) cls_count[(n[b] + kTileM - 1) / kTileM] += 1;
+}
+
+Schedule cached_schedule(ps_dtype dt, int m, int batch, const int32_t* n) {
+  int cc[kMaxClass + 1];
+  count_classes(batch, n, cc);
+  const std::string key = schedule_key(dt, m, cc);
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto it = g_cache.find(key);
+  return it == g_cache.end() ? Schedule() : it->second;
 }
 
 ps_status fill_args(ps_dtype dt, const double* coef, int m, const ps_opts* opts, BatchArgs& ba) {
@@ -732,14 +824,18 @@ ps_status fill_args(ps_dtype dt, const double* coef, int m, const ps_opts* opts,
 ps_status upload_and_args(const Plan2& P, char* ws, hipStream_t st, BatchArgs& ba) {
   hipError_t e = hipMemcpyAsync(ws + P.off_items, P.items.data(), sizeof(BatchItem) * P.items.size(),
                                 hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ws + P.off_tiles, P.tile_tasks.data(), sizeof(int) * P.tile_tasks.size(),
-                       hipMemcpyHostToDevice, st);
+  for (const Branch& B : P.br) {
+    if (e == hipSuccess && !B.mats.empty())
+      e = hipMemcpyAsync(ws + B.off_mats, B.mats.data(), sizeof(int) * B.mats.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !B.tiles.empty())
+      e = hipMemcpyAsync(ws + B.off_tiles, B.tiles.data(), sizeof(int) * B.tiles.size(), hipMemcpyHostToDevice, st);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors are released on return
   if (e != hipSuccess) return bfail(PS_ERR_HIP, "descriptor upload: %s", hipGetErrorString(e));
   ba.items = (const BatchItem*)(ws + P.off_items);
   ba.res = (BatchRes*)(ws + P.off_res);
-  ba.tile_tasks = (const int*)(ws + P.off_tiles);
+  ba.tile_tasks = nullptr;   // set per branch
+  ba.mat_tasks = nullptr;
   ba.pick = (int*)(ws + P.off_pick);
   ba.chosen = (int*)(ws + P.off_chosen);
   ba.batch = (int)P.items.size();
@@ -747,10 +843,13 @@ ps_status upload_and_args(const Plan2& P, char* ws, hipStream_t st, BatchArgs& b
   return PS_OK;
 }
 
-// the fixed launch sequence of a batch (stream-ordered; captured by ps_batched_prepare)
-ps_status launch_batch(int W, const BatchArgs& ba, const Plan2& P, hipStream_t st) {
+// the fixed launch sequence of one branch (stream-ordered)
+ps_status launch_branch(int W, BatchArgs ba, const Branch& B, hipStream_t st) {
+  if (B.mats.empty()) return PS_OK;
+  ba.tile_tasks = (const int*)(ba.ws + B.off_tiles);
+  ba.mat_tasks = (const int*)(ba.ws + B.off_mats);
   const dim3 blk(NT);
-  const unsigned nmat = (unsigned)ba.batch, ntile = (unsigned)P.tile_tasks.size();
+  const unsigned nmat = (unsigned)B.mats.size(), ntile = (unsigned)B.tiles.size();
 #define PS_BLAUNCH(KER, GRID, ...)                                                          \
   do {                                                                                       \
     if (W == 0) hipLaunchKernelGGL(KER<double>, dim3(GRID), blk, 0, st, ba, ##__VA_ARGS__); \
@@ -761,17 +860,86 @@ ps_status launch_batch(int W, const BatchArgs& ba, const Plan2& P, hipStream_t s
   // powers: for each j, the products of the matrices with j < s, then those
   // with j = s (Y) together with their block assembly (only for the block
   // sizes some matrix can take)
-  for (int j = 2; j <= P.smax; ++j) {
-    if (j < P.smax) PS_BLAUNCH(k_bpower, ntile, j);
-    if (P.s_possible[j]) PS_BLAUNCH(k_bpower_asm, ntile, j);
+  for (int j = 2; j <= B.smax; ++j) {
+    if (j < B.smax) PS_BLAUNCH(k_bpower, ntile, j);
+    if (B.s_possible[j]) PS_BLAUNCH(k_bpower_asm, ntile, j);
   }
-  if (P.s_possible[1]) PS_BLAUNCH(k_bassemble1, ntile);
+  if (B.s_possible[1]) PS_BLAUNCH(k_bassemble1, ntile);
   PS_BLAUNCH(k_bplan, nmat);
-  for (int k = -1; k < P.kmax; ++k) PS_BLAUNCH(k_bhorner, ntile, k);
-  for (int q = 1; q <= P.sigmax; ++q) PS_BLAUNCH(k_bsquare, ntile, q);
+  for (int k = -1; k < B.kmax; ++k) PS_BLAUNCH(k_bhorner, ntile, k);
+  for (int q = 1; q <= B.sigmax; ++q) PS_BLAUNCH(k_bsquare, ntile, q);
 #undef PS_BLAUNCH
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return bfail(PS_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+  return PS_OK;
+}
+
+// Side streams of the branches: a pool per device, created on first use and
+// kept for the life of the process (a stream destroyed with work in flight
+// may drop it).  g_branch_mu is held while a multi-branch batch is queued or
+// captured, so no other call puts work on a side stream meanwhile.
+std::mutex g_branch_mu;
+constexpr int kMaxDev = 64;
+hipStream_t g_side[kMaxDev][kMaxBranch];
+
+ps_status side_streams(hipStream_t* out, int count) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return bfail(PS_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDev) return bfail(PS_ERR_UNSUPPORTED, "device index %d", dev);
+  for (int k = 0; k < count; ++k) {
+    if (!g_side[dev][k]) {
+      e = hipStreamCreateWithFlags(&g_side[dev][k], hipStreamNonBlocking);
+      if (e != hipSuccess) return bfail(PS_ERR_HIP, "side stream: %s", hipGetErrorString(e));
+    }
+    out[k] = g_side[dev][k];
+  }
+  return PS_OK;
+}
+
+int used_branches(const Plan2& P) {
+  int used = 0;
+  for (const Branch& B : P.br) used += B.mats.empty() ? 0 : 1;
+  return used;
+}
+
+// every branch of a batch: the first on `st`, the others on side streams
+// forked from it by an event and joined back by one event each (under
+// capture the fork and the joins become graph edges).  The caller holds
+// g_branch_mu when more than one branch is used.
+ps_status launch_batch(int W, const BatchArgs& ba, const Plan2& P, hipStream_t st) {
+  if (used_branches(P) <= 1) {
+    for (const Branch& B : P.br)
+      if (ps_status r = launch_branch(W, ba, B, st)) return r;
+    return PS_OK;
+  }
+  hipStream_t side[kMaxBranch] = {};
+  if (ps_status r = side_streams(side, kMaxBranch - 1)) return r;
+  hipEvent_t fork = nullptr, join[kMaxBranch] = {};
+  ps_status r = PS_OK;
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(fork, st);
+  int k = 0;
+  for (size_t i = 0; i < P.br.size() && e == hipSuccess && r == PS_OK; ++i) {
+    const Branch& B = P.br[i];
+    if (B.mats.empty()) continue;
+    if (k == 0) {
+      r = launch_branch(W, ba, B, st);
+    } else {
+      hipStream_t sk = side[k - 1];
+      e = hipStreamWaitEvent(sk, fork, 0);
+      if (e == hipSuccess) r = launch_branch(W, ba, B, sk);
+      if (e == hipSuccess && r == PS_OK) e = hipEventCreateWithFlags(&join[k], hipEventDisableTiming);
+      if (e == hipSuccess && r == PS_OK) e = hipEventRecord(join[k], sk);
+      if (e == hipSuccess && r == PS_OK) e = hipStreamWaitEvent(st, join[k], 0);
+    }
+    ++k;
+  }
+  for (int i = 0; i < kMaxBranch; ++i)
+    if (join[i]) (void)hipEventDestroy(join[i]);
+  if (fork) (void)hipEventDestroy(fork);
+  if (r != PS_OK) return r;
+  if (e != hipSuccess) return bfail(PS_ERR_HIP, "branch fork/join: %s", hipGetErrorString(e));
   return PS_OK;
 }
 
@@ -790,7 +958,7 @@ ps_status ps_workspace_size_batched(ps_dtype dtype, int batch, const int32_t* n,
                                     size_t* bytes) {
   if (!bytes) return ps_set_error(bfail(PS_ERR_ARG, "bytes == NULL"), g_batch_err.c_str());
   Plan2 P;
-  ps_status st = build_plan(dtype, batch, n, m, s, nullptr, nullptr, nullptr, nullptr, nullptr, P, false);
+  ps_status st = build_plan(dtype, batch, n, m, s, nullptr, nullptr, nullptr, nullptr, nullptr, P, false, Schedule());
   if (st) return ps_set_error(st, g_batch_err.c_str());
   *bytes = P.total;
   return PS_OK;
@@ -799,8 +967,10 @@ ps_status ps_workspace_size_batched(ps_dtype dtype, int batch, const int32_t* n,
 static ps_status batched_common(ps_dtype dtype, int batch, const int32_t* n, const void* const* A, const int64_t* lda,
                                 const double* coef, int m, const int32_t* s, const int32_t* sigma, void* const* E,
                                 const int64_t* lde, const ps_opts* opts, void* ws, size_t ws_bytes, void* stream,
-                                Plan2& P, BatchArgs& ba) {
-  ps_status st = build_plan(dtype, batch, n, m, s, sigma, A, lda, E, lde, P, true);
+                                Plan2& P, BatchArgs& ba, const Schedule* sch = nullptr) {
+  if (batch < 1 || !n) return bfail(PS_ERR_ARG, "batch = %d or n == NULL", batch);
+  ps_status st = build_plan(dtype, batch, n, m, s, sigma, A, lda, E, lde, P, true,
+                            sch ? *sch : cached_schedule(dtype, m, batch, n));
   if (st) return st;
   if (ws_bytes < P.total) return bfail(PS_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, P.total);
   if (!ws || ((uintptr_t)ws & 255)) return bfail(PS_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
@@ -824,7 +994,11 @@ ps_status ps_expm_batched(ps_dtype dtype, int batch, const int32_t* n, const voi
   hipStream_t st = (hipStream_t)stream;
   ps_status r = batched_common(dtype, batch, n, A, lda, coef, m, s, sigma, E, lde, opts, ws, ws_bytes, stream, P, ba);
   if (r) return ps_set_error(r, g_batch_err.c_str());
-  if ((r = launch_batch(dtype == PS_F64 ? 0 : 1, ba, P, st))) return ps_set_error(r, g_batch_err.c_str());
+  {
+    std::unique_lock<std::mutex> lock(g_branch_mu, std::defer_lock);
+    if (used_branches(P) > 1) lock.lock();
+    if ((r = launch_batch(dtype == PS_F64 ? 0 : 1, ba, P, st))) return ps_set_error(r, g_batch_err.c_str());
+  }
   if (tiers_out) {
     std::vector<int> chosen(batch);
     hipError_t e = hipMemcpyAsync(chosen.data(), ba.chosen, sizeof(int) * batch, hipMemcpyDeviceToHost, st);
@@ -849,6 +1023,61 @@ ps_status ps_eval_batched(ps_dtype dtype, int batch, const int32_t* n, const voi
   return ps_expm_batched(dtype, batch, n, A, lda, coef, m, s, nullptr, P, ldp, opts, tiers_out, ws, ws_bytes, stream);
 }
 
+}  // extern "C"
+
+// capture one batch's launch sequence (on a private stream: the legacy null
+// stream cannot be captured) and instantiate it
+static ps_status capture_batch(int W, const BatchArgs& ba, const Plan2& P, ps_batched_exec** out) {
+  hipStream_t cap;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return bfail(PS_ERR_HIP, "%s", hipGetErrorString(e));
+  ps_batched_exec* h = new ps_batched_exec();
+  ps_status r = PS_OK;
+  {
+    std::unique_lock<std::mutex> lock(g_branch_mu, std::defer_lock);
+    if (used_branches(P) > 1) lock.lock();   // the side streams join this capture
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      r = launch_batch(W, ba, P, cap);
+      hipError_t e2 = hipStreamEndCapture(cap, &h->graph);
+      if (r == PS_OK && e2 != hipSuccess) e = e2;
+    }
+  }
+  if (e == hipSuccess && r == PS_OK) e = hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess || r != PS_OK) {
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    delete h;
+    return r ? r : bfail(PS_ERR_HIP, "%s", hipGetErrorString(e));
+  }
+  *out = h;
+  return PS_OK;
+}
+
+// the contiguous groupings of the present classes (in increasing order) into
+// at most kMaxBranch branches
+static std::vector<Schedule> candidate_schedules(const int cls_count[kMaxClass + 1]) {
+  std::vector<int> present;
+  for (int c = 1; c <= kMaxClass; ++c)
+    if (cls_count[c] > 0) present.push_back(c);
+  std::vector<Schedule> out;
+  const int K = (int)present.size();
+  if (K == 0) return {Schedule()};
+  for (int cut = 0; cut < (1 << (K - 1)); ++cut) {   // bit i: a new branch starts after present class i
+    Schedule sch;
+    int g = 0;
+    for (int i = 0; i < K; ++i) {
+      sch.group[present[i] - 1] = g;
+      if (i < K - 1 && ((cut >> i) & 1)) ++g;
+    }
+    out.push_back(sch);
+  }
+  return out;
+}
+
+extern "C" {
+
 ps_status ps_batched_prepare(ps_dtype dtype, int batch, const int32_t* n, const void* const* A, const int64_t* lda,
                              const double* coef, int m, const int32_t* s, const int32_t* sigma, void* const* E,
                              const int64_t* lde, const ps_opts* opts, void* ws, size_t ws_bytes, void* stream,
@@ -859,26 +1088,140 @@ ps_status ps_batched_prepare(ps_dtype dtype, int batch, const int32_t* n, const 
   BatchArgs ba;
   ps_status r = batched_common(dtype, batch, n, A, lda, coef, m, s, sigma, E, lde, opts, ws, ws_bytes, stream, P, ba);
   if (r) return ps_set_error(r, g_batch_err.c_str());
-  // capture on a private stream (the legacy null stream cannot be captured)
-  hipStream_t cap;
-  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-  if (e != hipSuccess) return ps_set_error(PS_ERR_HIP, hipGetErrorString(e));
-  ps_batched_exec* h = new ps_batched_exec();
-  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    r = launch_batch(dtype == PS_F64 ? 0 : 1, ba, P, cap);
-    hipError_t e2 = hipStreamEndCapture(cap, &h->graph);
-    if (r == PS_OK && e2 != hipSuccess) e = e2;
-  }
-  if (e == hipSuccess && r == PS_OK) e = hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0);
-  (void)hipStreamDestroy(cap);
-  if (e != hipSuccess || r != PS_OK) {
-    if (h->exec) (void)hipGraphExecDestroy(h->exec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
+  if ((r = capture_batch(dtype == PS_F64 ? 0 : 1, ba, P, out))) return ps_set_error(r, g_batch_err.c_str());
+  return PS_OK;
+}
+
+ps_status ps_batched_tune(ps_dtype dtype, int batch, const int32_t* n, const void* const* A, const int64_t* lda,
+                          const double* coef, int m, const int32_t* s, const int32_t* sigma, void* const* E,
+                          const int64_t* lde, const ps_opts* opts, void* ws, size_t ws_bytes, void* stream, int reps,
+                          int32_t* groups_out, float* ms_out, int* ncand_out) {
+  if (reps < 1 || reps > 1000) return ps_set_error(PS_ERR_ARG, "reps out of range [1, 1000]");
+  if (batch < 1 || !n) return ps_set_error(PS_ERR_ARG, "batch < 1 or n == NULL");
+  int cc[kMaxClass + 1];
+  count_classes(batch, n, cc);
+  const std::vector<Schedule> cand = candidate_schedules(cc);
+  hipStream_t st = (hipStream_t)stream;
+  const int W = dtype == PS_F64 ? 0 : 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) return ps_set_error(PS_ERR_HIP, hipGetErrorString(he));
+  int best = -1;
+  float best_ms = 0.0f;
+  ps_status r = PS_OK;
+  for (size_t k = 0; k < cand.size() && r == PS_OK; ++k) {
+    Plan2 P;
+    BatchArgs ba;
+    r = batched_common(dtype, batch, n, A, lda, coef, m, s, sigma, E, lde, opts, ws, ws_bytes, stream, P, ba,
+                       &cand[k]);
+    ps_batched_exec* h = nullptr;
+    if (r == PS_OK) r = capture_batch(W, ba, P, &h);
+    if (r != PS_OK) break;
+    // one warm-up replay, then the median of reps timed replays
+    std::vector<float> t;
+    he = hipGraphLaunch(h->exec, st);
+    for (int q = 0; q < reps && he == hipSuccess; ++q) {
+      he = hipEventRecord(e0, st);
+      if (he == hipSuccess) he = hipGraphLaunch(h->exec, st);
+      if (he == hipSuccess) he = hipEventRecord(e1, st);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      t.push_back(ms);
+    }
+    (void)hipGraphExecDestroy(h->exec);
+    (void)hipGraphDestroy(h->graph);
     delete h;
-    return ps_set_error(r ? r : PS_ERR_HIP, r ? g_batch_err.c_str() : hipGetErrorString(e));
+    if (he != hipSuccess) {
+      r = bfail(PS_ERR_HIP, "tuning replay: %s", hipGetErrorString(he));
+      break;
+    }
+    std::sort(t.begin(), t.end());
+    const float med = t[t.size() / 2];
+    if (ms_out && k < 8) ms_out[k] = med;
+    if (best < 0 || med < best_ms) {
+      best = (int)k;
+      best_ms = med;
+    }
   }
-  *out = h;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r != PS_OK) return ps_set_error(r, g_batch_err.c_str());
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    g_cache[schedule_key(dtype, m, cc)] = cand[best];
+  }
+  if (groups_out)
+    for (int c = 0; c < kMaxClass; ++c) groups_out[c] = cand[best].group[c];
+  if (ncand_out) *ncand_out = (int)cand.size();
+  return PS_OK;
+}
+
+ps_status ps_autotune_lookup(ps_dtype dtype, int batch, const int32_t* n, int m, int32_t* groups_out, int* found) {
+  if (!n || batch < 1 || !groups_out || !found) return ps_set_error(PS_ERR_ARG, "NULL argument or batch < 1");
+  int cc[kMaxClass + 1];
+  count_classes(batch, n, cc);
+  const std::string key = schedule_key(dtype, m, cc);
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto it = g_cache.find(key);
+  *found = it != g_cache.end();
+  const Schedule sch = *found ? it->second : Schedule();
+  for (int c = 0; c < kMaxClass; ++c) groups_out[c] = sch.group[c];
+  return PS_OK;
+}
+
+ps_status ps_autotune_clear(void) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  g_cache.clear();
+  return PS_OK;
+}
+
+ps_status ps_autotune_save(const char* path) {
+  if (!path) return ps_set_error(PS_ERR_ARG, "path == NULL");
+  FILE* f = fopen(path, "w");
+  if (!f) return ps_set_error(PS_ERR_ARG, "cannot open the cache file for writing");
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  fprintf(f, "{\"ps_autotune\": 1, \"entries\": [");
+  bool first = true;
+  for (const auto& kv : g_cache) {
+    fprintf(f, "%s\n  {\"key\": \"%s\", \"groups\": [%d, %d, %d, %d]}", first ? "" : ",", kv.first.c_str(),
+            kv.second.group[0], kv.second.group[1], kv.second.group[2], kv.second.group[3]);
+    first = false;
+  }
+  fprintf(f, "\n]}\n");
+  fclose(f);
+  return PS_OK;
+}
+
+ps_status ps_autotune_load(const char* path) {
+  if (!path) return ps_set_error(PS_ERR_ARG, "path == NULL");
+  FILE* f = fopen(path, "r");
+  if (!f) return ps_set_error(PS_ERR_ARG, "cannot open the cache file");
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  fclose(f);
+  if (text.find("\"ps_autotune\": 1") == std::string::npos) return ps_set_error(PS_ERR_ARG, "not a cache file");
+  std::map<std::string, Schedule> add;
+  size_t pos = 0;
+  while ((pos = text.find("\"key\": \"", pos)) != std::string::npos) {
+    pos += 8;
+    const size_t end = text.find('"', pos);
+    const size_t gp = text.find("\"groups\": [", end == std::string::npos ? pos : end);
+    if (end == std::string::npos || gp == std::string::npos) return ps_set_error(PS_ERR_ARG, "malformed cache entry");
+    Schedule sch;
+    if (sscanf(text.c_str() + gp + 11, "%d , %d , %d , %d", &sch.group[0], &sch.group[1], &sch.group[2],
+               &sch.group[3]) != 4)
+      return ps_set_error(PS_ERR_ARG, "malformed groups in the cache file");
+    for (int c = 0; c < kMaxClass; ++c)
+      if (sch.group[c] < 0 || sch.group[c] >= kMaxBranch) return ps_set_error(PS_ERR_ARG, "group out of range");
+    add[text.substr(pos, end - pos)] = sch;
+    pos = gp;
+  }
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  for (const auto& kv : add) g_cache[kv.first] = kv.second;
   return PS_OK;
 }
 

@@ -264,3 +264,43 @@ def test_eval_batched_requires_coefficients(ps):
                            (ctypes.c_void_p * 1)(0x2000), (ctypes.c_int64 * 1)(4), None, None, 0x40000000, 1 << 30,
                            None)
     assert st == -1 and b"coef" in L.ps_last_error()
+
+
+def test_autotune_cache_roundtrip(ps, tmp_path):
+    """The schedule cache on the host: a JSON file loaded, looked up, saved and
+    loaded again; malformed files refused.  The key's architecture part comes
+    from the device (on a machine without one it reads 'unknown')."""
+    import torch
+    ps.autotune_clear()
+    mats = [torch.zeros(n, n) for n in (8, 100, 250, 250)]
+    found, groups = ps.autotune_lookup(mats, 18)
+    assert not found and groups == [0, 0, 0, 0]
+    # write an entry under the key this process computes: find it by saving one
+    L = ps.lib()
+    n = (ctypes.c_int32 * 4)(8, 100, 250, 250)
+    arch = "unknown"
+    if torch.cuda.is_available():
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = "%s|f32|m18|1,1,0,2" % arch            # classes 1, 2 and 4 with 1, 1 and 2 matrices
+    p = tmp_path / "cache.json"
+    p.write_text('{"ps_autotune": 1, "entries": [{"key": "%s", "groups": [0, 1, 1, 2]}]}' % key)
+    ps.autotune_load(p)
+    found, groups = ps.autotune_lookup(mats, 18)
+    assert found and groups == [0, 1, 1, 2]
+    q = tmp_path / "saved.json"
+    ps.autotune_save(q)
+    ps.autotune_clear()
+    assert not ps.autotune_lookup(mats, 18)[0]
+    ps.autotune_load(q)
+    assert ps.autotune_lookup(mats, 18) == (True, [0, 1, 1, 2])
+    assert not ps.autotune_lookup(mats, 16)[0]    # another degree: another key
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"something": 1}')
+    with pytest.raises(ps.PSError):
+        ps.autotune_load(bad)
+    bad.write_text('{"ps_autotune": 1, "entries": [{"key": "x", "groups": [0, 9, 0, 0]}]}')
+    with pytest.raises(ps.PSError):
+        ps.autotune_load(bad)
+    with pytest.raises(ps.PSError):
+        ps.autotune_load(tmp_path / "missing.json")
+    ps.autotune_clear()
