@@ -10,24 +10,30 @@
 //   k_lu_panel       one workgroup (256 threads up to 256 rows, 512 up to
 //                    2048 rows, 1024 above) factors the (n - k0) x nb panel
 //                    held in registers (thread t owns rows k0 + t + NT q);
-//                    per column a workgroup arg-max picks the pivot (largest
-//                    |entry|, lowest row on ties), the two rows are exchanged
-//                    through LDS, the multipliers are formed by division and
-//                    the rank-one update stays in registers.  It also writes
-//                    the panel's exchanges as one gather list (<= 2 nb rows).
+//                    per column a DPP wave arg-max and one barrier pick the
+//                    pivot (largest |entry|, lowest position on ties); rows
+//                    never move in the registers (each keeps its current
+//                    position, and goes there when the panel is stored), the
+//                    pivot row is read from the winning wave's LDS copy, the
+//                    multipliers are formed by division and the rank-one
+//                    update stays in registers.  It also writes the panel's
+//                    exchanges as one gather list (<= 2 nb rows).
 //   k_lu_swap_trsm   one wave per column outside the panel (Q's and P's):
 //                    the gather list applied in one load/store round, then,
 //                    right of the panel, the unit-lower triangular solve with
-//                    the panel's L11 (lanes = rows, shuffles for the pivots).
+//                    the panel's L11 (lanes = rows, lane reads for the pivots).
 //   k_lu_update      C -= A B with K <= 32 (panels) or 64 (back
 //                    substitution, LDS sized for each) for 64 x 64 tiles of C, 256
 //                    threads, FMA in the working type (HBM bound: every C
-//                    element is read and written once per panel).
+//                    element is read and written once per panel; C's loads
+//                    are issued first, ahead of the operand staging).
 //   k_lu_trsm_upper  back substitution with a <= 64-row diagonal block of U,
-//                    one wave per right-hand side.
+//                    one wave per right-hand side, multiplying by the
+//                    reciprocals of U's diagonal (formed once per block).
 // Panel width: 24 (FP64) or 32 (FP32) columns while at most 1024 rows are
 // left, then 16, 8 and 4 columns up to 2048, 4096 and 8192 rows (the
-// largest order), so that a thread's rows fit its registers.
+// largest order), so that a thread's rows fit its registers (FP64 panels of
+// more than 2048 rows on 512 threads, eight or sixteen rows each).
 #include <hip/hip_runtime.h>
 
 #include "ps_internal.h"
@@ -42,127 +48,205 @@ __global__ void k_fill_int(int* p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// DPP controls (gfx9 encoding): row_shr:k = 0x110 + k, row_bcast:15 =
+// 0x142, row_bcast:31 = 0x143.  The 64-bit value moves as two 32-bit halves.
+template <int CTRL, int ROWM, int BANKM>
+__device__ __forceinline__ double dpp_f64(double old, double src) {
+  const long long o = __double_as_longlong(old), s = __double_as_longlong(src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, CTRL, ROWM, BANKM, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), CTRL, ROWM, BANKM, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// The largest value over the wave (operands not NaN), returned to every lane:
+// row shifts build each row's maximum in its lane 15, the two row
+// broadcasts carry it to lane 63, which is then read.
+__device__ __forceinline__ double wave_max_f64(double x) {
+  x = fmax(x, dpp_f64<0x111, 0xf, 0xf>(x, x));
+  x = fmax(x, dpp_f64<0x112, 0xf, 0xf>(x, x));
+  x = fmax(x, dpp_f64<0x113, 0xf, 0xf>(x, x));
+  x = fmax(x, dpp_f64<0x114, 0xf, 0xe>(x, x));
+  x = fmax(x, dpp_f64<0x118, 0xf, 0xc>(x, x));
+  x = fmax(x, dpp_f64<0x142, 0xa, 0xf>(x, x));
+  x = fmax(x, dpp_f64<0x143, 0xc, 0xf>(x, x));
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <typename T, int NW, int NB>
+struct PanelLds {
+  double val[2][NW];   // each wave's candidate |value| (-1: none), by column parity
+  int pos[2][NW];      // its position
+  int who[2][NW];      // its lane * 8 + slot
+  T wrow[2][NW][NB];   // its row, columns j .. NB-1
+  int piv[NB];
+};
+
+// Column j of the panel (a compile-time constant, so that the register array
+// keeps constant indices).  No row moves in the registers: slot q of thread t
+// holds one row throughout, ps[q] is its current position (the exchanges of
+// partial pivoting permute positions) and bit q of `done` marks a row already
+// used as a pivot.  One barrier per column (the LDS areas alternate with the
+// column's parity): every wave stages its best row, then every thread picks
+// the winner from the NW candidates and reads the pivot row from LDS.
+template <typename T, int R, int NB, int NT, int j>
+__device__ __forceinline__ void panel_column(T (&a)[R][NB], int (&ps)[R], unsigned& done,
+                                             PanelLds<T, NT / 64, NB>& S, int k0, int nbe, int t, int lane, int w,
+                                             int& first_zero) {
+  if constexpr (j < NB) {
+    if (j < nbe) {
+      constexpr int NW = NT / 64, b = j & 1;
+      const int kk = k0 + j;
+      // this thread's best active row: largest |a| (a NaN below every
+      // number), the lowest position on ties
+      double bv = -1.0;
+      int bp = 0x7fffffff, bq = 0;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const double x = fabs((double)a[q][j]);
+        const double v = ((done >> q) & 1u) ? -1.0 : ((x == x) ? x : -0.5);
+        const bool take = (v > bv) | ((v == bv) & (ps[q] < bp));
+        bv = take ? v : bv;
+        bp = take ? ps[q] : bp;
+        bq = take ? q : bq;
+      }
+      // the wave's best: its largest value, then the lowest position among
+      // the lanes that hold it
+      const double wv = wave_max_f64(bv);
+      int wl = 0, wp = 0x7fffffff;
+      if (wv >= -0.5) {
+        unsigned long long m = __ballot(bv == wv);
+        wl = __ffsll((long long)m) - 1;
+        wp = __builtin_amdgcn_readlane(bp, wl);
+        m &= m - 1;
+        while (m) {
+          const int l = __ffsll((long long)m) - 1;
+          const int p2 = __builtin_amdgcn_readlane(bp, l);
+          if (p2 < wp) { wp = p2; wl = l; }
+          m &= m - 1;
+        }
+      }
+      const int wq = __builtin_amdgcn_readlane(bq, wl);
+      if (lane == wl) {
+        if (wv >= -0.5) {
+#pragma unroll
+          for (int jj = j; jj < NB; ++jj) {
+            T v = a[0][jj];
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+              T x = a[q][jj];
+              // an empty asm keeps the choice a select of values: otherwise
+              // the compiler folds the selects into one load at a variable
+              // index and moves the whole register array to scratch memory
+              asm volatile("" : "+v"(x));
+              v = (wq == q) ? x : v;
+            }
+            S.wrow[b][w][jj] = v;
+          }
+        }
+        S.val[b][w] = wv;
+        S.pos[b][w] = wp;
+        S.who[b][w] = wl * 8 + wq;
+      }
+      __syncthreads();
+      double cv[NW];
+      int cp[NW], cw[NW];
+#pragma unroll
+      for (int u = 0; u < NW; ++u) { cv[u] = S.val[b][u]; cp[u] = S.pos[b][u]; cw[u] = S.who[b][u]; }
+      double pv = cv[0];
+      int p = cp[0], ws = 0, who = cw[0];
+#pragma unroll
+      for (int u = 1; u < NW; ++u) {
+        const bool take = (cv[u] > pv) | ((cv[u] == pv) & (cp[u] < p));
+        pv = take ? cv[u] : pv;
+        p = take ? cp[u] : p;
+        ws = take ? u : ws;
+        who = take ? cw[u] : who;
+      }
+      p = __builtin_amdgcn_readfirstlane(p);
+      ws = __builtin_amdgcn_readfirstlane(ws);
+      who = __builtin_amdgcn_readfirstlane(who);
+      const int xl = who >> 3, xq = who & 7;
+      // the exchange of positions kk and p; the pivot row retires
+#pragma unroll
+      for (int q = 0; q < R; ++q)
+        if (ps[q] == kk) ps[q] = p;
+      if (w == ws && lane == xl) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (q == xq) { ps[q] = kk; done |= 1u << q; }
+      }
+      const T d = S.wrow[b][ws][j];
+      if (t == 0) {
+        S.piv[j] = p;
+        if (d == T(0) && first_zero == 0) first_zero = kk + 1;
+      }
+      // multipliers and the rank-one update of the active rows
+      if (d != T(0)) {
+        T pr[NB];
+#pragma unroll
+        for (int jj = j + 1; jj < NB; ++jj) pr[jj] = S.wrow[b][ws][jj];
+        T l[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) l[q] = a[q][j] / d;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          if (!((done >> q) & 1u)) {
+            a[q][j] = l[q];
+#pragma unroll
+            for (int jj = j + 1; jj < NB; ++jj) a[q][jj] -= l[q] * pr[jj];
+          }
+        }
+      }
+    }
+    panel_column<T, R, NB, NT, j + 1>(a, ps, done, S, k0, nbe, t, lane, w, first_zero);
+  }
+}
+
 template <typename T, int R, int NB, int NT>
 __global__ __launch_bounds__(NT) void k_lu_panel(T* __restrict__ Q, int64_t ld, int n, int k0,
                                                 int* __restrict__ piv, int* __restrict__ list,
                                                 int* __restrict__ info) {
-  constexpr int NW = NT / 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   if (n - k0 > R * NT || n <= k0) return;   // the host never launches this
   const int nbe = min(NB, n - k0);
-  __shared__ double s_val[NW];
-  __shared__ int s_row[NW];
-  __shared__ T s_prow[NB], s_krow[NB];
-  __shared__ int s_piv[NB];
-
+  __shared__ PanelLds<T, NT / 64, NB> S;
   T a[R][NB];
+  int ps[R];
+  unsigned done = 0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int row = k0 + t + q * NT;
+    ps[q] = row;
+    if (row >= n) done |= 1u << q;   // no such row: never a candidate, never stored
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj)
       a[q][jj] = (row < n && jj < nbe) ? Q[row + (int64_t)(k0 + jj) * ld] : T(0);
   }
-
+  const unsigned valid = ~done;
   int first_zero = 0;
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    if (j < nbe) {
-      const int kk = k0 + j;
-      // pivot: largest |a(row, j)| over rows >= kk, lowest row on ties
-      double bv = -1.0;
-      int br = kk;
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int row = k0 + t + q * NT;
-        if (row >= kk && row < n) {
-          const double v = fabs((double)a[q][j]);
-          if (v > bv) { bv = v; br = row; }
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off, 64);
-        const int orow = __shfl_xor(br, off, 64);
-        if (ov > bv || (ov == bv && orow < br)) { bv = ov; br = orow; }
-      }
-      if (lane == 0) { s_val[w] = bv; s_row[w] = br; }
-      __syncthreads();
-      double pv = s_val[0];
-      int p = s_row[0];
-      for (int u = 1; u < NW; ++u) {
-        const double v = s_val[u];
-        const int rr = s_row[u];
-        if (v > pv || (v == pv && rr < p)) { pv = v; p = rr; }
-      }
-      // exchange rows kk (thread j, slot 0) and p (thread pt, slot pq) through LDS
-      const int pt = (p - k0) % NT, pq = (p - k0) / NT;
-      if (t == pt) {
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-          if (q == pq) {
-#pragma unroll
-            for (int jj = 0; jj < NB; ++jj) s_prow[jj] = a[q][jj];
-          }
-      }
-      if (t == j && p != kk) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) s_krow[jj] = a[0][jj];
-      }
-      __syncthreads();
-      if (t == pt && p != kk) {
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-          if (q == pq) {
-#pragma unroll
-            for (int jj = 0; jj < NB; ++jj) a[q][jj] = s_krow[jj];
-          }
-      }
-      if (t == j) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) a[0][jj] = s_prow[jj];
-      }
-      const T d = s_prow[j];
-      if (t == 0) {
-        s_piv[j] = p;
-        if (d == T(0) && first_zero == 0) first_zero = kk + 1;
-      }
-      // multipliers and the rank-one update of the panel's remaining columns
-      if (d != T(0)) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const int row = k0 + t + q * NT;
-          if (row > kk && row < n) {
-            const T l = a[q][j] / d;
-            a[q][j] = l;
-#pragma unroll
-            for (int jj = 0; jj < NB; ++jj)
-              if (jj > j) a[q][jj] -= l * s_prow[jj];
-          }
-        }
-      }
-    }
-  }
+  panel_column<T, R, NB, NT, 0>(a, ps, done, S, k0, nbe, t, lane, w, first_zero);
+  // each row to its final position
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int row = k0 + t + q * NT;
-    if (row < n) {
+    if (((valid >> q) & 1u) && ps[q] >= k0 && ps[q] < n) {
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj)
-        if (jj < nbe) Q[row + (int64_t)(k0 + jj) * ld] = a[q][jj];
+        if (jj < nbe) Q[ps[q] + (int64_t)(k0 + jj) * ld] = a[q][jj];
     }
   }
-  __syncthreads();   // s_piv (written by thread 0) is read by all of wave 0
+  __syncthreads();   // S.piv (written by thread 0) is read by all of wave 0
   // the panel's exchanges as one gather: new row pos <- old row org, one
   // touched row per lane of wave 0 (rows k0 .. k0 + nbe - 1 in lanes 0 ..
   // nbe - 1, then each pivot row from below the panel's block)
   if (w == 0) {
-    if (lane < nbe) piv[k0 + lane] = s_piv[lane];
+    if (lane < nbe) piv[k0 + lane] = S.piv[lane];
     int pos = lane < nbe ? k0 + lane : -1;
     int org = pos;
     int cnt = nbe;
     for (int j = 0; j < nbe; ++j) {
-      const int p = s_piv[j];
+      const int p = S.piv[j];
       if (p == k0 + j) continue;
       const unsigned long long hit = __ballot(pos == p);
       int idx;
@@ -181,6 +265,18 @@ __global__ __launch_bounds__(NT) void k_lu_panel(T* __restrict__ Q, int64_t ld, 
       list[0] = cnt;
       if (first_zero != 0 && *info == 0) *info = first_zero;
     }
+  }
+}
+
+// lane j's x, for a wave-uniform j (a scalar read instead of a permute)
+template <typename T>
+__device__ __forceinline__ T lane_value(T x, int j) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __double_as_longlong((double)x);
+    const int lo = __builtin_amdgcn_readlane((int)b, j), hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+    return (T)__longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)x), j));
   }
 }
 
@@ -216,7 +312,7 @@ __global__ __launch_bounds__(256) void k_lu_swap_trsm(T* __restrict__ Q, int64_t
   if (lane < cnt) x = c[s_org[lane]];
   if (trsm) {
     for (int j = 0; j + 1 < nbe; ++j) {
-      const T xj = __shfl(x, j, 64);
+      const T xj = lane_value(x, j);
       if (lane > j && lane < nbe) x -= Ls[j][lane] * xj;
     }
   }
@@ -241,6 +337,16 @@ __global__ __launch_bounds__(256) void k_lu_update(const T* __restrict__ A, int6
   const int64_t c0 = (int64_t)(ct < tiles0 ? ct : ct - tiles0) * 64;
   const int r0 = cr0 + blockIdx.x * 64;
   T* M = (T*)S.M;
+  const int i = t & 63, cg = (t >> 6) * 16;
+  const int r = r0 + i;
+  // this thread's 16 elements of C, loaded first so that the loads are in
+  // flight while the operands are staged and multiplied
+  T cv[16];
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) {
+    const int64_t col = c0 + cg + cc;
+    cv[cc] = (r < cr1 && col < S.ncols) ? M[r + (S.col0 + col) * S.ld] : T(0);
+  }
   for (int idx = t; idx < 64 * K; idx += 256) {
     const int k = idx >> 6, i = idx & 63;
     const int r = r0 + i;
@@ -252,7 +358,6 @@ __global__ __launch_bounds__(256) void k_lu_update(const T* __restrict__ A, int6
     Bs[k][cc] = col < S.ncols ? M[(kb0 + k) + (S.col0 + col) * S.ld] : T(0);
   }
   __syncthreads();
-  const int i = t & 63, cg = (t >> 6) * 16;
   T acc[16];
 #pragma unroll
   for (int cc = 0; cc < 16; ++cc) acc[cc] = T(0);
@@ -261,15 +366,11 @@ __global__ __launch_bounds__(256) void k_lu_update(const T* __restrict__ A, int6
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) acc[cc] = fma(av, Bs[k][cg + cc], acc[cc]);
   }
-  const int r = r0 + i;
   if (r < cr1) {
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
       const int64_t col = c0 + cg + cc;
-      if (col < S.ncols) {
-        T* ptr = M + r + (S.col0 + col) * S.ld;
-        *ptr = *ptr - acc[cc];
-      }
+      if (col < S.ncols) M[r + (S.col0 + col) * S.ld] = cv[cc] - acc[cc];
     }
   }
 }
@@ -278,19 +379,21 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_lu_trsm_upper(const T* __restrict__ Q, int64_t ldq, T* __restrict__ P,
                                                        int64_t ldp, int k0, int b, int nrhs) {
   __shared__ T Us[64][65];   // Us[j][i] = U(k0 + i, k0 + j)
+  __shared__ T rd[64];       // 1 / U(k0 + j, k0 + j)
   const int t = threadIdx.x, lane = t & 63;
   for (int idx = t; idx < b * b; idx += 256) {
     const int i = idx % b, j = idx / b;
     Us[j][i] = Q[(k0 + i) + (int64_t)(k0 + j) * ldq];
   }
+  if (t < b) rd[t] = T(1) / Q[(k0 + t) + (int64_t)(k0 + t) * ldq];
   __syncthreads();
   const int64_t col = (int64_t)blockIdx.x * 4 + (t >> 6);
   if (col >= nrhs) return;
   T* c = P + col * ldp;
   T x = lane < b ? c[k0 + lane] : T(0);
   for (int j = b - 1; j >= 0; --j) {
-    if (lane == j) x = x / Us[j][j];
-    const T xj = __shfl(x, j, 64);
+    const T xj = lane_value(x, j) * rd[j];
+    if (lane == j) x = xj;
     if (lane < j) x -= Us[j][lane] * xj;
   }
   if (lane < b) c[k0 + lane] = x;
@@ -326,12 +429,20 @@ hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int
       hipLaunchKernelGGL((k_lu_panel<T, 4, 16, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
     } else if (rem <= 4 * kPanelThreads) {
       nb = 8;
-      hipLaunchKernelGGL((k_lu_panel<T, 4, 8, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
-                         piv, list, info);
+      // FP64: 512 threads with eight rows each (1024 threads leave 128
+      // registers per lane, too few for the row positions and staging)
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((k_lu_panel<T, 8, 8, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
+      else
+        hipLaunchKernelGGL((k_lu_panel<T, 4, 8, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
+                           piv, list, info);
     } else {
       nb = 4;
-      hipLaunchKernelGGL((k_lu_panel<T, 8, 4, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
-                         piv, list, info);
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((k_lu_panel<T, 16, 4, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
+      else
+        hipLaunchKernelGGL((k_lu_panel<T, 8, 4, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
+                           piv, list, info);
     }
     const int nbe = nb < rem ? nb : rem;
     const int64_t cols = (int64_t)n - nbe + nrhs;   // every column outside the panel
