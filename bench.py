@@ -92,7 +92,130 @@ def parse():
                          "sequential: eager calls on one stream (kernels never overlap; used for kernel traces)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run three 256 MiB device-to-device copies (known traffic, for counter scaling)")
+    ap.add_argument("--summarize", nargs="+", metavar="ARG",
+                    help="write a profile summary under profiles/ from rocprofv3 CSV output instead of running: "
+                         "'stats OUT DIR', 'traffic OUT DIR_FETCH DIR_WRITE' or 'mfma OUT DIR' "
+                         "(the header lines come from --note, one per use)")
+    ap.add_argument("--note", action="append", default=[],
+                    help="a header line of the summary (the workload, the command that made the CSVs)")
     return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# profile summaries (rocprofv3 CSV -> short text under profiles/)
+# ---------------------------------------------------------------------------
+SRC_FILES = ("ps_kernels.hip", "ps_device.h", "ps_batched.hip", "ps_dd.hip", "ps_solve.hip", "ps_api.cpp",
+             "ps_backward.cpp")
+
+
+def source_hashes():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2312_17396_amd", "csrc")
+    return {f: hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest() for f in SRC_FILES}
+
+
+def _csvs(d, suffix):
+    import glob
+    out = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not out:
+        raise SystemExit("no *%s under %s" % (suffix, d))
+    return out
+
+
+def _short(name, w=72):
+    return name if len(name) <= w else name[:w]
+
+
+def _header(notes, what):
+    h = source_hashes()
+    lines = ["# " + n for n in notes]
+    lines.append("# " + what)
+    lines.append("# source sha256 (first 16 hex digits): " +
+                 ", ".join("%s %s" % (f, h[f][:16]) for f in SRC_FILES))
+    return lines
+
+
+def summarize(args):
+    import csv
+    kind, out = args.summarize[0], args.summarize[1]
+    path = os.path.join(ROOT, "profiles", out)
+    if kind == "stats":
+        rows = []
+        for f in _csvs(args.summarize[2], "kernel_stats.csv"):
+            rows += list(csv.DictReader(open(f)))
+        rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        tot = sum(float(r["TotalDurationNs"]) for r in rows)
+        lines = _header(args.note, "rocprofv3 --kernel-trace --stats: per-kernel durations")
+        lines.append("%-72s %6s %11s %9s %9s %9s %6s" % ("kernel", "calls", "total_ms", "avg_us", "min_us", "max_us",
+                                                       "pct"))
+        for r in rows:
+            lines.append("%-72s %6s %11.3f %9.2f %9.2f %9.2f %6.2f" % (
+                _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+                float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, 100.0 * float(r["TotalDurationNs"]) / tot))
+    elif kind in ("traffic", "mfma"):
+        def per_kernel(d):
+            acc = {}
+            for f in _csvs(d, "counter_collection.csv"):
+                for r in csv.DictReader(open(f)):
+                    k = (r["Kernel_Name"], r["Counter_Name"])
+                    v = acc.setdefault(k, {})
+                    v[r.get("Dispatch_Id", r.get("Correlation_Id"))] = float(r["Counter_Value"])
+            return {k: (len(v), sum(v.values()) / len(v), max(v.values())) for k, v in acc.items()}
+        if kind == "mfma":
+            pk = per_kernel(args.summarize[2])
+            names = sorted({k[0] for k in pk})
+            lines = _header(args.note, "rocprofv3 --pmc MfmaUtil MfmaFlopsF64: averages over dispatches "
+                                       "(MfmaUtil = MFMA-busy cycles / (active cycles x SIMDs) in percent; "
+                                       "MfmaFlopsF64 = F64 MFMA ops x 512)")
+            lines.append("%-72s %6s %11s %16s" % ("kernel", "calls", "MfmaUtil_%", "F64_GFLOP/launch"))
+            for nm in names:
+                u = pk.get((nm, "MfmaUtil"))
+                fl = pk.get((nm, "MfmaFlopsF64"))
+                if not u:
+                    continue
+                lines.append("%-72s %6d %11.1f %16.3f" % (_short(nm), u[0], u[1], (fl[1] / 1e9) if fl else 0.0))
+        else:
+            pf = per_kernel(args.summarize[2])
+            pw = per_kernel(args.summarize[3])
+            # calibration: the 256 MiB device copies (largest written bytes among the copy kernels)
+            cal = [k[0] for k in pw if k[1] == "WRITE_SIZE" and ("copy" in k[0].lower() or "Copy" in k[0])]
+            if not cal:
+                raise SystemExit("no copy kernel in the WRITE_SIZE run: take it with --calib-copy")
+            ck = max(cal, key=lambda nm: pw[(nm, "WRITE_SIZE")][2])
+            kib = 256 * 1024.0
+            f_cal, w_cal = pf[(ck, "FETCH_SIZE")][2], pw[(ck, "WRITE_SIZE")][2]
+            fs, wsc = kib / f_cal, kib / w_cal
+            lines = _header(args.note, "rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE (KiB per dispatch), "
+                                       "one run each, scaled by a 256 MiB device copy")
+            lines.append("# calibration: the copy reads %.1f KiB fetched, %.1f KiB written -> scale fetch x%.3f, "
+                         "write x%.3f" % (f_cal, w_cal, fs, wsc))
+            lines.append("%-72s %6s %11s %11s %15s" % ("kernel", "calls", "fetch_MiB", "write_MiB", "hbm_MiB/launch"))
+            names = sorted({k[0] for k in pf if k[1] == "FETCH_SIZE"} & {k[0] for k in pw if k[1] == "WRITE_SIZE"})
+            gemm = None
+            for nm in names:
+                if nm == ck:
+                    continue
+                fm = pf[(nm, "FETCH_SIZE")][1] * fs / 1024.0
+                wm = pw[(nm, "WRITE_SIZE")][1] * wsc / 1024.0
+                lines.append("%-72s %6d %11.2f %11.2f %15.2f" % (_short(nm), pf[(nm, "FETCH_SIZE")][0], fm, wm, fm + wm))
+                if nm.startswith("void psk::k_gemm<double, false, false>"):
+                    gemm = (fm, wm)
+            if gemm is not None:
+                h = source_hashes()
+                rec = {"kernel": "k_gemm<double,false,false> n=1024",
+                       "kernel_source_sha256": h["ps_kernels.hip"], "device_header_sha256": h["ps_device.h"],
+                       "hbm_bytes_per_launch": int(round((gemm[0] + gemm[1]) * 1024 * 1024)),
+                       "fetch_MiB": round(gemm[0], 3), "write_MiB": round(gemm[1], 3),
+                       "fetch_scale": round(fs, 4), "write_scale": round(wsc, 4),
+                       "algorithmic_bytes_per_launch": 3 * N * N * 8}
+                with open(os.path.join(ROOT, "profiles", "traffic_gemm_f64_n1024.json"), "w") as fh:
+                    json.dump(rec, fh, indent=1)
+                    fh.write("\n")
+    else:
+        raise SystemExit("--summarize: stats, traffic or mfma")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", path)
 
 
 def gemm_count(sigma):
@@ -120,6 +243,9 @@ def load_traffic():
 
 def main():
     args = parse()
+    if args.summarize:
+        summarize(args)
+        return
     if args.gpus != 1:
         print("bench.py: runs on one GPU only (no multi-GPU path is implemented); "
               "run with --gpus 1", file=sys.stderr)
