@@ -275,14 +275,19 @@ def main():
 
     streams = [torch.cuda.Stream(device=dev) for _ in mats]   # default priority
 
+    # the forked step issues the evaluations longest first (most products,
+    # i.e. most squarings), so that the longest chain starts first: the
+    # runtime starts a graph's independent branches one after another
+    order = sorted(range(len(mats)), key=lambda i: (-gemm_count(sigmas[i]), i))
+
     def step_forked(mode):
         """the four evaluations on four streams (they are independent), joined"""
         cur = torch.cuda.current_stream(dev)
         for st in streams:
             st.wait_stream(cur)
-        for a, o, w, sg, st in zip(mats, outs, wss, sigmas, streams):
+        for i, st in zip(order, streams):
             with torch.cuda.stream(st):
-                ps.ps_expm(a, M, s=S, sigma=sg, mode=mode, out=o, workspace=w)
+                ps.ps_expm(mats[i], M, s=S, sigma=sigmas[i], mode=mode, out=outs[i], workspace=wss[i])
         for st in streams:
             cur.wait_stream(st)
 
