@@ -36,6 +36,8 @@
 // more than 2048 rows on 512 threads, eight or sixteen rows each).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ps_internal.h"
 
 namespace psk {
@@ -204,14 +206,18 @@ __device__ __forceinline__ void panel_column(T (&a)[R][NB], int (&ps)[R], unsign
   }
 }
 
+// The factorisation of the panel at column k0 by one workgroup of NT threads.
+// Kp > 0: the panel's columns first take the trailing update of the previous
+// panel (at kp = k0 - Kp): a -= L21 U12 with the sum over k formed in the
+// order of k_lu_update (a fused multiply-add chain from k = 0, then one
+// subtraction), so the values are those the update kernel would store.
 template <typename T, int R, int NB, int NT>
-__global__ __launch_bounds__(NT) void k_lu_panel(T* __restrict__ Q, int64_t ld, int n, int k0,
-                                                int* __restrict__ piv, int* __restrict__ list,
-                                                int* __restrict__ info) {
+__device__ __forceinline__ void panel_factor(T* __restrict__ Q, int64_t ld, int n, int k0, int* __restrict__ piv,
+                                             int* __restrict__ list, int* __restrict__ info, int Kp) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  if (n - k0 > R * NT || n <= k0) return;   // the host never launches this
   const int nbe = min(NB, n - k0);
   __shared__ PanelLds<T, NT / 64, NB> S;
+  __shared__ T Us[32][NB];   // U12 of the previous panel, restricted to this panel's columns
   T a[R][NB];
   int ps[R];
   unsigned done = 0;
@@ -223,6 +229,36 @@ __global__ __launch_bounds__(NT) void k_lu_panel(T* __restrict__ Q, int64_t ld, 
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj)
       a[q][jj] = (row < n && jj < nbe) ? Q[row + (int64_t)(k0 + jj) * ld] : T(0);
+  }
+  if (Kp > 0) {
+    const int kp = k0 - Kp;
+    for (int idx = t; idx < Kp * NB; idx += NT) {
+      const int k = idx / NB, jj = idx - k * NB;
+      Us[k][jj] = jj < nbe ? Q[(kp + k) + (int64_t)(k0 + jj) * ld] : T(0);
+    }
+    __syncthreads();
+    // eight columns at a time (each element's sum is the same whatever the
+    // grouping), which keeps the accumulators within the register budget
+    constexpr int JC = NB < 8 ? NB : 8;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int row = k0 + t + q * NT;
+      if (row < n) {
+#pragma unroll
+        for (int j0 = 0; j0 < NB; j0 += JC) {
+          T acc[JC];
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj) acc[jj] = T(0);
+          for (int k = 0; k < Kp; ++k) {
+            const T lk = Q[row + (int64_t)(kp + k) * ld];
+#pragma unroll
+            for (int jj = 0; jj < JC; ++jj) acc[jj] = fma(lk, Us[k][j0 + jj], acc[jj]);
+          }
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj) a[q][j0 + jj] = a[q][j0 + jj] - acc[jj];
+        }
+      }
+    }
   }
   const unsigned valid = ~done;
   int first_zero = 0;
@@ -266,6 +302,14 @@ __global__ __launch_bounds__(NT) void k_lu_panel(T* __restrict__ Q, int64_t ld, 
       if (first_zero != 0 && *info == 0) *info = first_zero;
     }
   }
+}
+
+template <typename T, int R, int NB, int NT>
+__global__ __launch_bounds__(NT) void k_lu_panel(T* __restrict__ Q, int64_t ld, int n, int k0,
+                                                int* __restrict__ piv, int* __restrict__ list,
+                                                int* __restrict__ info) {
+  if (n - k0 > R * NT || n <= k0) return;   // the host never launches this
+  panel_factor<T, R, NB, NT>(Q, ld, n, k0, piv, list, info, 0);
 }
 
 // lane j's x, for a wave-uniform j (a scalar read instead of a permute)
@@ -375,6 +419,69 @@ __global__ __launch_bounds__(256) void k_lu_update(const T* __restrict__ A, int6
   }
 }
 
+// One step of the factorisation in one launch: block 0 factors the next
+// panel (at r1 = k0 + K, width nbn), first applying this step's trailing
+// update to its own columns (panel_factor with Kp = K), while the other
+// blocks apply the trailing update of the panel at k0 (C -= L21 U12 with
+// K <= 32, the arithmetic of k_lu_update) to 64 x 64 tiles of C outside the
+// next panel's columns.  The two parts write disjoint columns and read only
+// columns left of r1 and rows above it, which this launch does not write.
+template <typename T, int R, int NB, int NT>
+__global__ __launch_bounds__(NT) void k_lu_step(T* Q, int64_t ldq, int k0, int K, int cr1, int n, int nbn,
+                                               UpdSeg s0, UpdSeg s1, int tiles0, int nrt, int ntiles,
+                                               int* __restrict__ piv, int* __restrict__ list, int* __restrict__ info) {
+  constexpr int CPT = 4096 / NT;   // columns of the tile per thread
+  __shared__ T As[32][64];         // As[k][i]
+  __shared__ T Bs[32][64];         // Bs[k][c]
+  const int t = threadIdx.x;
+  const int cr0 = k0 + K;
+  if (blockIdx.x == 0) {
+    panel_factor<T, R, NB, NT>(Q, ldq, n, cr0, piv, list, info, K);
+    return;
+  }
+  const int idx = (int)blockIdx.x - 1;
+  const int ct = idx / nrt, rt = idx % nrt;
+  const UpdSeg S = ct < tiles0 ? s0 : s1;
+  const int64_t c0 = (int64_t)(ct < tiles0 ? ct : ct - tiles0) * 64;
+  const int64_t cskip = ct == 0 ? nbn : 0;   // the next panel's columns: block 0 updates them
+  const int r0 = cr0 + rt * 64;
+  T* M = (T*)S.M;
+  const int i = t & 63, cg = (t >> 6) * CPT;
+  const int r = r0 + i;
+  T cv[CPT];
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int64_t col = c0 + cg + cc;
+    cv[cc] = (r < cr1 && col < S.ncols && col >= cskip) ? M[r + (S.col0 + col) * S.ld] : T(0);
+  }
+  for (int idx2 = t; idx2 < 64 * K; idx2 += NT) {
+    const int k = idx2 >> 6, ii = idx2 & 63;
+    const int rr = r0 + ii;
+    As[k][ii] = rr < cr1 ? Q[rr + (int64_t)(k0 + k) * ldq] : T(0);
+  }
+  for (int idx2 = t; idx2 < 64 * K; idx2 += NT) {
+    const int cc = idx2 / K, k = idx2 - cc * K;
+    const int64_t col = c0 + cc;
+    Bs[k][cc] = col < S.ncols ? M[(k0 + k) + (S.col0 + col) * S.ld] : T(0);
+  }
+  __syncthreads();
+  T acc[CPT];
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) acc[cc] = T(0);
+  for (int k = 0; k < K; ++k) {
+    const T av = As[k][i];
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) acc[cc] = fma(av, Bs[k][cg + cc], acc[cc]);
+  }
+  if (r < cr1) {
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+      const int64_t col = c0 + cg + cc;
+      if (col < S.ncols && col >= cskip) M[r + (S.col0 + col) * S.ld] = cv[cc] - acc[cc];
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_trsm_upper(const T* __restrict__ Q, int64_t ldq, T* __restrict__ P,
                                                        int64_t ldp, int k0, int b, int nrhs) {
@@ -399,64 +506,107 @@ __global__ __launch_bounds__(256) void k_lu_trsm_upper(const T* __restrict__ Q, 
   if (lane < b) c[k0 + lane] = x;
 }
 
+// Launches the panel factorisation at k0 for `rem` rows left, alone
+// (step == nullptr) or fused with the trailing update of the previous panel
+// (k_lu_step); the panel shape (rows per thread R, width NB, threads NT) is
+// chosen by dispatch_panel below.
+template <typename T>
+struct PanelLaunch {
+  T* Q;
+  int64_t ldq;
+  int n, k0;
+  int *piv, *list, *info;
+  hipStream_t st;
+  // fused step: the previous panel at kp (width K), its update segments
+  bool fused;
+  int kp, K, tiles0, nrt, ntiles;
+  UpdSeg s0, s1;
+  template <int R, int NB, int NT>
+  void go() const {
+    if (!fused)
+      hipLaunchKernelGGL((k_lu_panel<T, R, NB, NT>), dim3(1), dim3(NT), 0, st, Q, ldq, n, k0, piv, list, info);
+    else
+      hipLaunchKernelGGL((k_lu_step<T, R, NB, NT>), dim3((unsigned)ntiles + 1), dim3(NT), 0, st, Q, ldq, kp, K, n,
+                         n, std::min(NB, n - k0), s0, s1, tiles0, nrt, ntiles, piv, list, info);
+  }
+};
+
+// Panel width: 24 (FP64) or 32 (FP32) columns while at most 1024 rows are
+// left, then 16, 8 and 4 columns up to 2048, 4096 and 8192 rows.  Returns
+// the width.
+template <typename T>
+int dispatch_panel(int rem, const PanelLaunch<T>& l) {
+  // 32 doubles per thread leave no room under the 128-VGPR limit of a
+  // 1024-thread workgroup (the compiler moves the array to scratch)
+  constexpr int NB1 = sizeof(T) == 8 ? 24 : 32;
+  if (rem <= 256) {
+    l.template go<1, NB1, 256>();
+    return NB1;
+  }
+  if (rem <= 512) {
+    l.template go<1, NB1, 512>();
+    return NB1;
+  }
+  if (rem <= kPanelThreads) {
+    // FP64: fewer waves per barrier, 512 threads with two rows each (64
+    // FP32 values per thread would go to scratch: 1024 threads there)
+    if constexpr (sizeof(T) == 8) l.template go<2, NB1, 512>();
+    else l.template go<1, NB1, kPanelThreads>();
+    return NB1;
+  }
+  if (rem <= 2 * kPanelThreads) {
+    l.template go<4, 16, 512>();
+    return 16;
+  }
+  if (rem <= 4 * kPanelThreads) {
+    // FP64: 512 threads with eight rows each (1024 threads leave 128
+    // registers per lane, too few for the row positions and staging)
+    if constexpr (sizeof(T) == 8) l.template go<8, 8, 512>();
+    else l.template go<4, 8, kPanelThreads>();
+    return 8;
+  }
+  if constexpr (sizeof(T) == 8) l.template go<16, 4, 512>();
+  else l.template go<8, 4, kPanelThreads>();
+  return 4;
+}
+
 template <typename T>
 hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int* piv, int* info, int* list,
                       hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, st, info, 0);
+  PanelLaunch<T> l{};
+  l.Q = Q;
+  l.ldq = ldq;
+  l.n = n;
+  l.piv = piv;
+  l.list = list;
+  l.info = info;
+  l.st = st;
+  l.fused = false;
+  l.k0 = 0;
+  int nb = dispatch_panel<T>(n, l);
   for (int k0 = 0; k0 < n;) {
     const int rem = n - k0;
-    int nb;
-    // 32 doubles per thread leave no room under the 128-VGPR limit of a
-    // 1024-thread workgroup (the compiler moves the array to scratch)
-    constexpr int NB1 = sizeof(T) == 8 ? 24 : 32;
-    if (rem <= 256) {
-      nb = NB1;
-      hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, 256>), dim3(1), dim3(256), 0, st, Q, ldq, n, k0, piv, list, info);
-    } else if (rem <= 512) {
-      nb = NB1;
-      hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
-    } else if (rem <= kPanelThreads) {
-      // FP64: fewer waves per barrier, 512 threads with two rows each (64
-      // FP32 values per thread would go to scratch: 1024 threads there)
-      nb = NB1;
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((k_lu_panel<T, 2, NB1, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
-      else
-        hipLaunchKernelGGL((k_lu_panel<T, 1, NB1, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n,
-                           k0, piv, list, info);
-    } else if (rem <= 2 * kPanelThreads) {
-      nb = 16;
-      hipLaunchKernelGGL((k_lu_panel<T, 4, 16, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
-    } else if (rem <= 4 * kPanelThreads) {
-      nb = 8;
-      // FP64: 512 threads with eight rows each (1024 threads leave 128
-      // registers per lane, too few for the row positions and staging)
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((k_lu_panel<T, 8, 8, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
-      else
-        hipLaunchKernelGGL((k_lu_panel<T, 4, 8, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
-                           piv, list, info);
-    } else {
-      nb = 4;
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((k_lu_panel<T, 16, 4, 512>), dim3(1), dim3(512), 0, st, Q, ldq, n, k0, piv, list, info);
-      else
-        hipLaunchKernelGGL((k_lu_panel<T, 8, 4, kPanelThreads>), dim3(1), dim3(kPanelThreads), 0, st, Q, ldq, n, k0,
-                           piv, list, info);
-    }
     const int nbe = nb < rem ? nb : rem;
     const int64_t cols = (int64_t)n - nbe + nrhs;   // every column outside the panel
     if (cols > 0)
       hipLaunchKernelGGL(k_lu_swap_trsm<T>, dim3((unsigned)((cols + 3) / 4)), dim3(256), 0, st, Q, ldq, P, ldp, n,
                          k0, nbe, nrhs, (const int*)list);
     const int r1 = k0 + nbe;
-    if (r1 < n) {
-      UpdSeg s0{Q, ldq, r1, n - r1}, s1{P, ldp, 0, nrhs};
-      const int t0 = (n - r1 + 63) / 64, t1 = (nrhs + 63) / 64;
-      hipLaunchKernelGGL((k_lu_update<T, 32>), dim3((n - r1 + 63) / 64, t0 + t1), dim3(256), 0, st, (const T*)Q, ldq, k0,
-                         nbe, k0, r1, n, s0, s1, t0);
-    }
-    k0 += nbe;
+    if (r1 >= n) break;
+    // the trailing update of this panel and the next panel's factorisation
+    // in one launch
+    l.fused = true;
+    l.k0 = r1;
+    l.kp = k0;
+    l.K = nbe;
+    l.s0 = UpdSeg{Q, ldq, r1, n - r1};
+    l.s1 = UpdSeg{P, ldp, 0, nrhs};
+    l.tiles0 = (n - r1 + 63) / 64;
+    l.nrt = (n - r1 + 63) / 64;
+    l.ntiles = l.nrt * (l.tiles0 + (nrhs + 63) / 64);
+    nb = dispatch_panel<T>(n - r1, l);
+    k0 = r1;
   }
   if (nrhs > 0) {
     for (int kb = (n - 1) / 64; kb >= 0; --kb) {
