@@ -7,8 +7,9 @@
 // L^{-1} Pi P and only the back substitution with U remains.
 //
 // Kernels (working type T = double or float):
-//   k_lu_panel       one workgroup (256 threads up to 256 rows, 512 up to
-//                    2048 rows, 1024 above) factors the (n - k0) x nb panel
+//   k_lu_panel       one workgroup (256 threads up to 256 rows, 512 above;
+//                    FP32: 1024 from 513 to 1024 and above 2048 rows) factors
+//                    the (n - k0) x nb panel
 //                    held in registers (thread t owns rows k0 + t + NT q);
 //                    per column a DPP wave arg-max and one barrier pick the
 //                    pivot (largest |entry|, lowest position on ties); rows
@@ -22,11 +23,14 @@
 //                    the gather list applied in one load/store round, then,
 //                    right of the panel, the unit-lower triangular solve with
 //                    the panel's L11 (lanes = rows, lane reads for the pivots).
-//   k_lu_update      C -= A B with K <= 32 (panels) or 64 (back
-//                    substitution, LDS sized for each) for 64 x 64 tiles of C, 256
-//                    threads, FMA in the working type (HBM bound: every C
-//                    element is read and written once per panel; C's loads
-//                    are issued first, ahead of the operand staging).
+//   k_lu_step        one launch per panel after the first: block 0 applies
+//                    the previous panel's trailing update to its own columns
+//                    and factors it (as k_lu_panel), the other blocks apply
+//                    that update, C -= L21 U12 with K <= 32, to the 64 x 64
+//                    tiles of the other columns (FMA in the working type,
+//                    C's loads issued first).
+//   k_lu_update_mfma the back substitution's update (K <= 64) on the FP64 /
+//                    FP32 matrix cores, 64 x 64 tiles.
 //   k_lu_trsm_upper  back substitution with a <= 64-row diagonal block of U,
 //                    one wave per right-hand side, multiplying by the
 //                    reciprocals of U's diagonal (formed once per block).
@@ -208,9 +212,9 @@ __device__ __forceinline__ void panel_column(T (&a)[R][NB], int (&ps)[R], unsign
 
 // The factorisation of the panel at column k0 by one workgroup of NT threads.
 // Kp > 0: the panel's columns first take the trailing update of the previous
-// panel (at kp = k0 - Kp): a -= L21 U12 with the sum over k formed in the
-// order of k_lu_update (a fused multiply-add chain from k = 0, then one
-// subtraction), so the values are those the update kernel would store.
+// panel (at kp = k0 - Kp): a -= L21 U12 with the sum over k formed as the
+// update tiles of k_lu_step form it (a fused multiply-add chain from k = 0,
+// then one subtraction).
 template <typename T, int R, int NB, int NT>
 __device__ __forceinline__ void panel_factor(T* __restrict__ Q, int64_t ld, int n, int k0, int* __restrict__ piv,
                                              int* __restrict__ list, int* __restrict__ info, int Kp) {
@@ -368,62 +372,12 @@ struct UpdSeg {
   int64_t ld, col0, ncols;
 };
 
-// C(r, col) -= sum_k A(r, ac0 + k) B(kb0 + k, col) for rows r in [cr0, cr1);
-// C and B are the segment's matrix, columns col0 .. col0 + ncols - 1.
-template <typename T, int KMAX>
-__global__ __launch_bounds__(256) void k_lu_update(const T* __restrict__ A, int64_t lda, int ac0, int K, int kb0,
-                                                   int cr0, int cr1, UpdSeg s0, UpdSeg s1, int tiles0) {
-  __shared__ T As[KMAX][64];   // As[k][i]
-  __shared__ T Bs[KMAX][64];   // Bs[k][c]
-  const int t = threadIdx.x;
-  const int ct = blockIdx.y;
-  const UpdSeg S = ct < tiles0 ? s0 : s1;
-  const int64_t c0 = (int64_t)(ct < tiles0 ? ct : ct - tiles0) * 64;
-  const int r0 = cr0 + blockIdx.x * 64;
-  T* M = (T*)S.M;
-  const int i = t & 63, cg = (t >> 6) * 16;
-  const int r = r0 + i;
-  // this thread's 16 elements of C, loaded first so that the loads are in
-  // flight while the operands are staged and multiplied
-  T cv[16];
-#pragma unroll
-  for (int cc = 0; cc < 16; ++cc) {
-    const int64_t col = c0 + cg + cc;
-    cv[cc] = (r < cr1 && col < S.ncols) ? M[r + (S.col0 + col) * S.ld] : T(0);
-  }
-  for (int idx = t; idx < 64 * K; idx += 256) {
-    const int k = idx >> 6, i = idx & 63;
-    const int r = r0 + i;
-    As[k][i] = r < cr1 ? A[r + (int64_t)(ac0 + k) * lda] : T(0);
-  }
-  for (int idx = t; idx < 64 * K; idx += 256) {
-    const int cc = idx / K, k = idx - cc * K;
-    const int64_t col = c0 + cc;
-    Bs[k][cc] = col < S.ncols ? M[(kb0 + k) + (S.col0 + col) * S.ld] : T(0);
-  }
-  __syncthreads();
-  T acc[16];
-#pragma unroll
-  for (int cc = 0; cc < 16; ++cc) acc[cc] = T(0);
-  for (int k = 0; k < K; ++k) {
-    const T av = As[k][i];
-#pragma unroll
-    for (int cc = 0; cc < 16; ++cc) acc[cc] = fma(av, Bs[k][cg + cc], acc[cc]);
-  }
-  if (r < cr1) {
-#pragma unroll
-    for (int cc = 0; cc < 16; ++cc) {
-      const int64_t col = c0 + cg + cc;
-      if (col < S.ncols) M[r + (S.col0 + col) * S.ld] = cv[cc] - acc[cc];
-    }
-  }
-}
 
 // One step of the factorisation in one launch: block 0 factors the next
 // panel (at r1 = k0 + K, width nbn), first applying this step's trailing
 // update to its own columns (panel_factor with Kp = K), while the other
 // blocks apply the trailing update of the panel at k0 (C -= L21 U12 with
-// K <= 32, the arithmetic of k_lu_update) to 64 x 64 tiles of C outside the
+// K <= 32) to 64 x 64 tiles of C outside the
 // next panel's columns.  The two parts write disjoint columns and read only
 // columns left of r1 and rows above it, which this launch does not write.
 template <typename T, int R, int NB, int NT>
@@ -482,15 +436,116 @@ __global__ __launch_bounds__(NT) void k_lu_step(T* Q, int64_t ldq, int k0, int K
   }
 }
 
+// The back substitution's update C -= A B (C: rows [0, cr1) of P, A: the
+// block column of U above the diagonal block, B: the block's solved rows of
+// P, K <= 64) on the matrix cores: a 64 x 64 tile of C per 256-thread
+// workgroup, each wave a 32 x 32 quadrant as 2 x 2 blocks of 16 x 16 x 4
+// MFMAs (lane (g, c) = (lane / 16, lane % 16) feeds A[c][k = g] and B[k =
+// g][c]; the FP64 product leaves D[4v + g][c], the FP32 one D[4g + v][c] in
+// its v-th value), A and B staged whole in LDS with K padded by zeros to a
+// multiple of 4, this lane's C elements loaded first.
+typedef double lu_d4 __attribute__((ext_vector_type(4)));
+typedef float lu_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct LuMma;
+template <> struct LuMma<double> {
+  typedef lu_d4 V;
+  static __device__ inline V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int v, int g) { return 4 * v + g; }
+};
+template <> struct LuMma<float> {
+  typedef lu_f4 V;
+  static __device__ inline V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int v, int g) { return 4 * g + v; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_update_mfma(const T* __restrict__ A, int64_t lda, int ac0, int K, int kb0,
+                                                        int cr1, T* __restrict__ M, int64_t ldm, int64_t ncols) {
+  __shared__ T As[64][65];   // As[k][i] = A(r0 + i, ac0 + k)
+  __shared__ T Bs[64][65];   // Bs[k][c] = M(kb0 + k, c0 + c)
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
+  const int r0 = blockIdx.x * 64;
+  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  const int K4 = (K + 3) & ~3;
+  // this lane's 16 elements of C
+  T cv[2][2][4];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + wr + 16 * mb + LuMma<T>::row(v, g);
+        const int64_t col = c0 + wc + 16 * nb + c;
+        cv[mb][nb][v] = (row < cr1 && col < ncols) ? M[row + col * ldm] : T(0);
+      }
+  // the operands: every load of a thread issued before the first LDS store
+  // (a loop with a run-time trip count would wait for each load in turn)
+  T ra[16], rb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q;
+    const int k = idx >> 6, i = idx & 63;
+    const int row = r0 + i;
+    ra[q] = (k < K && row < cr1) ? A[row + (int64_t)(ac0 + k) * lda] : T(0);
+    const int cc = idx / K4, kb = idx - cc * K4;
+    const int64_t col = c0 + cc;
+    rb[q] = (idx < 64 * K4 && kb < K && col < ncols) ? M[(kb0 + kb) + col * ldm] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q;
+    if (idx < 64 * K4) {
+      As[idx >> 6][idx & 63] = ra[q];
+      const int cc = idx / K4, kb = idx - cc * K4;
+      Bs[kb][cc] = rb[q];
+    }
+  }
+  __syncthreads();
+  typename LuMma<T>::V acc[2][2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) acc[mb][nb] = typename LuMma<T>::V{0, 0, 0, 0};
+  for (int k = 0; k < K4; k += 4) {
+    const T a0 = As[k + g][wr + c], a1 = As[k + g][wr + 16 + c];
+    const T b0 = Bs[k + g][wc + c], b1 = Bs[k + g][wc + 16 + c];
+    acc[0][0] = LuMma<T>::mma(a0, b0, acc[0][0]);
+    acc[0][1] = LuMma<T>::mma(a0, b1, acc[0][1]);
+    acc[1][0] = LuMma<T>::mma(a1, b0, acc[1][0]);
+    acc[1][1] = LuMma<T>::mma(a1, b1, acc[1][1]);
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + wr + 16 * mb + LuMma<T>::row(v, g);
+        const int64_t col = c0 + wc + 16 * nb + c;
+        if (row < cr1 && col < ncols) M[row + col * ldm] = cv[mb][nb][v] - acc[mb][nb][v];
+      }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_trsm_upper(const T* __restrict__ Q, int64_t ldq, T* __restrict__ P,
                                                        int64_t ldp, int k0, int b, int nrhs) {
   __shared__ T Us[64][65];   // Us[j][i] = U(k0 + i, k0 + j)
   __shared__ T rd[64];       // 1 / U(k0 + j, k0 + j)
   const int t = threadIdx.x, lane = t & 63;
-  for (int idx = t; idx < b * b; idx += 256) {
-    const int i = idx % b, j = idx / b;
-    Us[j][i] = Q[(k0 + i) + (int64_t)(k0 + j) * ldq];
+  // the block's loads all issued before the LDS stores
+  T ru[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q;
+    const int i = idx & 63, j = idx >> 6;
+    ru[q] = (i < b && j < b) ? Q[(k0 + i) + (int64_t)(k0 + j) * ldq] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q;
+    Us[idx >> 6][idx & 63] = ru[q];
   }
   if (t < b) rd[t] = T(1) / Q[(k0 + t) + (int64_t)(k0 + t) * ldq];
   __syncthreads();
@@ -613,12 +668,9 @@ hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int
       const int k0 = kb * 64, b = (n - k0) < 64 ? (n - k0) : 64;
       hipLaunchKernelGGL(k_lu_trsm_upper<T>, dim3((nrhs + 3) / 4), dim3(256), 0, st, (const T*)Q, ldq, P, ldp, k0, b,
                          nrhs);
-      if (k0 > 0) {
-        UpdSeg s0{P, ldp, 0, nrhs}, s1{nullptr, 0, 0, 0};
-        const int t0 = (nrhs + 63) / 64;
-        hipLaunchKernelGGL((k_lu_update<T, 64>), dim3((k0 + 63) / 64, t0), dim3(256), 0, st, (const T*)Q, ldq, k0, b, k0,
-                           0, k0, s0, s1, t0);
-      }
+      if (k0 > 0)
+        hipLaunchKernelGGL(k_lu_update_mfma<T>, dim3((k0 + 63) / 64, (nrhs + 63) / 64), dim3(256), 0, st, (const T*)Q,
+                           ldq, k0, b, k0, k0, P, ldp, (int64_t)nrhs);
     }
   }
   return hipGetLastError();
