@@ -337,9 +337,17 @@ __global__ __launch_bounds__(256) void k_lu_swap_trsm(T* __restrict__ Q, int64_t
   const int t = threadIdx.x, lane = t & 63;
   if (t == 0) s_cnt = list[0];
   if (t < kListMax) { s_pos[t] = list[1 + t]; s_org[t] = list[1 + kListMax + t]; }
-  for (int idx = t; idx < nbe * nbe; idx += 256) {
-    const int i = idx % nbe, j = idx / nbe;
-    Ls[j][i] = Q[(k0 + i) + (int64_t)(k0 + j) * ldq];
+  T rl[4];   // the panel's L11 (at most 32 x 32): loads first, then the stores
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = t + 256 * q;
+    const int i = idx & 31, j = idx >> 5;
+    rl[q] = (i < nbe && j < nbe) ? Q[(k0 + i) + (int64_t)(k0 + j) * ldq] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = t + 256 * q;
+    Ls[idx >> 5][idx & 31] = rl[q];
   }
   __syncthreads();
   const int cnt = s_cnt;
@@ -408,15 +416,27 @@ __global__ __launch_bounds__(NT) void k_lu_step(T* Q, int64_t ldq, int k0, int K
     const int64_t col = c0 + cg + cc;
     cv[cc] = (r < cr1 && col < S.ncols && col >= cskip) ? M[r + (S.col0 + col) * S.ld] : T(0);
   }
-  for (int idx2 = t; idx2 < 64 * K; idx2 += NT) {
+  // the operands: every load issued before the first LDS store
+  constexpr int AQ = 64 * 32 / NT;
+  T ra[AQ], rb[AQ];
+#pragma unroll
+  for (int q = 0; q < AQ; ++q) {
+    const int idx2 = t + NT * q;
     const int k = idx2 >> 6, ii = idx2 & 63;
     const int rr = r0 + ii;
-    As[k][ii] = rr < cr1 ? Q[rr + (int64_t)(k0 + k) * ldq] : T(0);
-  }
-  for (int idx2 = t; idx2 < 64 * K; idx2 += NT) {
-    const int cc = idx2 / K, k = idx2 - cc * K;
+    ra[q] = (k < K && rr < cr1) ? Q[rr + (int64_t)(k0 + k) * ldq] : T(0);
+    const int cc = idx2 / K, kb = idx2 - cc * K;
     const int64_t col = c0 + cc;
-    Bs[k][cc] = col < S.ncols ? M[(k0 + k) + (S.col0 + col) * S.ld] : T(0);
+    rb[q] = (idx2 < 64 * K && col < S.ncols) ? M[(k0 + kb) + (S.col0 + col) * S.ld] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < AQ; ++q) {
+    const int idx2 = t + NT * q;
+    if (idx2 < 64 * K) {
+      As[idx2 >> 6][idx2 & 63] = ra[q];
+      const int cc = idx2 / K, kb = idx2 - cc * K;
+      Bs[kb][cc] = rb[q];
+    }
   }
   __syncthreads();
   T acc[CPT];
