@@ -236,31 +236,41 @@ __device__ __forceinline__ void panel_factor(T* __restrict__ Q, int64_t ld, int 
   }
   if (Kp > 0) {
     const int kp = k0 - Kp;
-    for (int idx = t; idx < Kp * NB; idx += NT) {
+    constexpr int UQ = (32 * NB + NT - 1) / NT;   // U12 elements per thread (Kp <= 32)
+    T ru[UQ];
+#pragma unroll
+    for (int q = 0; q < UQ; ++q) {
+      const int idx = t + NT * q;
       const int k = idx / NB, jj = idx - k * NB;
-      Us[k][jj] = jj < nbe ? Q[(kp + k) + (int64_t)(k0 + jj) * ld] : T(0);
+      ru[q] = (k < Kp && jj < nbe) ? Q[(kp + k) + (int64_t)(k0 + jj) * ld] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < UQ; ++q) {
+      const int idx = t + NT * q;
+      if (idx < 32 * NB) Us[idx / NB][idx % NB] = ru[q];
     }
     __syncthreads();
-    // eight columns at a time (each element's sum is the same whatever the
-    // grouping), which keeps the accumulators within the register budget
-    constexpr int JC = NB < 8 ? NB : 8;
+    // eight k at a time: the row's eight L21 loads are issued together (a
+    // zero beyond Kp, whose product with U12's zero leaves the sum as it is:
+    // the sums start at +0 and never become -0)
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int row = k0 + t + q * NT;
       if (row < n) {
+        T acc[NB];
 #pragma unroll
-        for (int j0 = 0; j0 < NB; j0 += JC) {
-          T acc[JC];
+        for (int jj = 0; jj < NB; ++jj) acc[jj] = T(0);
+        for (int kc = 0; kc < Kp; kc += 8) {
+          T lk[8];
 #pragma unroll
-          for (int jj = 0; jj < JC; ++jj) acc[jj] = T(0);
-          for (int k = 0; k < Kp; ++k) {
-            const T lk = Q[row + (int64_t)(kp + k) * ld];
+          for (int kk = 0; kk < 8; ++kk) lk[kk] = (kc + kk < Kp) ? Q[row + (int64_t)(kp + kc + kk) * ld] : T(0);
 #pragma unroll
-            for (int jj = 0; jj < JC; ++jj) acc[jj] = fma(lk, Us[k][j0 + jj], acc[jj]);
-          }
+          for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
-          for (int jj = 0; jj < JC; ++jj) a[q][j0 + jj] = a[q][j0 + jj] - acc[jj];
+            for (int jj = 0; jj < NB; ++jj) acc[jj] = fma(lk[kk], Us[kc + kk][jj], acc[jj]);
         }
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) a[q][jj] = a[q][jj] - acc[jj];
       }
     }
   }
