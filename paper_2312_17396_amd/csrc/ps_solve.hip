@@ -395,9 +395,11 @@ struct UpdSeg {
 // panel (at r1 = k0 + K, width nbn), first applying this step's trailing
 // update to its own columns (panel_factor with Kp = K), while the other
 // blocks apply the trailing update of the panel at k0 (C -= L21 U12 with
-// K <= 32) to 64 x 64 tiles of C outside the
-// next panel's columns.  The two parts write disjoint columns and read only
-// columns left of r1 and rows above it, which this launch does not write.
+// K <= 32) to the 64 x 64 tiles of C outside the next panel's columns.  The
+// two parts write disjoint columns, and both read only the columns of the
+// panel at k0 (rows r1 and below) and the rows above r1, which this launch
+// does not write; the exchange list that block 0 writes is read by the next
+// launch only.
 template <typename T, int R, int NB, int NT>
 __global__ __launch_bounds__(NT) void k_lu_step(T* Q, int64_t ldq, int k0, int K, int cr1, int n, int nbn,
                                                UpdSeg s0, UpdSeg s1, int tiles0, int nrt, int ntiles,
