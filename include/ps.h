@@ -424,26 +424,33 @@ ps_status ps_batched_destroy(ps_batched_handle h);
  * branches; each branch is a launch sequence of its own over its matrices'
  * tiles, and the branches run concurrently (forked from the caller's stream
  * and joined back by events; graph edges under capture).  A schedule changes
- * which launch processes a tile, never a tile's arithmetic: every schedule
- * gives the same bits.
+ * which launch processes a tile, never a tile's arithmetic.  The matrices
+ * of class 1 (orders up to 64: one 64 x 64 tile) can instead be evaluated
+ * whole by one workgroup each, every phase in one launch (whole64 = 1), on
+ * the same tile routines in the same order.  Every schedule gives the same
+ * bits.
  *   ps_batched_tune: times every contiguous grouping of the batch's classes
- *     (in increasing order) into at most four branches on this batch (one
- *     captured graph per candidate, one warm-up replay, median of `reps`
- *     replays timed with events on `stream`, which the call synchronises),
- *     keeps the fastest in the process-wide cache under a key of device
- *     architecture, dtype, degree m and the order of magnitude of each
- *     class's matrix count, and returns it: groups_out[c-1] = branch of
- *     class c (host array of 4; may be NULL), ms_out[k] = candidate k's
- *     median (host array of 8; may be NULL), *ncand_out = candidates (may be
- *     NULL).  Arguments and workspace as ps_batched_prepare.  ps_expm_batched,
- *     ps_eval_batched and ps_batched_prepare use the cached schedule of a
- *     matching key, otherwise one branch.
- *   ps_autotune_lookup: the schedule the cache holds for such a batch
- *     (*found = 0: none; groups_out then the one-branch default).
+ *     (in increasing order) into at most four branches, and each grouping
+ *     that gives class 1 a branch of its own once more with whole64 = 1, on
+ *     this batch (one captured graph per candidate, one warm-up replay,
+ *     median of `reps` replays timed with events on `stream`, which the call
+ *     synchronises), keeps the fastest in the process-wide cache under a key
+ *     of device architecture, dtype, degree m and the order of magnitude of
+ *     each class's matrix count, and returns it: groups_out[c-1] = branch of
+ *     class c, groups_out[4] = whole64 (host array of 5; may be NULL),
+ *     ms_out[k] = candidate k's median (host array of 16; may be NULL),
+ *     *ncand_out = candidates (may be NULL).  Arguments and workspace as
+ *     ps_batched_prepare.  ps_expm_batched, ps_eval_batched and
+ *     ps_batched_prepare use the cached schedule of a matching key,
+ *     otherwise one branch of per-phase launches.
+ *   ps_autotune_lookup: the schedule the cache holds for such a batch, in
+ *     groups_out (host array of 5, as above; *found = 0: none, groups_out
+ *     then the one-branch default).
  *   ps_autotune_save / ps_autotune_load: the cache as a JSON file
- *     ({"ps_autotune": 1, "entries": [{"key": ..., "groups": [g1,g2,g3,g4]}]});
- *     load adds the file's entries to the cache (PS_ERR_ARG for a file that is
- *     missing or not such a cache).  ps_autotune_clear empties the cache.
+ *     ({"ps_autotune": 1, "entries": [{"key": ..., "groups": [g1,g2,g3,g4],
+ *     "whole64": w}]}; an entry without "whole64" reads as 0); load adds the
+ *     file's entries to the cache (PS_ERR_ARG for a file that is missing or
+ *     not such a cache).  ps_autotune_clear empties the cache.
  * The cache is guarded by a mutex; multi-branch batches are queued (or
  * captured) under a second mutex, since their side streams are a per-device
  * pool created on first use and kept until the process ends.

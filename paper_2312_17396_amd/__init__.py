@@ -707,7 +707,9 @@ def ps_expm_backward_batched(mats, grads, m, s=None, sigma=0, coef=None, recompu
 def batched_tune(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0, delta=10.0, rule="blocks",
                  reps=3):
     """Time the size-class schedules of this batch (ps_batched_tune) and keep
-    the fastest in the library's cache; returns {"groups": [...4], "ms": [...]}."""
+    the fastest in the library's cache; returns {"groups": [...4] (branch of
+    each size class), "whole64": 0/1 (class 1 evaluated one workgroup per
+    matrix), "ms": [...] (each candidate's median replay)}."""
     import torch
     mats = [_check_square(a) for a in mats]
     k = len(mats)
@@ -720,22 +722,26 @@ def batched_tune(mats, m, s=None, sigma=0, coef=None, mode="fixed", tier_mask=0,
     lda = (ctypes.c_int64 * k)(*[a.shape[0] for a in mats])
     o, _k = _opts(mode, tier_mask, delta, rule=rule)
     c = _darr(coef) if coef is not None else None
-    groups = (ctypes.c_int32 * 4)()
-    ms = (ctypes.c_float * 8)()
+    groups = (ctypes.c_int32 * 5)()
+    ms = (ctypes.c_float * 16)()
     ncand = ctypes.c_int()
     _check(lib().ps_batched_tune(dt, k, n, aptr, lda, c, int(m), sv, sgv, eptr, lda, ctypes.byref(o), wsp, wsb,
                                  _stream_ptr(mats[0].device), int(reps), groups, ms, ctypes.byref(ncand)))
-    return {"groups": list(groups), "ms": [round(ms[i], 4) for i in range(min(ncand.value, 8))]}
+    return {"groups": list(groups)[:4], "whole64": int(groups[4]),
+            "ms": [round(ms[i], 4) for i in range(min(ncand.value, 16))]}
 
 
-def autotune_lookup(mats, m):
-    """(found, groups) of the cached size-class schedule for such a batch."""
+def autotune_lookup(mats, m, whole64=False):
+    """(found, groups) of the cached size-class schedule for such a batch;
+    with whole64=True, (found, groups, whole64)."""
     k = len(mats)
     n = (ctypes.c_int32 * k)(*[int(a.shape[0]) for a in mats])
-    groups = (ctypes.c_int32 * 4)()
+    groups = (ctypes.c_int32 * 5)()
     found = ctypes.c_int()
     _check(lib().ps_autotune_lookup(_dtype_code(mats[0]), k, n, int(m), groups, ctypes.byref(found)))
-    return bool(found.value), list(groups)
+    if whole64:
+        return bool(found.value), list(groups)[:4], int(groups[4])
+    return bool(found.value), list(groups)[:4]
 
 
 def autotune_save(path):

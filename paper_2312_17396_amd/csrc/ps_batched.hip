@@ -128,11 +128,12 @@ __device__ inline int tiles_m(int64_t n) { return (int)((n + kTileM - 1) / kTile
 
 
 // ---- block size: ||X||_1 = 2^-sigma ||A||_1, then the cheaper of the two layouts
+// (whole workgroup; red: NW + 1 doubles of LDS).  Returns the pick (0: L[0],
+// 1: L[1]) to every thread; thread 0 also records it and the matrix's
+// resolved descriptor.
 template <typename W>
-__global__ __launch_bounds__(NT) void k_bchoose(BatchArgs a) {
+__device__ __forceinline__ int bchoose_body(const BatchArgs& a, int b, double* red) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
-  __shared__ double red[NW + 1];
-  const int b = a.mat_tasks[blockIdx.x];
   const BatchItem& it = a.items[b];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   int pick = 1;
@@ -188,13 +189,18 @@ __global__ __launch_bounds__(NT) void k_bchoose(BatchArgs a) {
     r.sigma = it.sigma;
     r.L = it.L[pick];
   }
+  return pick;
+}
+
+template <typename W>
+__global__ __launch_bounds__(NT) void k_bchoose(BatchArgs a) {
+  __shared__ double red[NW + 1];
+  (void)bchoose_body<W>(a, a.mat_tasks[blockIdx.x], red);
 }
 
 // ---- zero-padded copy of A: one 64 x kTileN tile of the padded square per workgroup
 template <typename W>
-__global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
-  const int task = a.tile_tasks[blockIdx.x];
-  const int b = task >> 8, tile = task & 255;
+__device__ __forceinline__ void bpad_tile(const BatchArgs& a, int b, int tile) {
   const BatchItem& it = a.items[b];
   const int64_t np = it.L[0].n, n = it.nv;
   const int ntm = tiles_m(np);
@@ -212,6 +218,12 @@ __global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
   }
 #pragma unroll
   for (int q = 0; q < TILE_Q; ++q) X[m0 + row + (n0 + (t >> 6) + NW * q) * np] = v[q];
+}
+
+template <typename W>
+__global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
+  const int task = a.tile_tasks[blockIdx.x];
+  bpad_tile<W>(a, task >> 8, task & 255);
 }
 
 // Sums over the 64 lanes of a wave of eight values per lane: three exchange
@@ -446,10 +458,7 @@ __device__ __forceinline__ void assemble_tile(const BatchArgs& a, const BatchRes
 // (Y), whose block assembly follows in the same workgroup.  Two kernels, so
 // that the plain products keep the register count (and occupancy) of a GEMM.
 template <typename W, bool ASM>
-__device__ __forceinline__ void bpower_tile(const BatchArgs& a, int j, char* smem) {
-  const int task = a.tile_tasks[blockIdx.x];
-  const int b = task >> 8, tile = task & 255;
-  const BatchRes& it = a.res[b];
+__device__ __forceinline__ void bpower_tile(const BatchArgs& a, const BatchRes& it, int tile, int j, char* smem) {
   const Layout& L = it.L;
   if (ASM ? (j != L.s) : (j >= L.s)) return;   // uniform: the whole workgroup leaves
   const int64_t n = L.n;
@@ -483,36 +492,39 @@ __device__ __forceinline__ void bpower_tile(const BatchArgs& a, int j, char* sme
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower(BatchArgs a, int j) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
-  bpower_tile<W, false>(a, j, smem);
+  const int task = a.tile_tasks[blockIdx.x];
+  bpower_tile<W, false>(a, a.res[task >> 8], task & 255, j, smem);
 }
 
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower_asm(BatchArgs a, int j) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
-  bpower_tile<W, true>(a, j, smem);
+  const int task = a.tile_tasks[blockIdx.x];
+  bpower_tile<W, true>(a, a.res[task >> 8], task & 255, j, smem);
 }
 
 // ---- block assembly of the matrices with s = 1 (no power products: Y = X_1)
 template <typename W>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bassemble1(BatchArgs a) {
-  const int task = a.tile_tasks[blockIdx.x];
-  const int b = task >> 8, tile = task & 255;
-  const BatchRes& it = a.res[b];
-  if (it.L.s != 1) return;   // uniform
+__device__ __forceinline__ void bassemble1_tile(const BatchArgs& a, const BatchRes& it, int tile) {
   const int ntm = tiles_m(it.L.n);
   W x[kAsmGather - 1][TILE_Q];
   assemble_tile<W, false>(a, it, (const W*)nullptr, 1.0, (int64_t)(tile % ntm) * kTileM,
                           (int64_t)(tile / ntm) * kTileN, x);
 }
 
-// ---- precision plan: one workgroup per matrix
 template <typename W>
-__global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bassemble1(BatchArgs a) {
+  const int task = a.tile_tasks[blockIdx.x];
+  const BatchRes& it = a.res[task >> 8];
+  if (it.L.s != 1) return;   // uniform
+  bassemble1_tile<W>(a, it, task & 255);
+}
+
+// ---- precision plan: one workgroup per matrix
+// red: 8 NW doubles, norms: PS_MAX_BLOCKS + 2 doubles of LDS; ends with a barrier
+template <typename W>
+__device__ __forceinline__ void bplan_body(const BatchArgs& a, const BatchRes& it, double* red, double* norms) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
-  __shared__ double red[8 * NW];
-  __shared__ double norms[PS_MAX_BLOCKS + 2];
-  const int b = a.mat_tasks[blockIdx.x];
-  const BatchRes& it = a.res[b];
   const Layout& L = it.L;
   PlanArgs pa;
   pa.r = L.r;
@@ -531,23 +543,27 @@ __global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
   plan_matrix<NT>(pa, L, pa.ws, red, norms);
 }
 
+template <typename W>
+__global__ __launch_bounds__(NT) void k_bplan(BatchArgs a) {
+  __shared__ double red[8 * NW];
+  __shared__ double norms[PS_MAX_BLOCKS + 2];
+  bplan_body<W>(a, a.res[a.mat_tasks[blockIdx.x]], red, norms);
+}
+
 // ---- Horner step k: k = -1 casts B_{i0} into the format of step i0; k >= 0
 // is step i = i0 - k.  The cast writes P0; step k reads P0 (k even) or P1
 // (k odd) and writes the other buffer.
+// tier_in, tier_out: the plan's tiers of step i and of the next step
+// (ignored where the cast or the final output fixes them)
 template <typename W>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bhorner(BatchArgs a, int k) {
+__device__ __forceinline__ void bhorner_tile(const BatchArgs& a, const BatchRes& it, int tile, int k, int tier_in,
+                                             int tier_out, char* smem) {
   constexpr int WT = std::is_same<W, double>::value ? 0 : 1;
-  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
-  const int task = a.tile_tasks[blockIdx.x];
-  const int b = task >> 8, tile = task & 255;
-  const BatchRes& it = a.res[b];
   const Layout& L = it.L;
   const int i0 = L.first_step;
-  if (k >= i0) return;   // uniform
   const int64_t n = L.n;
   const int ntm = tiles_m(n);
   char* ws = it.ws;
-  const Plan* P = (const Plan*)(ws + L.off_plan);
   const int64_t se = (int64_t)(L.slot / sizeof(W));
   const W* pw = (const W*)(ws + L.off_pow);
   const bool square = it.sigma > 0;
@@ -574,8 +590,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   h.fy32 = nullptr;
   h.fyc = 0.0;
   const bool final_out = cast ? (i0 == 0) : (i == 1);
-  h.t_in = cast ? -1 : P->tier[i];
-  h.t_out = final_out ? WT : P->tier[cast ? i0 : i - 1];
+  h.t_in = cast ? -1 : tier_in;
+  h.t_out = final_out ? WT : tier_out;
   h.pin = ws + ((k & 1) ? L.off_P1 : L.off_P0);
   h.pout = cast ? ws + L.off_P0 : ws + ((k & 1) ? L.off_P0 : L.off_P1);
   h.bsrc = (const W*)(ws + L.off_B) + (int64_t)(cast ? i0 : i - 1) * se;
@@ -586,14 +602,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   horner_tile<W, false>(h, (int64_t)(tile % ntm) * kTileM, (int64_t)(tile / ntm) * kTileN, smem);
 }
 
-// ---- squaring q (1..sigma): R_q = R_{q-1}^2, R_0 in L.off_R, ping-pong with P0
 template <typename W>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bsquare(BatchArgs a, int q) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bhorner(BatchArgs a, int k) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
-  const int b = task >> 8, tile = task & 255;
-  const BatchRes& it = a.res[b];
-  if (q > it.sigma) return;   // uniform
+  const BatchRes& it = a.res[task >> 8];
+  const int i0 = it.L.first_step;
+  if (k >= i0) return;   // uniform
+  const Plan* P = (const Plan*)(it.ws + it.L.off_plan);
+  const int i = i0 - k;
+  bhorner_tile<W>(a, it, task & 255, k, k < 0 ? -1 : P->tier[i], P->tier[k < 0 ? i0 : i - 1], smem);
+}
+
+// ---- squaring q (1..sigma): R_q = R_{q-1}^2, R_0 in L.off_R, ping-pong with P0
+template <typename W>
+__device__ __forceinline__ void bsquare_tile(const BatchRes& it, int tile, int q, char* smem) {
   const Layout& L = it.L;
   const int64_t n = L.n;
   const int ntm = tiles_m(n);
@@ -605,6 +628,64 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   const int64_t ldd = (q == it.sigma) ? it.lde : n;
   gemm_tile<W, false, false>(src, n, src, n, dst, ldd, n, (q == it.sigma) ? it.nv : n, (int64_t)(tile % ntm) * kTileM,
                              (int64_t)(tile / ntm) * kTileN, 1.0, 0, smem);
+}
+
+template <typename W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bsquare(BatchArgs a, int q) {
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
+  const int task = a.tile_tasks[blockIdx.x];
+  const BatchRes& it = a.res[task >> 8];
+  if (q > it.sigma) return;   // uniform
+  bsquare_tile<W>(it, task & 255, q, smem);
+}
+
+// a tier of the plan this workgroup has just written: a vector load (never
+// the scalar cache, which the workgroup's own stores do not update)
+__device__ inline int plan_tier(const Plan* P, int i) {
+  return __hip_atomic_load(&P->tier[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ---- the whole evaluation of a matrix of padded order 64 (a single tile) in
+// one workgroup: the phases above, in their order, on the same tile, each one
+// finished (its stores complete, then a barrier) before the next reads what it
+// wrote.  The arithmetic is that of the per-phase launches, so are the bits;
+// a size class of such matrices takes one launch instead of s + r + sigma + 5.
+template <typename W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bwhole(BatchArgs a) {
+  __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
+  __shared__ double red[8 * NW];
+  __shared__ double norms[PS_MAX_BLOCKS + 2];
+  // the matrix's resolved descriptor in LDS: read where each phase needs it,
+  // not held in registers across the phases
+  __shared__ BatchRes s_it;
+  const int b = a.mat_tasks[blockIdx.x];
+  const int pick = bchoose_body<W>(a, b, red);
+  if (threadIdx.x == 0) {
+    const BatchItem& item = a.items[b];
+    s_it.ws = a.ws + item.ws_off;
+    s_it.X1 = a.ws + item.ws_off + item.off_x1;
+    s_it.E = item.E;
+    s_it.lde = item.lde;
+    s_it.nv = item.nv;
+    s_it.sigma = item.sigma;
+    s_it.L = item.L[pick];
+  }
+  bpad_tile<W>(a, b, 0);
+  __syncthreads();
+  const BatchRes& it = s_it;
+  const int s = it.L.s;
+  for (int j = 2; j < s; ++j) bpower_tile<W, false>(a, it, 0, j, smem);
+  if (s >= 2) bpower_tile<W, true>(a, it, 0, s, smem);
+  else bassemble1_tile<W>(a, it, 0);
+  __syncthreads();
+  bplan_body<W>(a, it, red, norms);
+  const Plan* P = (const Plan*)(it.ws + it.L.off_plan);
+  const int i0 = it.L.first_step;
+  for (int k = -1; k < i0; ++k) {
+    const int i = i0 - k;
+    bhorner_tile<W>(a, it, 0, k, k < 0 ? -1 : plan_tier(P, i), plan_tier(P, k < 0 ? i0 : i - 1), smem);
+  }
+  for (int q = 1; q <= it.sigma; ++q) bsquare_tile<W>(it, 0, q, smem);
 }
 
 }  // namespace psk
@@ -632,14 +713,17 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kMaxClass = 4;     // padded orders 64, 128, 192, 256
 constexpr int kMaxBranch = 4;
+constexpr int kMaxCand = 16;     // schedules the tuner can time: 8 groupings, 4 with k_bwhole
 
 // one branch of a batch: its matrices, their tiles and the bounds of its
 // launch loops
 struct Branch {
-  std::vector<int> mats, tiles;
+  std::vector<int> mats, tiles;   // matrices (and their tiles) that take the per-phase launches
+  std::vector<int> whole;         // matrices evaluated by k_bwhole, one workgroup each
   int smax = 1, kmax = 0, sigmax = 0;
   std::vector<char> s_possible;   // s_possible[s]: some matrix of the branch may take block size s
-  size_t off_mats = 0, off_tiles = 0;
+  size_t off_mats = 0, off_tiles = 0, off_whole = 0;
+  bool empty() const { return mats.empty() && whole.empty(); }
 };
 
 struct Plan2 {
@@ -649,9 +733,12 @@ struct Plan2 {
   size_t off_items, off_res, off_pick, off_chosen, total;
 };
 
-// schedule: group[c - 1] = branch of class c (c = 1..kMaxClass)
+// schedule: group[c - 1] = branch of class c (c = 1..kMaxClass); whole64 = 1:
+// the matrices of class 1 (padded order 64, one tile) are evaluated by
+// k_bwhole, one workgroup per matrix, instead of the per-phase launches
 struct Schedule {
   int group[kMaxClass] = {0, 0, 0, 0};
+  int whole64 = 0;
 };
 
 int s_floor(int m) {
@@ -718,6 +805,10 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
     const int cls = (int)(np / kTileM);
     P.cls_count[cls] += 1;
     Branch& B = P.br[sch.group[cls - 1]];
+    if (cls == 1 && sch.whole64) {   // one workgroup does every phase: no launch bounds to widen
+      B.whole.push_back(b);
+      continue;
+    }
     B.mats.push_back(b);
     B.smax = std::max(B.smax, std::max(s0, s1));
     if ((int)B.s_possible.size() <= std::max(s0, s1)) B.s_possible.resize(std::max(s0, s1) + 1, 0);
@@ -731,9 +822,9 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
   P.off_res = al256(P.off_items + sizeof(BatchItem) * (size_t)batch);
   const size_t tasks0 = al256(P.off_res + sizeof(BatchRes) * (size_t)batch);
   size_t o = tasks0;
-  size_t ntiles = 0;
   for (Branch& B : P.br) {
     std::stable_sort(B.mats.begin(), B.mats.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::stable_sort(B.whole.begin(), B.whole.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     for (int b : B.mats) {
       const int64_t nb = n[b];
       const int nt = (int)(((nb + kTileM - 1) / kTileM) * ((nb + kTileN - 1) / kTileN));   // tiles of the padded square
@@ -743,11 +834,15 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
     o = al256(o + sizeof(int) * B.mats.size());
     B.off_tiles = o;
     o = al256(o + sizeof(int) * B.tiles.size());
-    ntiles += B.tiles.size();
+    B.off_whole = o;
+    o = al256(o + sizeof(int) * B.whole.size());
   }
-  // the task arrays get a region sized for any schedule (every branch's two
-  // arrays 256-byte rounded), so one workspace size covers all schedules
-  P.off_pick = al256(tasks0 + sizeof(int) * ((size_t)batch + ntiles) + (size_t)(2 * 256 * kMaxBranch));
+  // the task arrays get a region sized for any schedule (every branch's three
+  // arrays 256-byte rounded; a matrix is in one list of one branch and its
+  // tiles are listed at most once), so one workspace size covers all schedules
+  size_t ntiles_all = 0;
+  for (int b = 0; b < batch; ++b) ntiles_all += (size_t)(((n[b] + kTileM - 1) / kTileM) * ((n[b] + kTileN - 1) / kTileN));
+  P.off_pick = al256(tasks0 + sizeof(int) * ((size_t)batch + ntiles_all) + (size_t)(3 * 256 * kMaxBranch));
   if (o > P.off_pick) return bfail(PS_ERR_UNSUPPORTED, "task arrays exceed their region");
   P.off_chosen = al256(P.off_pick + sizeof(int) * (size_t)batch);
   P.total = al256(P.off_chosen + sizeof(int) * (size_t)batch);
@@ -829,6 +924,8 @@ ps_status upload_and_args(const Plan2& P, char* ws, hipStream_t st, BatchArgs& b
       e = hipMemcpyAsync(ws + B.off_mats, B.mats.data(), sizeof(int) * B.mats.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !B.tiles.empty())
       e = hipMemcpyAsync(ws + B.off_tiles, B.tiles.data(), sizeof(int) * B.tiles.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !B.whole.empty())
+      e = hipMemcpyAsync(ws + B.off_whole, B.whole.data(), sizeof(int) * B.whole.size(), hipMemcpyHostToDevice, st);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);   // host vectors are released on return
   if (e != hipSuccess) return bfail(PS_ERR_HIP, "descriptor upload: %s", hipGetErrorString(e));
@@ -845,16 +942,23 @@ ps_status upload_and_args(const Plan2& P, char* ws, hipStream_t st, BatchArgs& b
 
 // the fixed launch sequence of one branch (stream-ordered)
 ps_status launch_branch(int W, BatchArgs ba, const Branch& B, hipStream_t st) {
-  if (B.mats.empty()) return PS_OK;
-  ba.tile_tasks = (const int*)(ba.ws + B.off_tiles);
-  ba.mat_tasks = (const int*)(ba.ws + B.off_mats);
   const dim3 blk(NT);
-  const unsigned nmat = (unsigned)B.mats.size(), ntile = (unsigned)B.tiles.size();
 #define PS_BLAUNCH(KER, GRID, ...)                                                          \
   do {                                                                                       \
     if (W == 0) hipLaunchKernelGGL(KER<double>, dim3(GRID), blk, 0, st, ba, ##__VA_ARGS__); \
     else hipLaunchKernelGGL(KER<float>, dim3(GRID), blk, 0, st, ba, ##__VA_ARGS__);         \
   } while (0)
+  if (!B.whole.empty()) {
+    ba.mat_tasks = (const int*)(ba.ws + B.off_whole);
+    PS_BLAUNCH(k_bwhole, (unsigned)B.whole.size());
+  }
+  if (B.mats.empty()) {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PS_OK : bfail(PS_ERR_HIP, "batch launch: %s", hipGetErrorString(e));
+  }
+  ba.tile_tasks = (const int*)(ba.ws + B.off_tiles);
+  ba.mat_tasks = (const int*)(ba.ws + B.off_mats);
+  const unsigned nmat = (unsigned)B.mats.size(), ntile = (unsigned)B.tiles.size();
   PS_BLAUNCH(k_bchoose, nmat);
   PS_BLAUNCH(k_bpad, ntile);
   // powers: for each j, the products of the matrices with j < s, then those
@@ -899,7 +1003,7 @@ ps_status side_streams(hipStream_t* out, int count) {
 
 int used_branches(const Plan2& P) {
   int used = 0;
-  for (const Branch& B : P.br) used += B.mats.empty() ? 0 : 1;
+  for (const Branch& B : P.br) used += B.empty() ? 0 : 1;
   return used;
 }
 
@@ -922,7 +1026,7 @@ ps_status launch_batch(int W, const BatchArgs& ba, const Plan2& P, hipStream_t s
   int k = 0;
   for (size_t i = 0; i < P.br.size() && e == hipSuccess && r == PS_OK; ++i) {
     const Branch& B = P.br[i];
-    if (B.mats.empty()) continue;
+    if (B.empty()) continue;
     if (k == 0) {
       r = launch_branch(W, ba, B, st);
     } else {
@@ -1056,7 +1160,8 @@ static ps_status capture_batch(int W, const BatchArgs& ba, const Plan2& P, ps_ba
 }
 
 // the contiguous groupings of the present classes (in increasing order) into
-// at most kMaxBranch branches
+// at most kMaxBranch branches; where class 1 has a branch of its own, also
+// with that class on k_bwhole
 static std::vector<Schedule> candidate_schedules(const int cls_count[kMaxClass + 1]) {
   std::vector<int> present;
   for (int c = 1; c <= kMaxClass; ++c)
@@ -1072,6 +1177,17 @@ static std::vector<Schedule> candidate_schedules(const int cls_count[kMaxClass +
       if (i < K - 1 && ((cut >> i) & 1)) ++g;
     }
     out.push_back(sch);
+  }
+  if (cls_count[1] > 0) {
+    const size_t ng = out.size();
+    for (size_t k = 0; k < ng; ++k) {
+      bool alone = true;
+      for (int c = 2; c <= kMaxClass; ++c) alone = alone && !(cls_count[c] > 0 && out[k].group[c - 1] == out[k].group[0]);
+      if (!alone) continue;
+      Schedule w = out[k];
+      w.whole64 = 1;
+      out.push_back(w);
+    }
   }
   return out;
 }
@@ -1139,7 +1255,7 @@ ps_status ps_batched_tune(ps_dtype dtype, int batch, const int32_t* n, const voi
     }
     std::sort(t.begin(), t.end());
     const float med = t[t.size() / 2];
-    if (ms_out && k < 8) ms_out[k] = med;
+    if (ms_out && k < kMaxCand) ms_out[k] = med;
     if (best < 0 || med < best_ms) {
       best = (int)k;
       best_ms = med;
@@ -1152,8 +1268,10 @@ ps_status ps_batched_tune(ps_dtype dtype, int batch, const int32_t* n, const voi
     std::lock_guard<std::mutex> lock(g_cache_mu);
     g_cache[schedule_key(dtype, m, cc)] = cand[best];
   }
-  if (groups_out)
+  if (groups_out) {
     for (int c = 0; c < kMaxClass; ++c) groups_out[c] = cand[best].group[c];
+    groups_out[kMaxClass] = cand[best].whole64;
+  }
   if (ncand_out) *ncand_out = (int)cand.size();
   return PS_OK;
 }
@@ -1168,6 +1286,7 @@ ps_status ps_autotune_lookup(ps_dtype dtype, int batch, const int32_t* n, int m,
   *found = it != g_cache.end();
   const Schedule sch = *found ? it->second : Schedule();
   for (int c = 0; c < kMaxClass; ++c) groups_out[c] = sch.group[c];
+  groups_out[kMaxClass] = sch.whole64;
   return PS_OK;
 }
 
@@ -1185,8 +1304,9 @@ ps_status ps_autotune_save(const char* path) {
   fprintf(f, "{\"ps_autotune\": 1, \"entries\": [");
   bool first = true;
   for (const auto& kv : g_cache) {
-    fprintf(f, "%s\n  {\"key\": \"%s\", \"groups\": [%d, %d, %d, %d]}", first ? "" : ",", kv.first.c_str(),
-            kv.second.group[0], kv.second.group[1], kv.second.group[2], kv.second.group[3]);
+    fprintf(f, "%s\n  {\"key\": \"%s\", \"groups\": [%d, %d, %d, %d], \"whole64\": %d}", first ? "" : ",",
+            kv.first.c_str(), kv.second.group[0], kv.second.group[1], kv.second.group[2], kv.second.group[3],
+            kv.second.whole64);
     first = false;
   }
   fprintf(f, "\n]}\n");
@@ -1217,6 +1337,14 @@ ps_status ps_autotune_load(const char* path) {
       return ps_set_error(PS_ERR_ARG, "malformed groups in the cache file");
     for (int c = 0; c < kMaxClass; ++c)
       if (sch.group[c] < 0 || sch.group[c] >= kMaxBranch) return ps_set_error(PS_ERR_ARG, "group out of range");
+    // optional (files without it: per-phase launches); it belongs to this
+    // entry if it comes before the next entry's key
+    const size_t wp = text.find("\"whole64\": ", gp);
+    const size_t next = text.find("\"key\": \"", gp);
+    if (wp != std::string::npos && (next == std::string::npos || wp < next)) {
+      if (sscanf(text.c_str() + wp + 11, "%d", &sch.whole64) != 1 || sch.whole64 < 0 || sch.whole64 > 1)
+        return ps_set_error(PS_ERR_ARG, "malformed whole64 in the cache file");
+    }
     add[text.substr(pos, end - pos)] = sch;
     pos = gp;
   }

@@ -304,3 +304,37 @@ def test_autotune_cache_roundtrip(ps, tmp_path):
     with pytest.raises(ps.PSError):
         ps.autotune_load(tmp_path / "missing.json")
     ps.autotune_clear()
+
+
+def test_autotune_cache_whole64(ps, tmp_path):
+    """The class-1 kernel choice in the cache file: read per entry (an entry
+    without it reads as per-phase launches, even when the next entry has it),
+    kept by a save/load round trip, and out-of-range values refused."""
+    import torch
+    ps.autotune_clear()
+    arch = "unknown"
+    if torch.cuda.is_available():
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    a = [torch.zeros(n, n) for n in (8, 40, 250)]          # classes 1 and 4
+    b = [torch.zeros(n, n) for n in (8, 100)]              # classes 1 and 2
+    ka = "%s|f32|m18|2,0,0,1" % arch
+    kb = "%s|f32|m18|1,1,0,0" % arch
+    p = tmp_path / "cache.json"
+    p.write_text('{"ps_autotune": 1, "entries": [{"key": "%s", "groups": [0, 0, 0, 1]},\n'
+                 ' {"key": "%s", "groups": [0, 1, 0, 0], "whole64": 1}]}' % (ka, kb))
+    ps.autotune_load(p)
+    assert ps.autotune_lookup(a, 18, whole64=True) == (True, [0, 0, 0, 1], 0)
+    assert ps.autotune_lookup(b, 18, whole64=True) == (True, [0, 1, 0, 0], 1)
+    assert ps.autotune_lookup(b, 18) == (True, [0, 1, 0, 0])
+    q = tmp_path / "saved.json"
+    ps.autotune_save(q)
+    assert '"whole64": 1' in q.read_text() and '"whole64": 0' in q.read_text()
+    ps.autotune_clear()
+    ps.autotune_load(q)
+    assert ps.autotune_lookup(b, 18, whole64=True) == (True, [0, 1, 0, 0], 1)
+    assert ps.autotune_lookup(a, 18, whole64=True) == (True, [0, 0, 0, 1], 0)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"ps_autotune": 1, "entries": [{"key": "x", "groups": [0, 1, 0, 0], "whole64": 2}]}')
+    with pytest.raises(ps.PSError):
+        ps.autotune_load(bad)
+    ps.autotune_clear()
