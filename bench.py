@@ -491,8 +491,9 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
     """Secondary workloads of the hot path (each a few seconds):
     latency   one 64x64 FP64 matrix, ||A||_1 = 1, Taylor m = 16, s = 4, no
               scaling: microseconds per evaluation, as a stream of ps_expm
-              calls and as one replayed hipGraph (the batched path with one
-              matrix);
+              calls, as one ps_expm call captured into a hipGraph and
+              replayed, and as one replayed hipGraph of the batched path with
+              one matrix;
     sizes     one N(0,1) matrix with ||A||_1 = 1 (m = 30, s = 6, no scaling) at
               n = 512, 2048, 4096: mixed vs plain ms per evaluation and the FP64
               GEMM tile kernel's TFLOP/s (library profile mode, hipEvents);
@@ -529,7 +530,29 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
             g = ps.BatchedGraph([A1], 16, s=[4], sigma=[0], mode=mode)
             tg = _time(g.launch, 200, torch)
             g.close()
-            out[mode] = {"us_per_eval_calls": round(tc * 1e6, 2), "us_per_eval_graph": round(tg * 1e6, 2)}
+            # one ps_expm call captured into a hipGraph and replayed, checked
+            # bitwise against the eager call
+            ps.ps_expm(A1, 16, s=4, mode=mode, out=E1, workspace=ws1)
+            torch.cuda.synchronize()
+            ref1 = E1.clone()
+            side = torch.cuda.Stream(device=dev)
+            side.wait_stream(torch.cuda.current_stream(dev))
+            with torch.cuda.stream(side):
+                ps.ps_expm(A1, 16, s=4, mode=mode, out=E1, workspace=ws1)
+            torch.cuda.current_stream(dev).wait_stream(side)
+            torch.cuda.synchronize()
+            g1 = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g1):
+                ps.ps_expm(A1, 16, s=4, mode=mode, out=E1, workspace=ws1)
+            E1.zero_()
+            g1.replay()
+            torch.cuda.synchronize()
+            if not torch.equal(E1, ref1):
+                raise RuntimeError("graph replay of the 64 x 64 case differs from the eager call")
+            t1 = _time(g1.replay, 200, torch)
+            del g1
+            out[mode] = {"us_per_eval_calls": round(tc * 1e6, 2), "us_per_eval_graph": round(tg * 1e6, 2),
+                         "us_per_eval_call_graph": round(t1 * 1e6, 2)}
         res["latency_single_64"] = out
         del A1, E1, ws1
     # ---- other orders
@@ -575,7 +598,8 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
                          "tflops_credited": round(flops / tt / 1e12, 2),
                          "frac_fp32_mfma_credited": round(flops / tt / 157.3e12, 4),
                          "one_branch_ms": round(t * 1e3, 3),
-                         "tuned_schedule": {"branch_of_class": tune["groups"], "candidate_ms": tune["ms"]}}
+                         "tuned_schedule": {"branch_of_class": tune["groups"], "whole64": tune["whole64"],
+                                            "candidate_ms": tune["ms"]}}
         out["speedup_mixed_vs_fixed"] = round(out["fixed"]["ms"] / out["mixed"]["ms"], 3)
         # per size class (padded order 64 k): the class alone as a batch, mixed
         classes = {}
@@ -591,6 +615,10 @@ def extra_workloads(ps, inputs, torch, which=EXTRAS):
             per["n<=%d" % npad] = {"matrices": len(idx), "ms": round(tc * 1e3, 3),
                                    "tflops_credited": round(fc / tc / 1e12, 2),
                                    "frac_fp32_mfma_credited": round(fc / tc / 157.3e12, 4)}
+            if npad == 64:   # the per-phase launches against one workgroup per matrix (tuner candidates 0, 1)
+                t64 = ps.batched_tune([A[i] for i in idx], 18, sigma=[sig[i] for i in idx], mode="mixed", reps=5)
+                per["n<=64"]["phases_vs_one_workgroup_ms"] = t64["ms"][:2]
+                ps.autotune_clear()
         out["per_class_mixed"] = per
         sub = list(range(0, len(A), 8))          # per-matrix loop on every 8th matrix, scaled
         wsl = [ps.expm_workspace(A[i], 18, 0, sig[i]) for i in sub]
