@@ -32,7 +32,10 @@
 // process-wide cache keyed by device architecture, dtype, degree and the
 // batch's classes; ps_expm_batched and ps_batched_prepare use a cached
 // schedule when one matches (otherwise one branch), and ps_autotune_save /
-// ps_autotune_load keep the cache in a JSON file.
+// ps_autotune_load keep the cache in a JSON file.  A schedule can also hand
+// the class of orders up to 64 (one tile per matrix) to k_bwhole, which runs
+// every phase of a matrix in one workgroup: one launch for the class, the
+// same tile routines in the same order, the same bits.
 //
 // The block size is chosen per matrix among floor(sqrt m) and ceil(sqrt m)
 // (the two equally cheap choices of the paper's section 1) by the modelled
