@@ -29,8 +29,10 @@
 //                    that update, C -= L21 U12 with K <= 32, to the 64 x 64
 //                    tiles of the other columns (FMA in the working type,
 //                    C's loads issued first).
-//   k_lu_update_mfma the back substitution's update (K <= 64) on the FP64 /
-//                    FP32 matrix cores, 64 x 64 tiles.
+//   k_lu_backstep    one step of the back substitution: the update of the
+//                    rows above a solved block row (K <= 64) on the FP64 /
+//                    FP32 matrix cores in 64 x 64 tiles, and in the same
+//                    launch the block row just above it updated and solved.
 //   k_lu_trsm_upper  back substitution with a <= 64-row diagonal block of U,
 //                    one wave per right-hand side, multiplying by the
 //                    reciprocals of U's diagonal (formed once per block).
@@ -490,14 +492,14 @@ template <> struct LuMma<float> {
   static __device__ inline int row(int v, int g) { return 4 * g + v; }
 };
 
+// One 64 x 64 tile (rows r0.., columns c0..) of M -= A(:, ac0 .. ac0 + K)
+// M(kb0 .. kb0 + K, :), rows below cr1 only.  As, Bs: 64 x 65 elements of
+// LDS each: As[k][i] = A(r0 + i, ac0 + k), Bs[k][c] = M(kb0 + k, c0 + c).
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_update_mfma(const T* __restrict__ A, int64_t lda, int ac0, int K, int kb0,
-                                                        int cr1, T* __restrict__ M, int64_t ldm, int64_t ncols) {
-  __shared__ T As[64][65];   // As[k][i] = A(r0 + i, ac0 + k)
-  __shared__ T Bs[64][65];   // Bs[k][c] = M(kb0 + k, c0 + c)
+__device__ __forceinline__ void update_tile_mfma(const T* __restrict__ A, int64_t lda, int ac0, int K, int kb0,
+                                                 int cr1, T* __restrict__ M, int64_t ldm, int64_t ncols, int r0,
+                                                 int64_t c0, T (*As)[65], T (*Bs)[65]) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
-  const int r0 = blockIdx.x * 64;
-  const int64_t c0 = (int64_t)blockIdx.y * 64;
   const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
   const int K4 = (K + 3) & ~3;
   // this lane's 16 elements of C
@@ -591,6 +593,100 @@ __global__ __launch_bounds__(256) void k_lu_trsm_upper(const T* __restrict__ Q, 
     if (lane < j) x -= Us[j][lane] * xj;
   }
   if (lane < b) c[k0 + lane] = x;
+}
+
+// One step of the back substitution in one launch.  X_k, rows k0 .. k0 + b - 1
+// of P, is solved; the rows above take its update and the block above it,
+// rows d0 = k0 - 64 .. k0 - 1, is solved too.  The first ndiag workgroups
+// each take 16 right-hand sides of that block: its update by X_k, as the
+// update tiles form it (the same MFMA chain over k for every element), then
+// the substitution with its diagonal block of U, as k_lu_trsm_upper does it
+// (one wave per four right-hand sides).  The other workgroups are the 64 x 64
+// update tiles of the rows above d0.  The two parts write disjoint rows and
+// read only X_k besides their own rows, so no workgroup waits for another,
+// and the results are those of the update and substitution launches.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_backstep(const T* __restrict__ Q, int64_t ldq, T* __restrict__ P,
+                                                     int64_t ldp, int k0, int b, int nrhs, int ndiag) {
+  __shared__ T S[2][64][65];
+  const int d0 = k0 - 64;
+  if ((int)blockIdx.x >= ndiag) {
+    const int idx = blockIdx.x - ndiag, nrt = d0 / 64;
+    update_tile_mfma<T>(Q, ldq, k0, b, k0, d0, P, ldp, (int64_t)nrhs, (idx % nrt) * 64, (int64_t)(idx / nrt) * 64,
+                        S[0], S[1]);
+    return;
+  }
+  T (*Us)[65] = S[0];                      // Us[k][i] = Q(d0 + i, k0 + k), then Us[j][i] = Q(d0 + i, d0 + j)
+  T (*Xs)[17] = (T (*)[17])&S[1][0][0];    // Xs[k][c] = P(k0 + k, c0 + c)
+  T (*Cs)[17] = Xs + 64;                   // the block's rows after the update, Cs[i][c]
+  T* rd = &Cs[64][0];                      // 1 / Q(d0 + j, d0 + j)
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c = lane & 15;
+  const int64_t c0 = (int64_t)blockIdx.x * 16;
+  const int K4 = (b + 3) & ~3;
+  // every load of a thread issued before the first LDS store
+  T ru[16], rg[16], rx[4], cv[4];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q;
+    const int k = idx >> 6, i = idx & 63;
+    ru[q] = k < b ? Q[(d0 + i) + (int64_t)(k0 + k) * ldq] : T(0);
+    rg[q] = Q[(d0 + i) + (int64_t)(d0 + k) * ldq];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = t + 256 * q;
+    const int k = idx >> 4, cc = idx & 15;
+    rx[q] = (k < b && c0 + cc < nrhs) ? P[(k0 + k) + (c0 + cc) * ldp] : T(0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = d0 + 16 * w + LuMma<T>::row(v, g);
+    cv[v] = c0 + c < nrhs ? P[row + (c0 + c) * ldp] : T(0);
+  }
+  const T rdd = t < 64 ? T(1) / Q[(d0 + t) + (int64_t)(d0 + t) * ldq] : T(0);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q;
+    Us[idx >> 6][idx & 63] = ru[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = t + 256 * q;
+    Xs[idx >> 4][idx & 15] = rx[q];
+  }
+  __syncthreads();
+  // wave w: rows 16 w .. 16 w + 15 of the block
+  typename LuMma<T>::V acc = typename LuMma<T>::V{0, 0, 0, 0};
+  for (int k = 0; k < K4; k += 4) acc = LuMma<T>::mma(Us[k + g][16 * w + c], Xs[k + g][c], acc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Cs[16 * w + LuMma<T>::row(v, g)][c] = cv[v] - acc[v];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int idx = t + 256 * q;
+    Us[idx >> 6][idx & 63] = rg[q];
+  }
+  if (t < 64) rd[t] = rdd;
+  __syncthreads();
+  // wave w: right-hand sides 4 w .. 4 w + 3, lane = row
+  T x[4];
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) x[cc] = Cs[lane][4 * w + cc];
+  for (int j = 63; j >= 0; --j) {
+    T xj[4];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) xj[cc] = lane_value(x[cc], j) * rd[j];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc)
+      if (lane == j) x[cc] = xj[cc];
+    if (lane < j) {
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) x[cc] -= Us[j][lane] * xj[cc];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc)
+    if (c0 + 4 * w + cc < nrhs) P[(d0 + lane) + (c0 + 4 * w + cc) * ldp] = x[cc];
 }
 
 // Launches the panel factorisation at k0 for `rem` rows left, alone
@@ -696,13 +792,16 @@ hipError_t lu_solve_t(int n, T* Q, int64_t ldq, int nrhs, T* P, int64_t ldp, int
     k0 = r1;
   }
   if (nrhs > 0) {
-    for (int kb = (n - 1) / 64; kb >= 0; --kb) {
+    // the last block row alone, then per block row its update of the rows
+    // above fused with the substitution of the block row above it
+    const int kl = (n - 1) / 64;
+    hipLaunchKernelGGL(k_lu_trsm_upper<T>, dim3((nrhs + 3) / 4), dim3(256), 0, st, (const T*)Q, ldq, P, ldp, kl * 64,
+                       n - kl * 64, nrhs);
+    const int ndiag = (nrhs + 15) / 16, nct = (nrhs + 63) / 64;
+    for (int kb = kl; kb >= 1; --kb) {
       const int k0 = kb * 64, b = (n - k0) < 64 ? (n - k0) : 64;
-      hipLaunchKernelGGL(k_lu_trsm_upper<T>, dim3((nrhs + 3) / 4), dim3(256), 0, st, (const T*)Q, ldq, P, ldp, k0, b,
-                         nrhs);
-      if (k0 > 0)
-        hipLaunchKernelGGL(k_lu_update_mfma<T>, dim3((k0 + 63) / 64, (nrhs + 63) / 64), dim3(256), 0, st, (const T*)Q,
-                           ldq, k0, b, k0, k0, P, ldp, (int64_t)nrhs);
+      hipLaunchKernelGGL(k_lu_backstep<T>, dim3((unsigned)(ndiag + (kb - 1) * nct)), dim3(256), 0, st, (const T*)Q,
+                         ldq, P, ldp, k0, b, nrhs, ndiag);
     }
   }
   return hipGetLastError();
