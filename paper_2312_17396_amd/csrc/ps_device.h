@@ -457,11 +457,15 @@ __device__ __forceinline__ void mainloop_lowp(const uint8_t* __restrict__ A, con
 // issued first, so the workgroup waits for memory once; the slabs then pass
 // through the two LDS stages (one barrier per slab: the barrier of slab k+1
 // follows every wave's reads of slab k, so slab k+2 may overwrite its stage).
+// after_issue() runs once the slab loads are issued: loads it issues retire
+// after the slabs' (the memory counter counts in issue order), so the first
+// slab does not wait for them.
 constexpr int LP_ALL = 8;
+template <typename F>
 __device__ __forceinline__ void mainloop_fp8_all(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
                                                  const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs,
                                                  int64_t Kp, int64_t n, int64_t m0, int64_t n0, char* smem,
-                                                 f4v acc[2]) {
+                                                 f4v acc[2], F&& after_issue) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
   const int64_t Ks = Kp / 32;
@@ -472,6 +476,7 @@ __device__ __forceinline__ void mainloop_fp8_all(const uint8_t* __restrict__ A, 
 #pragma unroll
   for (int i = 0; i < LP_ALL; ++i)
     if (i < ns) lp_load_raw<true>(A, As, B, Bs, Kp, Ks, m0, n0, i, t, r[i]);
+  after_issue();
 #pragma unroll
   for (int i = 0; i < LP_ALL; ++i) {
     if (i < ns) {
@@ -643,18 +648,23 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
   const int t = threadIdx.x;
   const int row = t & 63;
   const int64_t gr = m0 + row;
-  // this thread's elements of B_{i-1}: the loads are issued first, before the
-  // tiers are known and before the main loop's loads, so their round trip
-  // overlaps everything up to the epilogue (the block is in the working
-  // precision whatever the tier)
+  // this thread's elements of B_{i-1} (the block is in the working precision
+  // whatever the tier): their loads are issued before the main loop's, so
+  // their round trip overlaps everything up to the epilogue, except for an
+  // FP8 product of order <= 1024, which issues them right after its slab
+  // loads, so that its first slab does not wait for them
   W bq[TILE_Q];
+  auto load_bq = [&]() {
 #pragma unroll
-  for (int q = 0; q < TILE_Q; ++q) {
-    const int64_t gc = n0 + (t >> 6) + NW * q;
-    const bool in = gr < h.nvb && gc < h.nvb;
-    const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
-    bq[q] = in ? x : W(0);
-  }
+    for (int q = 0; q < TILE_Q; ++q) {
+      const int64_t gc = n0 + (t >> 6) + NW * q;
+      const bool in = gr < h.nvb && gc < h.nvb;
+      const W x = h.bsrc[(in ? gr : 0) + (in ? gc : 0) * n];
+      bq[q] = in ? x : W(0);
+    }
+  };
+  const bool fp8all = FP8ALL && t_in == 3 && n <= LP_ALL * 128;
+  if (!fp8all) load_bq();
   if (t_in == WT) {
     typename MF<W>::V acc[2];
     mainloop_lds<W, false, false>((const W*)h.pin, n, h.ysrc, h.ldy, n, m0, n0, smem, acc);
@@ -670,7 +680,7 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
   } else if (t_in == 3) {
     f4v acc[2];
     const uint8_t* p8 = (const uint8_t*)h.pin;
-    if (FP8ALL && n <= LP_ALL * 128) mainloop_fp8_all(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
+    if (fp8all) mainloop_fp8_all(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc, load_bq);
     else mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else {   // cast only

@@ -118,9 +118,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_
     // Y was formed in FP32; a Horner product in the working precision (the
     // folded step r included) needs it in the working precision as well, and
     // so does an FP32 product whose u_i is below kY32Margin u32 (eq. (cond-Y):
-    // Y must be accurate to u_i, and the FP32 product's error is ~5 u32)
-    for (int i = 1; i <= L.r; ++i)
-      y64 = y64 || plan->tier[i] == WT || (plan->tier[i] == 1 && plan->u[i] < kY32Margin * 0x1p-24);
+    // Y must be accurate to u_i, and the FP32 product's error is ~5 u32).
+    // Lane i - 1 of every wave tests step i (r < PS_MAX_BLOCKS): one round
+    // trip to the plan instead of one per step.
+    const int i = 1 + (int)(threadIdx.x & 63);
+    bool need = false;
+    if (i <= L.r) {
+      const int ti = plan->tier[i];
+      const double ui = plan->u[i];
+      need = ti == WT || (ti == 1 && ui < kY32Margin * 0x1p-24);
+    }
+    y64 = __any(need);
     if (y64)
       gemm_tile<W, false, false>((const W*)a.ya.p + b * a.ya.stride, a.ya.ld, (const W*)a.yb.p + b * a.yb.stride,
                                  a.yb.ld, (W*)a.yc.p + b * a.yc.stride, a.yc.ld, a.n, a.n, (int64_t)tm * kTileM,
