@@ -6,8 +6,11 @@
 // tiers), the Horner chain in the planned tiers and the squarings
 // (eq. (scal-idea)).  Each phase step is one launch over the whole batch: a
 // task table built on the host at set-up lists (matrix, output tile) pairs,
-// largest matrices first, and workgroup g takes task g.  Matrices that have
-// no work in a step (a smaller block size, fewer squarings) leave at once.
+// largest matrices first, and workgroup g takes task g.  The workgroups of a
+// launch go to the eight XCDs in turn, so the table keeps all tiles of a
+// matrix on one XCD (every eighth entry) and its operand panels in one L2.
+// Matrices that have no work in a step (a smaller block size, fewer
+// squarings) leave at once.
 // Every matrix is first copied into a zero-padded square of order
 // np = ceil(n / 64) 64 inside its workspace region, and all later phases work
 // on order np: every tile and K slab is then whole, so the GEMM and Horner
@@ -87,7 +90,7 @@ struct BatchRes {
 struct BatchArgs {
   const BatchItem* items;
   BatchRes* res;
-  const int* tile_tasks;  // (matrix << 8) | tile, largest matrices first (this branch's)
+  const int* tile_tasks;  // (matrix << 8) | tile in XCD lanes, largest matrices first, -1: none (this branch's)
   const int* mat_tasks;   // matrices of this branch (per-matrix kernels)
   int* pick;              // per matrix: 0 -> L[0], 1 -> L[1]
   int* chosen;            // per matrix: chosen block size (for reports)
@@ -226,6 +229,7 @@ __device__ __forceinline__ void bpad_tile(const BatchArgs& a, int b, int tile) {
 template <typename W>
 __global__ __launch_bounds__(NT) void k_bpad(BatchArgs a) {
   const int task = a.tile_tasks[blockIdx.x];
+  if (task < 0) return;   // a hole of the XCD-lane layout
   bpad_tile<W>(a, task >> 8, task & 255);
 }
 
@@ -496,6 +500,7 @@ template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower(BatchArgs a, int j) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
+  if (task < 0) return;   // a hole of the XCD-lane layout
   bpower_tile<W, false>(a, a.res[task >> 8], task & 255, j, smem);
 }
 
@@ -503,6 +508,7 @@ template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bpower_asm(BatchArgs a, int j) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
+  if (task < 0) return;   // a hole of the XCD-lane layout
   bpower_tile<W, true>(a, a.res[task >> 8], task & 255, j, smem);
 }
 
@@ -518,6 +524,7 @@ __device__ __forceinline__ void bassemble1_tile(const BatchArgs& a, const BatchR
 template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bassemble1(BatchArgs a) {
   const int task = a.tile_tasks[blockIdx.x];
+  if (task < 0) return;   // a hole of the XCD-lane layout
   const BatchRes& it = a.res[task >> 8];
   if (it.L.s != 1) return;   // uniform
   bassemble1_tile<W>(a, it, task & 255);
@@ -609,6 +616,7 @@ template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bhorner(BatchArgs a, int k) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
+  if (task < 0) return;   // a hole of the XCD-lane layout
   const BatchRes& it = a.res[task >> 8];
   const int i0 = it.L.first_step;
   if (k >= i0) return;   // uniform
@@ -637,6 +645,7 @@ template <typename W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bsquare(BatchArgs a, int q) {
   __shared__ __attribute__((aligned(16))) char smem[smem_bytes<W>()];
   const int task = a.tile_tasks[blockIdx.x];
+  if (task < 0) return;   // a hole of the XCD-lane layout
   const BatchRes& it = a.res[task >> 8];
   if (q > it.sigma) return;   // uniform
   bsquare_tile<W>(it, task & 255, q, smem);
@@ -717,6 +726,7 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int kMaxClass = 4;     // padded orders 64, 128, 192, 256
 constexpr int kMaxBranch = 4;
 constexpr int kMaxCand = 16;     // schedules the tuner can time: 8 groupings, 4 with k_bwhole
+constexpr int kXcd = 8;          // XCDs, to which a launch's workgroups go in turn
 
 // one branch of a batch: its matrices, their tiles and the bounds of its
 // launch loops
@@ -828,11 +838,24 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
   for (Branch& B : P.br) {
     std::stable_sort(B.mats.begin(), B.mats.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     std::stable_sort(B.whole.begin(), B.whole.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    // XCD lanes: workgroup g runs on XCD g mod kXcd, so the tiles of one
+    // matrix go to one lane (task positions l, l + kXcd, l + 2 kXcd, ...)
+    // and share that XCD's L2 for their operand panels; each matrix joins
+    // the lane with the fewest tiles so far, and the shorter lanes end in
+    // holes (task -1)
+    std::vector<std::vector<int>> lane(kXcd);
+    std::vector<size_t> load(kXcd, 0);
     for (int b : B.mats) {
       const int64_t nb = n[b];
       const int nt = (int)(((nb + kTileM - 1) / kTileM) * ((nb + kTileN - 1) / kTileN));   // tiles of the padded square
-      for (int t = 0; t < nt; ++t) B.tiles.push_back((b << 8) | t);
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      for (int t = 0; t < nt; ++t) lane[l].push_back((b << 8) | t);
+      load[l] += (size_t)nt;
     }
+    const size_t len = *std::max_element(load.begin(), load.end());
+    B.tiles.assign(len * kXcd, -1);
+    for (int l = 0; l < kXcd; ++l)
+      for (size_t k = 0; k < lane[l].size(); ++k) B.tiles[k * kXcd + l] = lane[l][k];
     B.off_mats = o;
     o = al256(o + sizeof(int) * B.mats.size());
     B.off_tiles = o;
@@ -842,10 +865,13 @@ ps_status build_plan(ps_dtype dt, int batch, const int32_t* n, int m, const int3
   }
   // the task arrays get a region sized for any schedule (every branch's three
   // arrays 256-byte rounded; a matrix is in one list of one branch and its
-  // tiles are listed at most once), so one workspace size covers all schedules
+  // tiles are listed at most once; a branch's lanes differ in length by at
+  // most one matrix's 16 tiles, so its holes number fewer than 16 kXcd), so
+  // one workspace size covers all schedules
   size_t ntiles_all = 0;
   for (int b = 0; b < batch; ++b) ntiles_all += (size_t)(((n[b] + kTileM - 1) / kTileM) * ((n[b] + kTileN - 1) / kTileN));
-  P.off_pick = al256(tasks0 + sizeof(int) * ((size_t)batch + ntiles_all) + (size_t)(3 * 256 * kMaxBranch));
+  P.off_pick = al256(tasks0 + sizeof(int) * ((size_t)batch + ntiles_all + (size_t)(16 * kXcd * kMaxBranch)) +
+                     (size_t)(3 * 256 * kMaxBranch));
   if (o > P.off_pick) return bfail(PS_ERR_UNSUPPORTED, "task arrays exceed their region");
   P.off_chosen = al256(P.off_pick + sizeof(int) * (size_t)batch);
   P.total = al256(P.off_chosen + sizeof(int) * (size_t)batch);
