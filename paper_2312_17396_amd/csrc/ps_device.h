@@ -423,10 +423,12 @@ __device__ __forceinline__ void lp_mma(const char* st, int wr, int wc, int g, in
 // slab block b of row (column) l%16 is the one passed by lane l%16 + 16b.
 // Reading each lane's halves from those two offsets makes every hardware
 // scale block coincide with one 32-element block of the packed layout.
-template <bool FP8>
+// after_issue() runs once the loads of the first two slabs are issued (as in
+// mainloop_fp8_all: loads it issues retire after theirs).
+template <bool FP8, typename F>
 __device__ __forceinline__ void mainloop_lowp(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
                                      const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t Kp,
-                                     int64_t n, int64_t m0, int64_t n0, char* smem, f4v acc[2]) {
+                                     int64_t n, int64_t m0, int64_t n0, char* smem, f4v acc[2], F&& after_issue) {
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wr = wave_row0(), wc = wave_col0();
   const int64_t rsb = FP8 ? Kp : 2 * Kp;             // row stride in bytes
@@ -438,6 +440,7 @@ __device__ __forceinline__ void mainloop_lowp(const uint8_t* __restrict__ A, con
   LpRegs r0, r1;
   lp_load<FP8>(A, As, B, Bs, rsb, Ks, n, m0, n0, 0, t, r0);
   lp_load<FP8>(A, As, B, Bs, rsb, Ks, n, m0, n0, min<int64_t>(1, ns - 1), t, r1);
+  after_issue();
   lp_store<FP8>(smem, t, r0);
   __syncthreads();
   auto step = [&](int64_t kt, LpRegs& rn, const LpRegs& rf) {
@@ -451,6 +454,12 @@ __device__ __forceinline__ void mainloop_lowp(const uint8_t* __restrict__ A, con
     step(kt, r0, r1);
     step(kt + 1, r1, r0);
   }
+}
+template <bool FP8>
+__device__ __forceinline__ void mainloop_lowp(const uint8_t* __restrict__ A, const uint8_t* __restrict__ As,
+                                     const uint8_t* __restrict__ B, const uint8_t* __restrict__ Bs, int64_t Kp,
+                                     int64_t n, int64_t m0, int64_t n0, char* smem, f4v acc[2]) {
+  mainloop_lowp<FP8>(A, As, B, Bs, Kp, n, m0, n0, smem, acc, [] {});
 }
 
 // FP8 with at most LP_ALL slabs (n <= 1024): the loads of every slab are
@@ -649,10 +658,11 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
   const int row = t & 63;
   const int64_t gr = m0 + row;
   // this thread's elements of B_{i-1} (the block is in the working precision
-  // whatever the tier): their loads are issued before the main loop's, so
-  // their round trip overlaps everything up to the epilogue, except for an
-  // FP8 product of order <= 1024, which issues them right after its slab
-  // loads, so that its first slab does not wait for them
+  // whatever the tier): their round trip overlaps everything up to the
+  // epilogue.  FP64 and FP32 products issue them before the main loop; the
+  // BF16 and FP8 loops issue them right after their first slab loads, so
+  // that the first slab does not wait for them (the memory counter retires
+  // loads in issue order)
   W bq[TILE_Q];
   auto load_bq = [&]() {
 #pragma unroll
@@ -664,7 +674,7 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
     }
   };
   const bool fp8all = FP8ALL && t_in == 3 && n <= LP_ALL * 128;
-  if (!fp8all) load_bq();
+  if (t_in != 2 && t_in != 3) load_bq();
   if (t_in == WT) {
     typename MF<W>::V acc[2];
     mainloop_lds<W, false, false>((const W*)h.pin, n, h.ysrc, h.ldy, n, m0, n0, smem, acc);
@@ -675,13 +685,14 @@ __device__ __forceinline__ void horner_tile(const HornerTile<W>& h, int64_t m0, 
     frag_to_cs<float, W>(acc, Cs, 1.0);
   } else if (t_in == 2) {
     f4v acc[2];
-    mainloop_lowp<false>((const uint8_t*)h.pin, nullptr, (const uint8_t*)h.ybf16, nullptr, Kp, n, m0, n0, smem, acc);
+    mainloop_lowp<false>((const uint8_t*)h.pin, nullptr, (const uint8_t*)h.ybf16, nullptr, Kp, n, m0, n0, smem, acc,
+                         load_bq);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else if (t_in == 3) {
     f4v acc[2];
     const uint8_t* p8 = (const uint8_t*)h.pin;
     if (fp8all) mainloop_fp8_all(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc, load_bq);
-    else mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc);
+    else mainloop_lowp<true>(p8, p8 + h.Mp * Kp, h.yfp8, h.yfp8s, Kp, n, m0, n0, smem, acc, load_bq);
     frag_f32_to_cs_any(acc, (double*)smem, (float*)smem, WT == 0);
   } else {   // cast only
     if (h.fyc != 0.0) {
